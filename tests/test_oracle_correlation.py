@@ -1,0 +1,153 @@
+"""Pins for the oracle's correlation grid (Sec. 3, Fig. 2: mixing, correlation
+over all code shifts, detection) and its block processing (Sec. 4).
+
+Pins: a textbook numpy circular cross-correlation (brute force with np.roll
+and through the FFT) in the Doppler-0 complex case where the wipe factor is
+exactly 4096; the closed form of the noiseless code-vs-code correlation at
+integer samples per chip; the planted code phase; a tone at a bin's exact
+quantised frequency; agreement of the two oracle routes; recovery of planted
+satellites at the configured C/N0.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+
+def _cplx_record(re, im):
+    x = np.empty(2 * re.size, np.int8)
+    x[0::2] = re
+    x[1::2] = im
+    return x
+
+
+def test_doppler0_matches_numpy_circular_correlation():
+    rng = np.random.default_rng(1)
+    fs, N, Tc, Nnc = 2046000, 2046, 2, 3
+    re = rng.integers(-127, 128, Tc * Nnc * N).astype(np.int8)
+    im = rng.integers(-127, 128, Tc * Nnc * N).astype(np.int8)
+    x = _cplx_record(re, im)
+    prns = [5, 17]
+    P = O.grid_direct(x, O.CPLX_I8, fs, 0.0, prns, 0.0, 100.0, 1, Tc, Nnc)
+    xc = re.astype(np.float64) + 1j * im.astype(np.float64)
+    for pi, prn in enumerate(prns):
+        c = O.code_replica(prn, fs, N).astype(np.float64)
+        expect = np.zeros(N)
+        for b in range(Nnc):
+            blk = xc[b * Tc * N:(b + 1) * Tc * N]
+            # brute force: R[tau] = sum_n x[n] c[(n - tau) mod N] ; np.roll(c, tau)[n] = c[n - tau]
+            R = np.array([np.dot(blk, np.tile(np.roll(c, tau), Tc)) for tau in range(N)])
+            # and the textbook FFT form of the same circular correlation
+            fold = blk.reshape(Tc, N).sum(axis=0)
+            R2 = np.fft.ifft(np.fft.fft(fold) * np.conj(np.fft.fft(c)))
+            assert np.allclose(R, R2, rtol=0, atol=1e-6 * np.abs(R).max())
+            expect += np.abs(R) ** 2
+        # the wipe factor is exactly 4096 at 0 Hz, so P = sum_b |R_b|^2 up to
+        # the FP64 rounding of the squares (|4096 R|^2 exceeds 2^53)
+        assert np.all(np.abs(P[pi, 0] - expect) <= 1e-15 * expect)
+
+
+@pytest.mark.parametrize("spc", [1, 2, 4])
+def test_noiseless_code_closed_form(spc):
+    """x[n] = c_p[(n - d) mod N] (I only, 0 Hz): R[tau] = 4096 Tc A(d - tau) with
+    A(k q + s) = (k - s) rho[q] + s rho[q + 1], rho the chip-level periodic
+    autocorrelation.  P = Nnc (Tc A)^2 exactly (integers)."""
+    fs = 1023000 * spc
+    N, Tc, Nnc, d, prn = 1023 * spc, 2, 2, 37 * spc + 1, 9
+    code = 1 - 2 * O.ca_code(prn).astype(np.int64)
+    rho = np.array([int(np.dot(code, np.roll(code, -q))) for q in range(1023)])
+    rep = O.code_replica(prn, fs, N).astype(np.int64)
+    sig = np.tile(np.roll(rep, d), Tc * Nnc)
+    x = _cplx_record(sig.astype(np.int8), np.zeros_like(sig, dtype=np.int8))
+    P = O.grid_direct(x, O.CPLX_I8, fs, 0.0, [prn], 0.0, 100.0, 1, Tc, Nnc)[0, 0]
+    tau = np.arange(N)
+    delta = (d - tau) % N
+    q, s = delta // spc, delta % spc
+    A = (spc - s) * rho[q] + s * rho[(q + 1) % 1023]
+    assert np.array_equal(P, Nnc * (Tc * A).astype(np.float64) ** 2)
+    assert int(np.argmax(P)) == d
+    assert P[d] == Nnc * float(Tc * N) ** 2
+
+
+def test_planted_tone_at_exact_bin_frequency():
+    fs, N, Tc, Nnc, prn, d = 4092000, 4092, 2, 3, 23, 1234
+    lo, step, nd = -1000.0, 500.0, 5
+    k = 3
+    D = O.nco_step(0.0, O.bin_freq(lo, step, k), float(fs))
+    fq = D * fs / 2.0 ** 32
+    n = np.arange(Tc * Nnc * N)
+    A = 60.0
+    rep = O.code_replica(prn, fs, N).astype(np.float64)
+    sig = A * np.tile(np.roll(rep, d), Tc * Nnc) * np.exp(2j * np.pi * fq * n / fs + 0.7j)
+    x = _cplx_record(np.rint(sig.real).astype(np.int8), np.rint(sig.imag).astype(np.int8))
+    P = O.grid_direct(x, O.CPLX_I8, fs, 0.0, [prn], lo, step, nd, Tc, Nnc)[0]
+    kk, tt = np.unravel_index(np.argmax(P), P.shape)
+    assert (kk, tt) == (k, d)
+    expect = Nnc * (A * Tc * N) ** 2
+    assert abs(P[k, d] / expect - 1.0) < 2e-3
+
+
+def test_fft_route_matches_direct_route():
+    snap, srch = synth.strong_real_2bit(O.ca_code, seed=4)
+    prns = [p.prn for p in snap.planted[:2]] + [31]
+    nd, lo = 7, -1500.0
+    args = (snap.samples, snap.fmt, snap.fs_hz, snap.f_if_hz, prns, lo, 500.0, nd, 1, 4)
+    Pd = O.grid_direct(*args)
+    Pf = O.grid_fft(*args)
+    for i in range(len(prns)):
+        tol = 1e-12 * (Pd[i] + Pd[i].mean())
+        assert np.all(np.abs(Pd[i] - Pf[i]) <= tol)
+
+
+def test_cells_equal_grid_cells():
+    snap, _ = synth.strong_real_2bit(O.ca_code, seed=5)
+    prns, lo, step, nd = [3, 14], -500.0, 500.0, 3
+    args = (snap.samples, snap.fmt, snap.fs_hz, snap.f_if_hz, prns, lo, step, nd, 1, 3)
+    P = O.grid_direct(*args)
+    rng = np.random.default_rng(0)
+    cells = np.stack([rng.integers(0, 2, 50), rng.integers(0, nd, 50),
+                      rng.integers(0, 4092, 50)], axis=1)
+    vals = O.cells_direct(*args, cells)
+    assert np.array_equal(vals, P[cells[:, 0], cells[:, 1], cells[:, 2]])
+
+
+def test_folded_blocks_are_sums_of_mixed_samples():
+    rng = np.random.default_rng(8)
+    fs, N, Tc, Nnc = 1023000, 1023, 3, 2
+    x = rng.integers(-127, 128, 2 * Tc * Nnc * N + 20).astype(np.int8)
+    f = O.wipe_fold(x, O.CPLX_I8, fs, 0.0, -200.0, 200.0, 3, Tc, Nnc)
+    for k in range(3):
+        D = O.nco_step(0.0, -200.0 + 200.0 * k, float(fs))
+        y = O.wipe(x, O.CPLX_I8, D, 0, Tc * Nnc * N)
+        for b in range(Nnc):
+            expect = y[b * Tc * N:(b + 1) * Tc * N].reshape(Tc, N, 2).sum(axis=0)
+            assert np.array_equal(f[k, b], expect)
+
+
+def test_strong_workload_recovers_planted():
+    snap, srch = synth.strong_real_2bit(O.ca_code, seed=1)
+    nd = O.n_doppler(srch.lo, srch.hi, srch.step)
+    assert nd == 21
+    P = O.grid_fft(snap.samples, snap.fmt, snap.fs_hz, snap.f_if_hz, srch.prns, srch.lo,
+                   srch.step, nd, srch.T_coh, srch.N_noncoh)
+    pk = O.peaks(P, srch.prns, 4, 2.5, srch.lo, srch.step)
+    planted = {p.prn: p for p in snap.planted}
+    for r in pk:
+        if r.prn in planted:
+            p = planted[r.prn]
+            assert r.detected
+            assert r.code_phase == p.code_phase
+            assert abs((srch.lo + r.doppler_bin * srch.step) - p.doppler_hz) <= 0.6 * srch.step
+        else:
+            assert not r.detected
+
+
+def test_invalid_arguments_rejected():
+    x = np.zeros(100, np.int8)
+    with pytest.raises(ValueError):
+        O.grid_direct(x, O.REAL_I8, 4092000, 0.0, [1], 0.0, 1.0, 1, 1, 1)  # too few samples
+    with pytest.raises(ValueError):
+        O.ca_code(38)
+    with pytest.raises(ValueError):
+        O.grid_direct(np.zeros(5000, np.int8), O.REAL_I8, 4092500, 0.0, [1], 0.0, 1.0, 1, 1, 1)
