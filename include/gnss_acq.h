@@ -1,0 +1,196 @@
+/*
+ * gnss_acq.h -- C ABI of the MI355X (gfx950) GPS L1 C/A acquisition engine.
+ *
+ * The engine is the acquisition channel of Karimi, Pamir and Afzal,
+ * "Accelerating a Cloud-Based Software GNSS Receiver" (Sec. 3, Figs. 1-2):
+ * carrier and code NCOs generate local replicas, the first mixing stage wipes
+ * the carrier off the recorded samples, FFTs of the mixed signal and of the
+ * code replica are multiplied (frequency-domain correlation) and an IFFT
+ * returns the correlation over every code shift, which is used to detect each
+ * satellite and to estimate its coarse Doppler and code phase.  Coherent
+ * blocks follow the paper's block processing (Sec. 4) and the whole coherent
+ * integration is processed as one batch on the device (Sec. 5).
+ *
+ * Conventions common to every entry point
+ *  - Every function returns int: GNSS_OK (0) or a negative GNSS_E* code;
+ *    gnss_last_error() then gives a thread-local message.
+ *  - Sample rate fs (Hz) must be an integer multiple of the chip rate
+ *    1.023 MHz, at most 16.368 MHz; N = fs/1000 samples per millisecond and
+ *    spc = fs/1.023e6 samples per chip.  Other rates give GNSS_ENOTSUP.
+ *  - Doppler bins f_k = lo + k*step (IEEE double, as written), k = 0..n_dopp-1,
+ *    n_dopp = floor((hi - lo)/step + 1e-9) + 1 (both ends inclusive).
+ *  - Coherent block b covers samples [b*T*N, (b+1)*T*N), T = T_coh_ms; blocks
+ *    start at sample 0 and samples beyond T*N_noncoh*N are ignored.
+ *  - Carrier NCO: 32-bit phase, step D_k = (uint32)(int64)llround((f_if + f_k)
+ *    * 2^32 / fs), phase of sample n = (uint32)(n * D_k), 1024-entry integer
+ *    LUT (amplitude 4096, index = phase >> 22), mixing by exp(-j theta).
+ *  - C/A codes: IS-GPS-200 Table 3-Ia, chip value 0 -> +1, 1 -> -1.
+ *  - Correlation of block b at lag tau (tau = sample at which chip 0 starts):
+ *      R_b[tau] = sum_{n in block b} y[n] * c[(n - tau) mod N]
+ *    Power grid P[p][k][tau] = sum_b |R_b[tau]|^2 * 2^-24, FP32, layout
+ *    [prn][doppler][tau] (tau fastest).
+ *  - Detection per PRN: Q[tau] = max_k P (lowest k on ties), tau* = argmax Q
+ *    (lowest tau), second = max Q over circular |tau - tau*| > spc,
+ *    ratio = peak/second, detected = ratio >= threshold (default 2.5).
+ *    Sub-bin refinement: 3-point parabolas in FP64 along tau (circular) and
+ *    along Doppler (not at the first or last bin).
+ */
+#ifndef GNSS_ACQ_H
+#define GNSS_ACQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define GNSS_OK 0
+#define GNSS_EINVAL (-1)   /* bad argument (null pointer, out-of-range value) */
+#define GNSS_ENOMEM (-2)   /* host or device allocation failed, or HBM budget exceeded */
+#define GNSS_EDEVICE (-3)  /* a HIP runtime call or kernel launch failed */
+#define GNSS_EBUSY (-4)    /* context busy */
+#define GNSS_ENOTSUP (-5)  /* valid but unsupported configuration (e.g. fs) */
+
+/* ---- sample formats ---------------------------------------------------- */
+#define GNSS_REAL_I8 0          /* one int8 per real sample (2-bit data as -3,-1,1,3) */
+#define GNSS_CPLX_I8 1          /* interleaved I, Q int8 per complex sample           */
+#define GNSS_REAL_2BIT_PACKED 2 /* 4 real samples per byte, first sample in the low
+                                   bits, 00:+1 01:+3 10:-1 11:-3                      */
+
+/* ---- precision --------------------------------------------------------- */
+#define GNSS_FP32 0
+
+/* One detection result per requested PRN (Sec. 3: coarse Doppler and code
+ * phase; refined values come from the FP64 parabolas). */
+typedef struct gnss_peak {
+    int32_t prn;          /* PRN number (1..37)                                */
+    int32_t doppler_bin;  /* k* (0-based index into the Doppler grid)          */
+    int32_t code_phase;   /* tau* in samples, 0..N-1                           */
+    int32_t detected;     /* 1 if ratio >= threshold                           */
+    float peak;           /* P[k*][tau*]                                       */
+    float second;         /* highest Q outside +-1 chip of tau*                */
+    float mean;           /* mean of P over the PRN's grid                     */
+    float ratio;          /* peak / second (+inf if second == 0)               */
+    double doppler_hz;    /* f_k* + delta_d * step                             */
+    double code_phase_frac; /* tau* + delta_c (samples)                        */
+} gnss_peak;
+
+typedef struct gnss_ctx gnss_ctx;
+
+/* A request: the arguments of gnss_acquire gathered in one struct. */
+typedef struct gnss_request {
+    const void *samples;   /* record (host memory for gnss_acquire, device memory
+                              for gnss_acquire_device)                         */
+    int32_t fmt;           /* GNSS_REAL_I8 / GNSS_CPLX_I8 / GNSS_REAL_2BIT_PACKED */
+    size_t n;              /* samples in the record (not bytes)                */
+    double fs;             /* sample rate, Hz                                  */
+    double f_if;           /* intermediate frequency, Hz (0 for baseband)      */
+    const int32_t *prn_list; /* host memory, n_prn PRN numbers in 1..37        */
+    int32_t n_prn;         /* 1..64                                            */
+    double doppler_lo, doppler_hi, doppler_step; /* Hz                        */
+    int32_t T_coh_ms;      /* coherent integration, 1..16 ms                   */
+    int32_t N_noncoh;      /* non-coherent blocks, >= 1                        */
+    float *out_grid;       /* nullable; n_prn*n_dopp*N floats [prn][dopp][tau] */
+    gnss_peak *out_peaks;  /* n_prn entries, same order as prn_list            */
+} gnss_request;
+
+/* Synchronous acquisition on host buffers (Sec. 3, Fig. 2).  Uses an
+ * internally locked default context on device 0; thread-safe.  samples,
+ * prn_list, out_grid (nullable) and out_peaks are host memory owned by the
+ * caller; outputs are written before the call returns.  Errors: GNSS_EINVAL
+ * (arguments), GNSS_ENOTSUP (fs), GNSS_ENOMEM, GNSS_EDEVICE. */
+int gnss_acquire(const void *samples, int32_t fmt, size_t n, double fs, double f_if,
+                 const int32_t *prn_list, int32_t n_prn, double doppler_lo,
+                 double doppler_hi, double doppler_step, int32_t T_coh_ms,
+                 int32_t N_noncoh, float *out_grid, gnss_peak *out_peaks);
+
+/* Context: one device, one HIP stream, the device-resident tables (carrier
+ * LUT, C/A codes, code spectra, twiddles) and a workspace that grows on
+ * demand up to hbm_budget_bytes (0 = no limit).  precision must be GNSS_FP32.
+ * Errors: GNSS_EINVAL, GNSS_ENOMEM, GNSS_EDEVICE. */
+int gnss_ctx_create(gnss_ctx **out, int device, size_t hbm_budget_bytes, int precision);
+void gnss_ctx_destroy(gnss_ctx *ctx);
+
+/* Context options: "threshold" (detection ratio, > 0), "hbm_budget" (bytes,
+ * 0 = unlimited), "profile" (1: record per-stage HIP events, see
+ * gnss_stage_times; 0: off).  Errors: GNSS_EINVAL. */
+int gnss_ctx_set(gnss_ctx *ctx, const char *key, double value);
+
+/* Device bytes the context's workspace needs for a request (does not
+ * allocate).  Errors: as gnss_acquire's argument checks. */
+int gnss_workspace_bytes(const gnss_request *req, size_t *bytes);
+
+/* Acquisition on device buffers (Sec. 3, Fig. 2; the whole coherent
+ * integration as one device batch, Sec. 5).  req->samples, req->out_grid
+ * (nullable) and req->out_peaks are device pointers; req->prn_list is host
+ * memory.  Work is enqueued on `stream` (a hipStream_t; NULL = the context's
+ * own stream) and the call returns without waiting; outputs are valid once
+ * the stream reaches that point.  The context's workspace is reused, so calls
+ * on one context must not overlap on different streams.  May allocate
+ * workspace on first use or growth.  Errors: GNSS_EINVAL, GNSS_ENOTSUP,
+ * GNSS_ENOMEM, GNSS_EDEVICE. */
+int gnss_acquire_device(gnss_ctx *ctx, const gnss_request *req, void *stream);
+
+/* ---- stage entry points (device pointers, enqueued on `stream`) ---------- */
+
+/* C/A code generator (code NCO source, Sec. 3 Fig. 2; IS-GPS-200 Table 3-Ia):
+ * d_codes[i*1023 + n] = chip n (0/1) of prn_list[i].  prn_list is host memory.
+ * Errors: GNSS_EINVAL. */
+int gnss_gold_codes(gnss_ctx *ctx, const int32_t *prn_list, int32_t n_prn, uint8_t *d_codes,
+                    void *stream);
+
+/* Code replica (code NCO, Sec. 3 Fig. 2): d_out[i*n + m] =
+ * 1 - 2*code_i[floor(m*1023000/fs) mod 1023] (int8), any integer fs in Hz. */
+int gnss_code_replica(gnss_ctx *ctx, const int32_t *prn_list, int32_t n_prn, double fs,
+                      size_t n, int8_t *d_out, void *stream);
+
+/* Carrier LUT (carrier NCO, Sec. 3 Fig. 2): d_cos[i], d_sin[i] =
+ * lround(4096 cos/sin(2 pi i/1024)), i < 1024 (int16). */
+int gnss_nco_lut(gnss_ctx *ctx, int16_t *d_cos, int16_t *d_sin, void *stream);
+
+/* First mixing stage + coherent folding (Sec. 3 Fig. 2; block processing,
+ * Sec. 4): d_out[((k*N_noncoh + b)*N + m)*2 + {0,1}] = re/im of
+ * sum_{t<T} y_k[(b*T + t)*N + m], exact int32.  Other fields of req as for
+ * gnss_acquire_device (outputs ignored). */
+int gnss_wipe_fold(gnss_ctx *ctx, const gnss_request *req, int32_t *d_out, void *stream);
+
+/* Batched 2048-point complex FFT (the FFT/IFFT stages of Fig. 2), natural
+ * order in and out, interleaved float re/im, forward exp(-2 pi i nk/2048) or
+ * (inverse != 0) unnormalised exp(+2 pi i nk/2048).  d_in and d_out hold
+ * batch*2048 complex values and may not overlap. */
+int gnss_fft2048(gnss_ctx *ctx, const float *d_in, float *d_out, int32_t batch,
+                 int32_t inverse, void *stream);
+
+/* Detection and refinement on a device grid [n_prn][n_dopp][N] (rule in the
+ * header comment): fills d_peaks[n_prn] (device memory).  spc > 0 gives the
+ * +-1 chip exclusion.  prn_list is host memory and only labels the results. */
+int gnss_peaks(gnss_ctx *ctx, const float *d_grid, const int32_t *prn_list, int32_t n_prn,
+               int32_t n_dopp, int32_t N, int32_t spc, double doppler_lo, double doppler_step,
+               gnss_peak *d_peaks, void *stream);
+
+/* ---- per-stage device timing -------------------------------------------- */
+#define GNSS_STAGE_WIPE_FOLD 0  /* carrier NCO, mixing, fold, boxcar, polyphase */
+#define GNSS_STAGE_FFT 1        /* forward FFT of the mixed blocks              */
+#define GNSS_STAGE_CORR 2       /* spectrum product, IFFT, |.|^2, block sum     */
+#define GNSS_STAGE_DETECT 3     /* column max, peaks, refinement                */
+#define GNSS_N_STAGES 4
+
+/* While the context's "profile" option is 1, every search records HIP events
+ * on its stream around each stage.  This call waits for the recorded events
+ * and adds their elapsed milliseconds to ms_total[i] and the number of timed
+ * launches to launches[i] (host arrays of n >= GNSS_N_STAGES entries, set to
+ * the totals since the last reset); reset != 0 clears the totals.
+ * Errors: GNSS_EINVAL, GNSS_EDEVICE. */
+int gnss_stage_times(gnss_ctx *ctx, double *ms_total, int64_t *launches, int32_t n, int32_t reset);
+
+/* ---- errors ------------------------------------------------------------ */
+const char *gnss_strerror(int code);
+const char *gnss_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GNSS_ACQ_H */

@@ -1,0 +1,66 @@
+// gnss_internal.hpp -- launch wrappers shared by the C ABI and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/gnss_acq.h"
+
+namespace gnss {
+
+constexpr int kMaxPrn = 37;            // PRNs 1..37 (IS-GPS-200 Table 3-Ia)
+constexpr int kCodeLen = 1023;
+constexpr int kMaxList = 64;           // PRNs per request (duplicates allowed)
+constexpr int kMaxSpc = 16;            // samples per chip: fs <= 16.368 MHz
+constexpr int kMaxN = kCodeLen * kMaxSpc;
+constexpr int kVec = 1024;             // float4 per storage-order spectrum (2048 complex)
+constexpr int kPolyLen = 1024;         // int2 per polyphase component (1023 + 1 zero)
+
+struct PrnList {
+    int32_t v[kMaxList];
+};
+
+// Derived sizes of one acquisition request.
+struct Plan {
+    int fmt;
+    int64_t n_samples;
+    int64_t fs_hz;
+    double f_if, lo, step;
+    int N;          // samples per ms
+    int spc;        // samples per chip
+    int n_dopp;
+    int Tc, Nnc;
+    int n_prn;
+    PrnList prns;   // PRN numbers (1..37)
+    int64_t grid_elems() const { return (int64_t)n_prn * n_dopp * N; }
+    int64_t n_vec() const { return (int64_t)n_dopp * Nnc * spc; }
+};
+
+// one-time tables
+hipError_t launch_gold_codes(uint8_t *d_codes /*[38][1023], row = prn*/, hipStream_t s);
+hipError_t launch_code_replica(const uint8_t *d_codes, PrnList prns, int n_prn, int64_t fs_hz,
+                               int64_t n, int8_t *d_out, hipStream_t s);
+hipError_t launch_lut(uint32_t *d_lut_packed, int16_t *d_cos, int16_t *d_sin, hipStream_t s);
+hipError_t launch_twiddles(float2 *d_tw, hipStream_t s);
+hipError_t launch_code_spectra(const uint8_t *d_codes, const float2 *d_tw, float4 *d_cs,
+                               hipStream_t s);
+
+// hot path
+hipError_t launch_wipe_fold(const void *d_samples, const Plan &p, const uint32_t *d_lut,
+                            int32_t *d_out /*[n_dopp][Nnc][N][2]*/, hipStream_t s);
+hipError_t launch_wipe_fold_box(const void *d_samples, const Plan &p, const uint32_t *d_lut,
+                                int2 *d_F, hipStream_t s);
+hipError_t launch_fft_poly(const int2 *d_F, const float2 *d_tw, float4 *d_G, int64_t n_vec,
+                           hipStream_t s);
+hipError_t launch_corr(const float4 *d_G, const float4 *d_cs, const float2 *d_tw, float *d_grid,
+                       const Plan &p, hipStream_t s);
+hipError_t launch_peaks(const float *d_grid, const Plan &p, float threshold, float *d_Q,
+                        int32_t *d_K, double *d_part, gnss_peak *d_peaks, hipStream_t s);
+size_t peak_scratch_part_elems(const Plan &p);
+
+// test entry: natural-order batched 2048-point transforms
+hipError_t launch_fft_test(const float2 *d_in, float2 *d_out, int batch, int inverse,
+                           const float2 *d_tw, hipStream_t s);
+
+}  // namespace gnss

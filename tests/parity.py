@@ -1,0 +1,67 @@
+"""Parity helpers shared by the GPU tests (no GPU or oracle code here).
+
+Tolerance on FP32 correlation power (per request and PRN grid):
+    |P_gpu - P_ref| <= 1e-4 * (P_ref + mean(P_ref))
+A pure per-cell relative test would fail on noiseless inputs, where off-peak
+cells are tiny exact integers; FP32 FFT rounding is relative to the norm of
+the whole transform, which the grid mean stands in for.
+
+Detections must be identical (detected flag, Doppler bin, code phase) unless
+the oracle's decision is a near tie: its two largest cells differ by less
+than 2e-4 relative, or its ratio is within 2e-4 of the threshold.
+"""
+import sys
+
+import numpy as np
+
+GRID_TOL = 1e-4
+TIE_REL = 2e-4
+
+
+def log(msg: str):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def grid_error(P_gpu: np.ndarray, P_ref: np.ndarray) -> float:
+    worst = 0.0
+    for i in range(P_ref.shape[0]):
+        ref = np.asarray(P_ref[i], np.float64)
+        g = np.asarray(P_gpu[i], np.float64)
+        err = np.abs(g - ref) / (ref + ref.mean())
+        worst = max(worst, float(err.max()))
+    return worst
+
+
+def assert_grid_close(P_gpu, P_ref, tol: float = GRID_TOL) -> float:
+    assert P_gpu.shape == P_ref.shape, (P_gpu.shape, P_ref.shape)
+    assert np.all(np.isfinite(P_gpu))
+    worst = grid_error(P_gpu, P_ref)
+    assert worst <= tol, "max mixed-relative power error %.3e > %.1e" % (worst, tol)
+    return worst
+
+
+def compare_detections(gpu_peaks, ref_peaks, P_ref, threshold: float = 2.5):
+    """Returns the number of near-tie exemptions; raises on a real mismatch."""
+    exempt = 0
+    for i, r in enumerate(ref_peaks):
+        g = gpu_peaks[i]
+        assert int(g["prn"]) == r.prn
+        same_cell = int(g["doppler_bin"]) == r.doppler_bin and int(g["code_phase"]) == r.code_phase
+        same_det = bool(g["detected"]) == r.detected
+        if same_cell:
+            assert abs(float(g["peak"]) - r.peak) <= 1e-4 * r.peak, (r.prn, g["peak"], r.peak)
+        assert abs(float(g["mean"]) - r.mean) <= 1e-4 * r.mean, (r.prn, g["mean"], r.mean)
+        if same_cell and same_det:
+            continue
+        flat = np.asarray(P_ref[i], np.float64).ravel()
+        v2, v1 = np.partition(flat, -2)[-2:]
+        near_cell = (v1 - v2) <= TIE_REL * v1
+        near_thr = abs(r.ratio - threshold) <= TIE_REL * threshold
+        if (same_cell and near_thr) or near_cell:
+            exempt += 1
+            continue
+        raise AssertionError("PRN %d: gpu (det %d, k %d, tau %d) vs oracle (det %d, k %d, tau %d), "
+                             "ratio %.6f" % (r.prn, g["detected"], g["doppler_bin"], g["code_phase"],
+                                             r.detected, r.doppler_bin, r.code_phase, r.ratio))
+    return exempt
