@@ -125,15 +125,16 @@ int gnss_workspace_bytes(const gnss_request *req, size_t *bytes);
 /* Acquisition on device buffers (Sec. 3, Fig. 2; the whole coherent
  * integration as one device batch, Sec. 5).  req->samples, req->out_grid
  * (nullable) and req->out_peaks are device pointers; req->prn_list is host
- * memory.  Work is enqueued on `stream` (a hipStream_t; NULL = the context's
- * own stream) and the call returns without waiting; outputs are valid once
+ * memory.  Work is enqueued on `stream` (a hipStream_t; NULL = the HIP null
+ * stream, which is PyTorch's default stream) and the call returns without waiting; outputs are valid once
  * the stream reaches that point.  The context's workspace is reused, so calls
  * on one context must not overlap on different streams.  May allocate
  * workspace on first use or growth.  Errors: GNSS_EINVAL, GNSS_ENOTSUP,
  * GNSS_ENOMEM, GNSS_EDEVICE. */
 int gnss_acquire_device(gnss_ctx *ctx, const gnss_request *req, void *stream);
 
-/* ---- stage entry points (device pointers, enqueued on `stream`) ---------- */
+/* ---- stage entry points (device pointers, enqueued on `stream`, a
+ *      hipStream_t; NULL = the HIP null stream) ----------------------------- */
 
 /* C/A code generator (code NCO source, Sec. 3 Fig. 2; IS-GPS-200 Table 3-Ia):
  * d_codes[i*1023 + n] = chip n (0/1) of prn_list[i].  prn_list is host memory.

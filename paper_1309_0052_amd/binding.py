@@ -7,6 +7,14 @@ import os
 
 import numpy as np
 
+try:
+    # Load PyTorch's HIP runtime first when it is present: the library then
+    # binds to that same runtime (one runtime per process), which is also what
+    # lets it run on torch-allocated memory and torch streams.
+    import torch  # noqa: F401
+except ImportError:  # plain C/numpy users get the system ROCm runtime
+    torch = None
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgnss_acq.so")
 

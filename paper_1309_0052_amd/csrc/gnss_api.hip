@@ -442,7 +442,7 @@ int gnss_acquire_device(gnss_ctx *ctx, const gnss_request *req, void *stream)
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
     if (g.rc) return g.rc;
-    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    hipStream_t s = (hipStream_t)stream;
     return run_device(ctx, p, req->samples, req->out_grid, req->out_peaks, s);
 }
 
@@ -506,7 +506,7 @@ int gnss_gold_codes(gnss_ctx *ctx, const int32_t *prn_list, int32_t n_prn, uint8
         if (prn_list[i] < 1 || prn_list[i] > gnss::kMaxPrn) return set_err(GNSS_EINVAL, "PRN outside [1, 37]");
     DeviceGuard g(ctx->device);
     if (g.rc) return g.rc;
-    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    hipStream_t s = (hipStream_t)stream;
     // rows of the context's generated table, gathered in list order
     for (int i = 0; i < n_prn; ++i)
         HIP_TRY(hipMemcpyAsync(d_codes + (size_t)i * gnss::kCodeLen, ctx->d_codes + prn_list[i] * gnss::kCodeLen,
@@ -529,7 +529,7 @@ int gnss_code_replica(gnss_ctx *ctx, const int32_t *prn_list, int32_t n_prn, dou
     if (n == 0) return GNSS_OK;
     DeviceGuard g(ctx->device);
     if (g.rc) return g.rc;
-    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    hipStream_t s = (hipStream_t)stream;
     HIP_TRY(gnss::launch_code_replica(ctx->d_codes, pl, n_prn, (int64_t)fs, (int64_t)n, d_out, s));
     return GNSS_OK;
 }
@@ -539,7 +539,7 @@ int gnss_nco_lut(gnss_ctx *ctx, int16_t *d_cos, int16_t *d_sin, void *stream)
     if (!ctx || !d_cos || !d_sin) return set_err(GNSS_EINVAL, "null argument");
     DeviceGuard g(ctx->device);
     if (g.rc) return g.rc;
-    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    hipStream_t s = (hipStream_t)stream;
     HIP_TRY(gnss::launch_lut(nullptr, d_cos, d_sin, s));
     return GNSS_OK;
 }
@@ -552,7 +552,7 @@ int gnss_wipe_fold(gnss_ctx *ctx, const gnss_request *req, int32_t *d_out, void 
     if (rc) return rc;
     DeviceGuard g(ctx->device);
     if (g.rc) return g.rc;
-    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    hipStream_t s = (hipStream_t)stream;
     HIP_TRY(gnss::launch_wipe_fold(req->samples, p, ctx->d_lut, d_out, s));
     return GNSS_OK;
 }
@@ -565,7 +565,7 @@ int gnss_fft2048(gnss_ctx *ctx, const float *d_in, float *d_out, int32_t batch, 
     if (d_in == d_out) return set_err(GNSS_EINVAL, "in-place transform is not supported");
     DeviceGuard g(ctx->device);
     if (g.rc) return g.rc;
-    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    hipStream_t s = (hipStream_t)stream;
     HIP_TRY(gnss::launch_fft_test((const float2 *)d_in, (float2 *)d_out, batch, inverse ? 1 : 0, ctx->d_tw, s));
     return GNSS_OK;
 }
@@ -592,7 +592,7 @@ int gnss_peaks(gnss_ctx *ctx, const float *d_grid, const int32_t *prn_list, int3
     int rc;
     if ((rc = ensure(ctx, ctx->Q, w.Q)) || (rc = ensure(ctx, ctx->K, w.K)) || (rc = ensure(ctx, ctx->part, w.part)))
         return rc;
-    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    hipStream_t s = (hipStream_t)stream;
     HIP_TRY(gnss::launch_peaks(d_grid, p, ctx->threshold, (float *)ctx->Q.p, (int32_t *)ctx->K.p,
                                (double *)ctx->part.p, d_peaks, s));
     return GNSS_OK;

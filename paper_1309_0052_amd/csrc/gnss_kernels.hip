@@ -284,58 +284,74 @@ hipError_t launch_wipe_fold(const void *d_samples, const Plan &p, const uint32_t
     return hipGetLastError();
 }
 
-// Hot-path stage A1: wipe + fold into LDS, then the one-chip boxcar
-// F[n] = sum_{t<spc} f[(n+t) mod N] as a sliding sum over runs of 16
-// outputs, written split by phase: Fout[k][b][s][m] = F[spc m + s], m < 1023,
-// Fout[..][1023] = 0.  All integer, exact.
-constexpr int kRun = 16;
-__device__ __forceinline__ int pidx(int n) { return n + (n >> 4); }  // bank-conflict padding
+// Hot-path stage A1: wipe + fold, then the one-chip boxcar
+// F[n] = sum_{t<spc} f[(n+t) mod N], written split by phase:
+// Fout[k][b][s][m] = F[spc m + s] (m < 1023), Fout[..][1023] = 0.  Each
+// workgroup covers a chunk of kBoxChunk outputs of one (Doppler, block) and
+// wipes the spc - 1 samples past it as a halo.  All integer, exact.
+constexpr int kBoxChunk = 2048;
+constexpr int kBoxRun = 8;
+__device__ __forceinline__ int bpad(int i) { return i + (i >> 3); }  // bank-conflict padding
 
 __global__ __launch_bounds__(256) void k_wipe_fold_box(const void *samples, const uint32_t *lut,
-                                                       WipeArgs a, int2 *Fout)
+                                                       WipeArgs a, int2 *Fout, int n_chunks)
 {
-    __shared__ int2 s_f[kMaxN + kMaxN / 16 + 16];
+    __shared__ int2 s_f[(kBoxChunk + kMaxSpc) + (kBoxChunk + kMaxSpc) / 8 + 8];
     __shared__ uint32_t s_lut[1024];
     for (int i = threadIdx.x; i < 1024; i += 256) s_lut[i] = lut[i];
-    const int k = blockIdx.x / a.Nnc, b = blockIdx.x % a.Nnc;
+    const int chunk = blockIdx.x % n_chunks, kb = blockIdx.x / n_chunks;
+    const int k = kb / a.Nnc, b = kb % a.Nnc;
     const uint32_t D = nco_step(a, k);
     const int N = a.N, spc = a.spc;
+    const int n0 = chunk * kBoxChunk;
+    const int cnt = min(kBoxChunk, N - n0);
+    const int len = cnt + spc - 1;
     __syncthreads();
-    for (int m = threadIdx.x; m < N; m += 256) s_f[pidx(m)] = wipe_fold_one(samples, a, s_lut, D, b, m);
+    for (int i = threadIdx.x; i < len; i += 256) {
+        int n = n0 + i;
+        if (n >= N) n -= N;
+        s_f[bpad(i)] = wipe_fold_one(samples, a, s_lut, D, b, n);
+    }
     __syncthreads();
-    int2 *dst = Fout + (long long)blockIdx.x * spc * kPolyLen;
-    const int n_runs = (N + kRun - 1) / kRun;
+    int2 *dst = Fout + (long long)kb * spc * kPolyLen;
+    const int n_runs = (cnt + kBoxRun - 1) / kBoxRun;
     for (int r = threadIdx.x; r < n_runs; r += 256) {
-        const int n0 = r * kRun;
+        const int i0 = r * kBoxRun;
         int sx = 0, sy = 0;
         for (int t = 0; t < spc; ++t) {
-            int idx = n0 + t;
-            if (idx >= N) idx -= N;
-            int2 v = s_f[pidx(idx)];
+            int2 v = s_f[bpad(i0 + t)];
             sx += v.x;
             sy += v.y;
         }
-        for (int j = 0; j < kRun; ++j) {
-            const int n = n0 + j;
-            if (n >= N) break;
-            const int m = n / spc, s = n - m * spc;
+        const int n = n0 + i0;
+        int m = n / spc, s = n - m * spc;
+#pragma unroll
+        for (int j = 0; j < kBoxRun; ++j) {
+            const int i = i0 + j;
+            if (i >= cnt) break;
             dst[s * kPolyLen + m] = make_int2(sx, sy);
-            int nin = n + spc;
-            if (nin >= N) nin -= N;
-            int2 vo = s_f[pidx(n)], vi = s_f[pidx(nin)];
-            sx += vi.x - vo.x;
-            sy += vi.y - vo.y;
+            if (i + 1 < cnt) {
+                int2 vi = s_f[bpad(i + spc)], vo = s_f[bpad(i)];
+                sx += vi.x - vo.x;
+                sy += vi.y - vo.y;
+            }
+            if (++s == spc) {
+                s = 0;
+                ++m;
+            }
         }
     }
-    if (threadIdx.x < spc) dst[threadIdx.x * kPolyLen + (kPolyLen - 1)] = make_int2(0, 0);
+    if (chunk == 0 && threadIdx.x < spc) dst[threadIdx.x * kPolyLen + (kPolyLen - 1)] = make_int2(0, 0);
 }
 
 hipError_t launch_wipe_fold_box(const void *d_samples, const Plan &p, const uint32_t *d_lut,
                                 int2 *d_F, hipStream_t s)
 {
     WipeArgs a{p.fmt, p.N, p.spc, p.Tc, p.Nnc, (double)p.fs_hz, p.f_if, p.lo, p.step};
-    hipLaunchKernelGGL(k_wipe_fold_box, dim3(p.n_dopp * p.Nnc), dim3(256), 0, s, d_samples, d_lut,
-                       a, d_F);
+    const int n_chunks = (p.N + kBoxChunk - 1) / kBoxChunk;
+    const long long nwg = (long long)p.n_dopp * p.Nnc * n_chunks;
+    hipLaunchKernelGGL(k_wipe_fold_box, dim3((unsigned)nwg), dim3(256), 0, s, d_samples, d_lut, a,
+                       d_F, n_chunks);
     return hipGetLastError();
 }
 
