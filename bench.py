@@ -109,6 +109,8 @@ def main():
     ap.add_argument("--workload", default="weak", choices=["weak", "strong"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the search shards by request or by PRN with no "
@@ -131,6 +133,13 @@ def main():
         ctx.gold_codes([prn], d.data_ptr(), stream)
         torch.cuda.synchronize()
         return d.cpu().numpy()
+
+    if args.copy_mb:
+        a = torch.ones(args.copy_mb << 18, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     snap, srch, desc = workload(args.workload, code_fn)
     nd = G.n_doppler(srch.lo, srch.hi, srch.step)
