@@ -195,12 +195,22 @@ __device__ __forceinline__ void dft16(float2 (&a)[LEN])
 // ---------------------------------------------------------------------------
 // wave-private LDS transposes
 // ---------------------------------------------------------------------------
-// Row strides (in float2) of the two transpose buffers; padded against bank
-// conflicts.  A wave needs kXbufElems float2 of LDS scratch.
-constexpr int kStrideA = 136;  // rows of 128 (+8) for the n2 x k1 exchange
-constexpr int kStrideB = 152;  // rows of 16 x 9 (+8) for the (k1, m2) x k2a exchange
-constexpr int kXbufElems = 8 * kStrideB;
-static_assert(8 * kStrideA <= kXbufElems, "transpose buffer");
+// Row strides (in float2) of the two transpose buffers.  A wave needs
+// kXbufElems float2 of LDS scratch.  Exchange A writes rows of 128 and reads
+// 8 rows x 8 columns per 32 lanes: a stride of 136 (= 8 mod 32 float2) puts the
+// 8 rows in distinct 64-byte bank groups.  Exchange B is indexed
+// kl*kStrideB + 8*k1 + (m2 ^ (k1 >> 2)); with kStrideB = 4 mod 8 both its
+// write (8 k1 x 8 m2 per 32 lanes) and its read (16 k1 x 2 rows per 32 lanes)
+// touch 32 distinct 8-byte bank slots.
+constexpr int kStrideA = 136;
+constexpr int kStrideB = 132;
+constexpr int kXbufElems = 8 * kStrideA;
+static_assert(8 * kStrideB <= kXbufElems, "transpose buffer");
+
+__device__ __forceinline__ int xb_b(int kl, int k1, int m2)
+{
+    return kl * kStrideB + 8 * k1 + (m2 ^ ((k1 >> 2) & 7));
+}
 
 __device__ __forceinline__ void lds_fence()
 {
@@ -266,14 +276,13 @@ __device__ __forceinline__ void transpose_b_inv(float2 (&v)[32], float2 *xb, int
         for (int hp = 0; hp < 2; ++hp)
 #pragma unroll
             for (int kl = 0; kl < 8; ++kl)
-                xb[kl * kStrideB + 9 * ((l >> 3) + 8 * hp) + (l & 7)] = v[16 * hp + 8 * hb + kl];
+                xb[xb_b(kl, (l >> 3) + 8 * hp, l & 7)] = v[16 * hp + 8 * hb + kl];
         lds_fence();
 #pragma unroll
-        for (int uu = 0; uu < 2; ++uu) {
-            const float2 *src = xb + ((l >> 4) + 4 * uu) * kStrideB + 9 * (l & 15);
+        for (int uu = 0; uu < 2; ++uu)
 #pragma unroll
-            for (int m2 = 0; m2 < 8; ++m2) nv[8 * (2 * hb + uu) + m2] = src[m2];
-        }
+            for (int m2 = 0; m2 < 8; ++m2)
+                nv[8 * (2 * hb + uu) + m2] = xb[xb_b((l >> 4) + 4 * uu, l & 15, m2)];
         lds_fence();
     }
 #pragma unroll
@@ -287,17 +296,16 @@ __device__ __forceinline__ void transpose_b_fwd(float2 (&v)[32], float2 *xb, int
 #pragma unroll
     for (int hb = 0; hb < 2; ++hb) {
 #pragma unroll
-        for (int uu = 0; uu < 2; ++uu) {
-            float2 *dst = xb + ((l >> 4) + 4 * uu) * kStrideB + 9 * (l & 15);
+        for (int uu = 0; uu < 2; ++uu)
 #pragma unroll
-            for (int m2 = 0; m2 < 8; ++m2) dst[m2] = v[8 * (2 * hb + uu) + m2];
-        }
+            for (int m2 = 0; m2 < 8; ++m2)
+                xb[xb_b((l >> 4) + 4 * uu, l & 15, m2)] = v[8 * (2 * hb + uu) + m2];
         lds_fence();
 #pragma unroll
         for (int hp = 0; hp < 2; ++hp)
 #pragma unroll
             for (int kl = 0; kl < 8; ++kl)
-                nv[16 * hp + 8 * hb + kl] = xb[kl * kStrideB + 9 * ((l >> 3) + 8 * hp) + (l & 7)];
+                nv[16 * hp + 8 * hb + kl] = xb[xb_b(kl, (l >> 3) + 8 * hp, l & 7)];
         lds_fence();
     }
 #pragma unroll

@@ -419,15 +419,29 @@ __device__ __forceinline__ int xcd_remap(int bid, int nwg)
 
 constexpr int kCorrWaves = 8;
 
+// Staging of the finished sums for the grid write: [PT][1024 q][9] floats
+// (8 waves + 1 pad, so both the per-wave writes and the per-row reads are
+// free of bank conflicts).
+constexpr int kStagePad = kCorrWaves + 1;
+
 template <int PT>
 __global__ __launch_bounds__(64 * kCorrWaves) void k_corr(const float4 *G,
                                                           const float4 *__restrict__ CS,
                                                           const float2 *__restrict__ tw,
                                                           float *__restrict__ grid, CorrArgs a)
 {
-    __shared__ float4 s_cc[PT][kVec];
-    __shared__ float2 s_tw[kTwElems];
-    __shared__ float2 s_xb[kCorrWaves][kXbufElems];
+    constexpr int kCcBytes = PT * kVec * (int)sizeof(float4);
+    constexpr int kTwBytes = kTwElems * (int)sizeof(float2);
+    constexpr int kXbBytes = kCorrWaves * kXbufElems * (int)sizeof(float2);
+    constexpr int kStageBytes = PT * 1024 * kStagePad * (int)sizeof(float);
+    constexpr int kSmem = (kCcBytes + kTwBytes + kXbBytes) > kStageBytes ? (kCcBytes + kTwBytes + kXbBytes)
+                                                                          : kStageBytes;
+    __shared__ __align__(16) unsigned char smem[kSmem];
+    float4 *s_cc = (float4 *)smem;
+    float2 *s_tw = (float2 *)(smem + kCcBytes);
+    float2 *s_xb = (float2 *)(smem + kCcBytes + kTwBytes);
+    float *s_stage = (float *)smem;  // reused after the transforms
+
     const int tid = threadIdx.x;
     const int logical = xcd_remap(blockIdx.x, gridDim.x);
     const int ptile = logical % a.n_ptiles, chunk = logical / a.n_ptiles;
@@ -435,14 +449,14 @@ __global__ __launch_bounds__(64 * kCorrWaves) void k_corr(const float4 *G,
         int p = i / kVec, e = i - p * kVec;
         int pi = ptile * PT + p;
         int prn = pi < a.n_prn ? a.prns.v[pi] : 0;
-        s_cc[p][e] = CS[(long long)prn * kVec + e];
+        s_cc[i] = CS[(long long)prn * kVec + e];
     }
     stage_twiddles(s_tw, tw, tid, 64 * kCorrWaves);
     __syncthreads();
 
     const int w = tid >> 6, l = tid & 63;
     const int item = chunk * kCorrWaves + w;
-    if (item >= a.n_items) return;
+    const bool active = item < a.n_items;
     const int k = item / a.spc, s = item - k * a.spc;
 
     float acc[PT][16];
@@ -451,53 +465,75 @@ __global__ __launch_bounds__(64 * kCorrWaves) void k_corr(const float4 *G,
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[p][i] = 0.f;
 
-    const float4 *gk = G + ((long long)k * a.Nnc * a.spc + s) * kVec;
-    for (int b = 0; b < a.Nnc; ++b) {
-        const float4 *gp = gk + (long long)b * a.spc * kVec;
-        // PRN slots past n_prn hold the all-zero spectrum of row 0; they are
-        // computed (no branch in the loop) but never written.
+    if (active) {
+        const float4 *gk = G + ((long long)k * a.Nnc * a.spc + s) * kVec;
+        float2 *xb = s_xb + w * kXbufElems;
+        for (int b = 0; b < a.Nnc; ++b) {
+            const float4 *gp = gk + (long long)b * a.spc * kVec;
+            // PRN slots past n_prn hold the all-zero spectrum of row 0; they are
+            // computed (no branch in the loop) but never written.
 #pragma unroll
-        for (int p = 0; p < PT; ++p) {
-            // the block spectrum is re-read for every PRN of the tile (L1/L2
-            // hits after the first) rather than pinned in registers
-            float2 z[32];
-            // launder the block pointer so the compiler does not merge these
-            // loads with the previous PRN's (which would pin 64 more VGPRs)
-            const float4 *gq = gp;
-            asm volatile("" : "+v"(gq));
-            phase_barrier();
+            for (int p = 0; p < PT; ++p) {
+                // the block spectrum is re-read for every PRN of the tile (L1/L2
+                // hits after the first) rather than pinned in registers
+                float2 z[32];
+                const float4 *gq = gp;
+                asm volatile("" : "+v"(gq));
+                phase_barrier();
 #pragma unroll
-            for (int jj = 0; jj < 16; ++jj) {
-                float4 t = gq[jj * 64 + l];
-                float4 c = s_cc[p][jj * 64 + l];
-                z[2 * jj] = c_mul(make_float2(t.x, t.y), make_float2(c.x, c.y));
-                z[2 * jj + 1] = c_mul(make_float2(t.z, t.w), make_float2(c.z, c.w));
-            }
-            phase_barrier();
-            ifft2048<true>(z, s_xb[w], s_tw, s_tw + kT1Elems, l);
-            phase_barrier();
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int k2b = 0; k2b < 4; ++k2b) {
-                    float2 r = z[8 * u + k2b];
-                    acc[p][4 * u + k2b] = fmaf(r.x, r.x, fmaf(r.y, r.y, acc[p][4 * u + k2b]));
+                for (int jj = 0; jj < 16; ++jj) {
+                    float4 t = gq[jj * 64 + l];
+                    float4 c = s_cc[p * kVec + jj * 64 + l];
+                    z[2 * jj] = c_mul(make_float2(t.x, t.y), make_float2(c.x, c.y));
+                    z[2 * jj + 1] = c_mul(make_float2(t.z, t.w), make_float2(c.z, c.w));
                 }
+                phase_barrier();
+                ifft2048<true>(z, xb, s_tw, s_tw + kT1Elems, l);
+                phase_barrier();
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int k2b = 0; k2b < 4; ++k2b) {
+                        float2 r = z[8 * u + k2b];
+                        acc[p][4 * u + k2b] = fmaf(r.x, r.x, fmaf(r.y, r.y, acc[p][4 * u + k2b]));
+                    }
+            }
         }
     }
-    // P = |IFFT|^2 * 2^-46: 2^-22 for the unnormalised 2048-point IFFT, 2^-24 for the LUT scale
+
+    // Grid write.  P = |IFFT|^2 * 2^-46 (2^-22 for the unnormalised 2048-point
+    // IFFT, 2^-24 for the LUT scale).  Lag tau = spc*q + s interleaves the
+    // waves' phases, so the sums are staged in LDS and written as contiguous
+    // runs of consecutive tau.
+    __syncthreads();
 #pragma unroll
-    for (int p = 0; p < PT; ++p) {
-        const int pi = ptile * PT + p;
-        if (pi >= a.n_prn) break;
-        float *row = grid + ((long long)pi * a.n_dopp + k) * a.N + s;
+    for (int p = 0; p < PT; ++p)
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
             for (int k2b = 0; k2b < 4; ++k2b) {
                 int q = l + 64 * u + 256 * k2b;
-                if (q < kCodeLen) row[(long long)a.spc * q] = acc[p][4 * u + k2b] * 0x1p-46f;
+                s_stage[(p * 1024 + q) * kStagePad + w] = acc[p][4 * u + k2b] * 0x1p-46f;
             }
+    __syncthreads();
+    const int first = chunk * kCorrWaves;
+    const int n_items_here = min(kCorrWaves, a.n_items - first);
+    int wa = 0;
+    while (wa < n_items_here) {
+        const int ka = (first + wa) / a.spc, sa = (first + wa) - ka * a.spc;
+        int ns = min(a.spc - sa, n_items_here - wa);  // consecutive phases of Doppler bin ka
+        const int total = kCodeLen * ns;
+        for (int p = 0; p < PT; ++p) {
+            const int pi = ptile * PT + p;
+            if (pi >= a.n_prn) break;
+            float *row = grid + ((long long)pi * a.n_dopp + ka) * a.N + sa;
+            const float *st = s_stage + p * 1024 * kStagePad + wa;
+            for (int idx = tid; idx < total; idx += 64 * kCorrWaves) {
+                const int q = idx / ns, j = idx - q * ns;
+                row[(long long)a.spc * q + j] = st[q * kStagePad + j];
+            }
+        }
+        wa += ns;
     }
 }
 
