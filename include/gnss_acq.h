@@ -114,8 +114,10 @@ int gnss_ctx_create(gnss_ctx **out, int device, size_t hbm_budget_bytes, int pre
 void gnss_ctx_destroy(gnss_ctx *ctx);
 
 /* Context options: "threshold" (detection ratio, > 0), "hbm_budget" (bytes,
- * 0 = unlimited), "profile" (1: record per-stage HIP events, see
- * gnss_stage_times; 0: off).  Errors: GNSS_EINVAL. */
+ * 0 = unlimited; device memory of tables and workspaces), "profile" (1:
+ * record per-stage HIP events, see gnss_stage_times; 0: off), "corr_ptile"
+ * (PRNs per correlation workgroup: 2 or 4; 0 = autotuned, default 4),
+ * "max_slots" (requests per served batch, 1..4096).  Errors: GNSS_EINVAL. */
 int gnss_ctx_set(gnss_ctx *ctx, const char *key, double value);
 
 /* Device bytes the context's workspace needs for a request (does not
@@ -132,6 +134,61 @@ int gnss_workspace_bytes(const gnss_request *req, size_t *bytes);
  * workspace on first use or growth.  Errors: GNSS_EINVAL, GNSS_ENOTSUP,
  * GNSS_ENOMEM, GNSS_EDEVICE. */
 int gnss_acquire_device(gnss_ctx *ctx, const gnss_request *req, void *stream);
+
+/* Batched acquisition on device buffers: n_req requests of any lengths,
+ * sample rates, PRN lists and Doppler windows searched by one pass of the
+ * persistent stage kernels (the batch mode of the paper's Listing 3(b),
+ * applied to whole requests).  Each request as for gnss_acquire_device.
+ * Results are identical to running each request alone.  Errors: as
+ * gnss_acquire_device; a bad request reports its index. */
+int gnss_acquire_batch_device(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, void *stream);
+
+/* A batch captured once into a HIP graph (metadata copy and every stage
+ * kernel) with its own workspace, replayed by gnss_graph_launch on any
+ * stream; device buffers named by the requests must stay valid and keep
+ * their sizes.  Replays of one graph must not overlap.  Errors: as
+ * gnss_acquire_batch_device. */
+typedef struct gnss_graph gnss_graph;
+int gnss_graph_create(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, gnss_graph **out);
+int gnss_graph_launch(gnss_graph *graph, void *stream);
+void gnss_graph_destroy(gnss_graph *graph);
+
+/* Picks the correlation PRN tile (2 or 4) for batches with the sample rates
+ * of `reqs` by timing both on the device (reqs are device-buffer requests,
+ * their outputs are overwritten), or takes it from the text cache file
+ * `cache_path` (nullable) keyed by device and rate signature; writes the
+ * cache and sets the context to use the choice.  *chosen (nullable) gets it. */
+int gnss_autotune(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, const char *cache_path,
+                  int32_t *chosen);
+
+/* ---- serving: continuous batching of submitted requests --------------- */
+/* Outcome of a finished ticket: status (GNSS_OK or the request's error),
+ * seconds queued (submission to start of its batch), running (batch start
+ * to results delivered) and in total, and the size of its batch. */
+typedef struct gnss_ticket_info {
+    int32_t status;
+    int32_t batch_size;
+    double queued_s, run_s, total_s;
+} gnss_ticket_info;
+
+/* Submits a request with host buffers (the paper's cloud setting, Sec. 1:
+ * clients upload recordings, results go back).  samples are copied before
+ * the call returns; prn_list is copied; out_peaks (and out_grid if not
+ * null) must stay valid until the ticket is reported done.  A context
+ * thread batches queued requests as batch slots and the HBM budget allow
+ * (two batches in flight, overlapping on the device).  Errors: argument
+ * errors as gnss_acquire; GNSS_ENOMEM if the request alone exceeds a batch
+ * slot's share of the budget. */
+int gnss_submit(gnss_ctx *ctx, const gnss_request *req, uint64_t *ticket);
+
+/* Non-blocking completion check.  When *done is 1 the outputs are written,
+ * info (nullable) is filled, the ticket is released and the return value is
+ * the request's status. */
+int gnss_poll(gnss_ctx *ctx, uint64_t ticket, int *done, gnss_ticket_info *info);
+
+/* Blocks until the ticket is done (timeout_s < 0: no limit); then as
+ * gnss_poll with *done = 1.  GNSS_EBUSY on timeout (ticket kept). */
+int gnss_wait(gnss_ctx *ctx, uint64_t ticket, double timeout_s, gnss_ticket_info *info);
 
 /* ---- stage entry points (device pointers, enqueued on `stream`, a
  *      hipStream_t; NULL = the HIP null stream) ----------------------------- */

@@ -34,7 +34,9 @@ EXPORTED = [
     "gnss_acquire", "gnss_ctx_create", "gnss_ctx_destroy", "gnss_ctx_set",
     "gnss_workspace_bytes", "gnss_acquire_device", "gnss_gold_codes", "gnss_code_replica",
     "gnss_nco_lut", "gnss_wipe_fold", "gnss_fft2048", "gnss_peaks", "gnss_stage_times",
-    "gnss_strerror", "gnss_last_error",
+    "gnss_strerror", "gnss_last_error", "gnss_acquire_batch_device", "gnss_graph_create",
+    "gnss_graph_launch", "gnss_graph_destroy", "gnss_autotune", "gnss_submit", "gnss_poll",
+    "gnss_wait",
 ]
 
 GNSS_N_STAGES = 4
@@ -71,6 +73,12 @@ class gnss_request(ctypes.Structure):
                 ("out_peaks", ctypes.c_void_p)]
 
 
+class gnss_ticket_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("batch_size", ctypes.c_int32),
+                ("queued_s", ctypes.c_double), ("run_s", ctypes.c_double),
+                ("total_s", ctypes.c_double)]
+
+
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError("libgnss_acq.so is not built (run __graft_entry__.build() or "
@@ -92,6 +100,16 @@ def _load() -> ctypes.CDLL:
         "gnss_fft2048": [vp, vp, vp, i32, i32, vp],
         "gnss_peaks": [vp, vp, pi32, i32, i32, i32, i32, dbl, dbl, vp, vp],
         "gnss_stage_times": [vp, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64), i32, i32],
+        "gnss_acquire_batch_device": [vp, ctypes.POINTER(gnss_request), i32, vp],
+        "gnss_graph_create": [vp, ctypes.POINTER(gnss_request), i32, ctypes.POINTER(vp)],
+        "gnss_graph_launch": [vp, vp],
+        "gnss_graph_destroy": [vp],
+        "gnss_autotune": [vp, ctypes.POINTER(gnss_request), i32, ctypes.c_char_p,
+                          ctypes.POINTER(i32)],
+        "gnss_submit": [vp, ctypes.POINTER(gnss_request), ctypes.POINTER(ctypes.c_uint64)],
+        "gnss_poll": [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int),
+                      ctypes.POINTER(gnss_ticket_info)],
+        "gnss_wait": [vp, ctypes.c_uint64, dbl, ctypes.POINTER(gnss_ticket_info)],
         "gnss_strerror": [ctypes.c_int],
         "gnss_last_error": [],
     }
@@ -100,6 +118,7 @@ def _load() -> ctypes.CDLL:
         f.argtypes = args
         f.restype = ctypes.c_int
     lib.gnss_ctx_destroy.restype = None
+    lib.gnss_graph_destroy.restype = None
     lib.gnss_strerror.restype = ctypes.c_char_p
     lib.gnss_last_error.restype = ctypes.c_char_p
     return lib
@@ -245,6 +264,44 @@ class Context:
         _check(_lib.gnss_stage_times(self.handle, ms, cnt, GNSS_N_STAGES, 1 if reset else 0))
         return {STAGE_NAMES[i]: (ms[i], cnt[i]) for i in range(GNSS_N_STAGES)}
 
+    # -- batches, graphs, autotuning ----------------------------------------
+    def acquire_batch_device(self, reqs, stream=None):
+        arr = _req_array(reqs)
+        _check(_lib.gnss_acquire_batch_device(self.handle, arr, len(reqs), _stream_ptr(stream)))
+
+    def graph(self, reqs):
+        """Captures the batch `reqs` (device-buffer requests) into a HIP graph."""
+        return Graph(self, reqs)
+
+    def autotune(self, reqs, cache_path: str | None = None) -> int:
+        arr = _req_array(reqs)
+        out = ctypes.c_int32(0)
+        _check(_lib.gnss_autotune(self.handle, arr, len(reqs),
+                                  cache_path.encode() if cache_path else None, ctypes.byref(out)))
+        return out.value
+
+    # -- serving --------------------------------------------------------------
+    def submit(self, req: gnss_request) -> int:
+        """Submits a host-buffer request; returns its ticket.  The request's
+        output arrays must stay alive until the ticket is done."""
+        t = ctypes.c_uint64(0)
+        _check(_lib.gnss_submit(self.handle, ctypes.byref(req), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        """(done, info or None)."""
+        done = ctypes.c_int(0)
+        info = gnss_ticket_info()
+        _check(_lib.gnss_poll(self.handle, ctypes.c_uint64(ticket), ctypes.byref(done),
+                              ctypes.byref(info)))
+        return bool(done.value), (info if done.value else None)
+
+    def wait(self, ticket: int, timeout_s: float = -1.0) -> gnss_ticket_info:
+        info = gnss_ticket_info()
+        _check(_lib.gnss_wait(self.handle, ctypes.c_uint64(ticket), float(timeout_s),
+                              ctypes.byref(info)))
+        return info
+
     # -- stage entry points (device pointers as ints) ------------------------
     def gold_codes(self, prns, d_codes: int, stream=None):
         a, p = _prn_array(prns)
@@ -271,3 +328,35 @@ class Context:
         _check(_lib.gnss_peaks(self.handle, d_grid, p, a.size, int(n_dopp), int(N), int(spc),
                                float(doppler_lo), float(doppler_step), d_peaks,
                                _stream_ptr(stream)))
+
+
+def _req_array(reqs):
+    arr = (gnss_request * len(reqs))()
+    for i, r in enumerate(reqs):
+        arr[i] = r
+    return arr
+
+
+class Graph:
+    """gnss_graph: a captured batch replayed with launch()."""
+
+    def __init__(self, ctx: Context, reqs):
+        self._reqs = list(reqs)  # keep PRN arrays alive
+        arr = _req_array(self._reqs)
+        h = ctypes.c_void_p()
+        _check(_lib.gnss_graph_create(ctx.handle, arr, len(self._reqs), ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self, stream=None):
+        _check(_lib.gnss_graph_launch(self.handle, _stream_ptr(stream)))
+
+    def close(self):
+        if self.handle:
+            _lib.gnss_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -2,26 +2,30 @@
 //
 // A context owns one device, one HIP stream (default priority), the
 // device-resident tables built once at creation (carrier LUT, C/A codes, FFT
-// twiddles, the 2048-point code spectra of all 37 PRNs) and a workspace that
-// grows on demand under an HBM budget.  The device keeps every intermediate
+// twiddles, the 2048-point code spectra of all 37 PRNs) and workspaces that
+// grow on demand under an HBM budget.  The device keeps every intermediate
 // of a request (the paper keeps intermediate results on the GPU and batches
 // the whole coherent integration, Sec. 5); a host request crosses the bus
 // once in (samples) and once out (peaks, and the grid if asked for).
+//
+// Every search runs as a batch: the host writes a table of request
+// descriptors and per-stage work-item prefix sums into pinned memory, one
+// copy moves it to the device, and the persistent stage kernels walk it.  A
+// single request is a batch of one; a batch can be captured once into a
+// HIP graph and replayed (gnss_graph_*).
 #include "fft2048.hpp"
 #include "gnss_internal.hpp"
+#include "gnss_runtime.hpp"
 
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
 
-#include <array>
-#include <mutex>
+#include <algorithm>
 #include <new>
-#include <string>
-#include <vector>
 
-namespace {
+namespace gnss_rt {
 
 thread_local std::string t_err;
 
@@ -36,63 +40,29 @@ int set_err(int code, const char *fmt, ...)
     return code;
 }
 
-#define HIP_TRY(expr)                                                                     \
-    do {                                                                                  \
-        hipError_t e_ = (expr);                                                           \
-        if (e_ != hipSuccess)                                                             \
-            return set_err(GNSS_EDEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), \
-                           __FILE__, __LINE__);                                           \
-    } while (0)
-
-struct DevBuf {
-    void *p = nullptr;
-    size_t cap = 0;
-};
-
-}  // namespace
-
-struct gnss_ctx {
-    int device = 0;
-    size_t budget = 0;  // 0: unlimited
-    int precision = GNSS_FP32;
-    float threshold = 2.5f;
-    hipStream_t stream = nullptr;
-    // tables
-    uint32_t *d_lut = nullptr;  // [1024] packed cos16 | sin16 << 16
-    uint8_t *d_codes = nullptr; // [38][1023], row = PRN
-    float2 *d_tw = nullptr;     // twiddles
-    float4 *d_cs = nullptr;     // [38][1024] code spectra, storage order
-    size_t table_bytes = 0;
-    // workspace
-    DevBuf samples, F, G, grid, Q, K, part, peaks;
-    // per-stage timing
-    bool profile = false;
-    std::vector<hipEvent_t> event_pool;
-    std::vector<std::array<hipEvent_t, GNSS_N_STAGES + 1>> pending;
-    double stage_ms[GNSS_N_STAGES] = {0, 0, 0, 0};
-    int64_t stage_n[GNSS_N_STAGES] = {0, 0, 0, 0};
-    std::mutex mu;
-};
-
-namespace {
-
-size_t ws_total(const gnss_ctx *c)
+size_t sample_bytes(int fmt, size_t n)
 {
-    return c->samples.cap + c->F.cap + c->G.cap + c->grid.cap + c->Q.cap + c->K.cap + c->part.cap +
-           c->peaks.cap;
+    if (fmt == GNSS_CPLX_I8) return 2 * n;
+    if (fmt == GNSS_REAL_I8) return n;
+    return (n + 3) / 4;
 }
 
+// ---------------------------------------------------------------------------
+// device memory under the context's HBM budget
+// ---------------------------------------------------------------------------
 int ensure(gnss_ctx *c, DevBuf &b, size_t bytes)
 {
     if (bytes <= b.cap) return GNSS_OK;
-    size_t other = ws_total(c) - b.cap + c->table_bytes;
-    if (c->budget && other + bytes > c->budget)
-        return set_err(GNSS_ENOMEM, "workspace of %zu bytes exceeds the HBM budget (%zu of %zu in use)",
-                       bytes, other, c->budget);
+    std::lock_guard<std::mutex> lk(c->mem_mu);
+    const size_t in_use = c->dev_bytes - b.cap;
+    if (c->budget && in_use + bytes > c->budget)
+        return set_err(GNSS_ENOMEM, "device buffer of %zu bytes exceeds the HBM budget (%zu of %zu in use)",
+                       bytes, in_use, c->budget);
     if (b.p) {
         // the old buffer may still be in use by enqueued work
         (void)hipDeviceSynchronize();
         hipError_t e = hipFree(b.p);
+        c->dev_bytes -= b.cap;
         b.p = nullptr;
         b.cap = 0;
         if (e != hipSuccess) return set_err(GNSS_EDEVICE, "hipFree: %s", hipGetErrorString(e));
@@ -104,17 +74,35 @@ int ensure(gnss_ctx *c, DevBuf &b, size_t bytes)
         return set_err(GNSS_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
     }
     b.cap = bytes;
+    c->dev_bytes += bytes;
     return GNSS_OK;
 }
 
-size_t sample_bytes(int fmt, size_t n)
+void release(gnss_ctx *c, DevBuf &b)
 {
-    if (fmt == GNSS_CPLX_I8) return 2 * n;
-    if (fmt == GNSS_REAL_I8) return n;
-    return (n + 3) / 4;
+    if (!b.p) return;
+    (void)hipFree(b.p);
+    std::lock_guard<std::mutex> lk(c->mem_mu);
+    c->dev_bytes -= b.cap;
+    b.p = nullptr;
+    b.cap = 0;
 }
 
-// Validates a request and derives its plan.
+void release_ws(gnss_ctx *c, Workspace &w)
+{
+    if (w.stage_ev) (void)hipEventSynchronize(w.stage_ev);
+    for (DevBuf *b : {&w.F, &w.G, &w.Q, &w.K, &w.part, &w.grid, &w.meta, &w.samples, &w.peaks})
+        release(c, *b);
+    if (w.h_stage) (void)hipHostFree(w.h_stage);
+    if (w.stage_ev) (void)hipEventDestroy(w.stage_ev);
+    w.h_stage = nullptr;
+    w.h_stage_cap = 0;
+    w.stage_ev = nullptr;
+}
+
+// ---------------------------------------------------------------------------
+// request validation
+// ---------------------------------------------------------------------------
 int make_plan(const gnss_request *r, gnss::Plan &p, bool need_outputs)
 {
     if (!r) return set_err(GNSS_EINVAL, "request is null");
@@ -167,21 +155,135 @@ int make_plan(const gnss_request *r, gnss::Plan &p, bool need_outputs)
     return GNSS_OK;
 }
 
-struct WsSizes {
-    size_t F, G, grid, Q, K, part, peaks;
-};
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+static long long cdiv(long long a, long long b) { return (a + b - 1) / b; }
 
-WsSizes ws_sizes(const gnss::Plan &p)
+// Lays out the requests of a batch: descriptors, prefix sums of work items
+// per stage and workspace sizes.  Device pointers of the request (samples,
+// grid, peaks) are copied; null grids get offsets in the workspace grid.
+void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int corr_pt,
+                 float threshold, BatchHost &B)
 {
-    WsSizes w;
-    w.F = (size_t)p.n_vec() * gnss::kPolyLen * sizeof(int2);
-    w.G = (size_t)p.n_vec() * gnss::kVec * sizeof(float4);
-    w.grid = (size_t)p.grid_elems() * sizeof(float);
-    w.Q = (size_t)p.n_prn * p.N * sizeof(float);
-    w.K = (size_t)p.n_prn * p.N * sizeof(int32_t);
-    w.part = gnss::peak_scratch_part_elems(p) * sizeof(double);
-    w.peaks = (size_t)p.n_prn * sizeof(gnss_peak);
-    return w;
+    B.d.assign(n, gnss::ReqDesc{});
+    B.pre.assign((size_t)gnss::kNumStages * (n + 1), 0);
+    B.grid_off.assign(n, -1);
+    long long tot[gnss::kNumStages] = {0, 0, 0, 0, 0};
+    long long vec = 0, qk = 0, part = 0, grid_int = 0;
+    for (int r = 0; r < n; ++r) {
+        const gnss::Plan &p = plans[r];
+        gnss::ReqDesc &d = B.d[r];
+        d.samples = reqs[r].samples;
+        d.grid = reqs[r].out_grid;
+        d.peaks = reqs[r].out_peaks;
+        d.vec_off = vec;
+        d.qk_off = qk;
+        d.part_off = part;
+        d.fs = (double)p.fs_hz;
+        d.f_if = p.f_if;
+        d.lo = p.lo;
+        d.step = p.step;
+        d.fmt = p.fmt;
+        d.N = p.N;
+        d.spc = p.spc;
+        d.n_dopp = p.n_dopp;
+        d.Tc = p.Tc;
+        d.Nnc = p.Nnc;
+        d.n_prn = p.n_prn;
+        d.n_chunks_box = (int)cdiv(p.N, gnss::kBoxChunk);
+        d.n_items = p.n_dopp * p.spc;
+        d.n_ptiles = (int)cdiv(p.n_prn, corr_pt);
+        d.n_tau_blk = (int)cdiv(p.N, gnss::kPeakThreads);
+        d.threshold = threshold;
+        for (int i = 0; i < gnss::kMaxList; ++i) d.prns[i] = p.prns.v[i];
+        if (!d.grid) {
+            B.grid_off[r] = grid_int;
+            grid_int += p.grid_elems();
+        }
+        const long long cnt[gnss::kNumStages] = {
+            (long long)p.n_dopp * p.Nnc * d.n_chunks_box, p.n_vec(),
+            (long long)d.n_ptiles * cdiv(d.n_items, 8), (long long)p.n_prn * d.n_tau_blk, (long long)p.n_prn};
+        for (int st = 0; st < gnss::kNumStages; ++st) {
+            B.pre[(size_t)st * (n + 1) + r] = tot[st];
+            tot[st] += cnt[st];
+        }
+        vec += p.n_vec();
+        qk += (long long)p.n_prn * p.N;
+        part += (long long)p.n_prn * d.n_tau_blk;
+    }
+    for (int st = 0; st < gnss::kNumStages; ++st) {
+        B.pre[(size_t)st * (n + 1) + n] = tot[st];
+        B.total[st] = tot[st];
+    }
+    B.n = n;
+    B.corr_pt = corr_pt;
+    B.F_bytes = (size_t)vec * gnss::kPolyLen * sizeof(int2);
+    B.G_bytes = (size_t)vec * gnss::kVec * sizeof(float4);
+    B.Q_bytes = (size_t)qk * sizeof(float);
+    B.K_bytes = (size_t)qk * sizeof(int32_t);
+    B.part_bytes = (size_t)part * sizeof(double);
+    B.grid_bytes = (size_t)grid_int * sizeof(float);
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t meta_bytes(int n)
+{
+    return align256(sizeof(gnss::BatchHdr)) + align256((size_t)gnss::kNumStages * (n + 1) * sizeof(long long)) +
+           align256((size_t)n * sizeof(gnss::ReqDesc));
+}
+
+size_t batch_device_bytes(const BatchHost &B)
+{
+    return B.F_bytes + B.G_bytes + B.Q_bytes + B.K_bytes + B.part_bytes + B.grid_bytes + meta_bytes(B.n);
+}
+
+// Allocates the workspace of a laid-out batch, fills in internal grid
+// pointers, writes the metadata into pinned memory and enqueues its copy to
+// the device on stream s.  Returns the kernels' view of the batch in L.
+int stage_batch(gnss_ctx *c, Workspace &w, BatchHost &B, hipStream_t s, gnss::Launch &L)
+{
+    int rc;
+    const size_t mb = meta_bytes(B.n);
+    if ((rc = ensure(c, w.F, std::max<size_t>(B.F_bytes, 1))) || (rc = ensure(c, w.G, std::max<size_t>(B.G_bytes, 1))) ||
+        (rc = ensure(c, w.Q, std::max<size_t>(B.Q_bytes, 1))) || (rc = ensure(c, w.K, std::max<size_t>(B.K_bytes, 1))) ||
+        (rc = ensure(c, w.part, std::max<size_t>(B.part_bytes, 1))) ||
+        (rc = ensure(c, w.grid, std::max<size_t>(B.grid_bytes, 1))) || (rc = ensure(c, w.meta, mb)))
+        return rc;
+    for (int r = 0; r < B.n; ++r)
+        if (B.grid_off[r] >= 0) B.d[r].grid = (float *)w.grid.p + B.grid_off[r];
+    // pinned staging: wait until the previous copy out of it has finished
+    if (w.stage_ev) HIP_TRY(hipEventSynchronize(w.stage_ev));
+    if (w.h_stage_cap < mb) {
+        if (w.h_stage) HIP_TRY(hipHostFree(w.h_stage));
+        w.h_stage = nullptr;
+        w.h_stage_cap = 0;
+        HIP_TRY(hipHostMalloc(&w.h_stage, mb, hipHostMallocDefault));
+        w.h_stage_cap = mb;
+    }
+    if (!w.stage_ev) HIP_TRY(hipEventCreateWithFlags(&w.stage_ev, hipEventDisableTiming));
+    unsigned char *h = (unsigned char *)w.h_stage;
+    memset(h, 0, mb);
+    gnss::BatchHdr hdr{};
+    hdr.n_req = B.n;
+    hdr.corr_pt = B.corr_pt;
+    for (int st = 0; st < gnss::kNumStages; ++st) hdr.total[st] = B.total[st];
+    const size_t off_pre = align256(sizeof(gnss::BatchHdr));
+    const size_t off_desc = off_pre + align256((size_t)gnss::kNumStages * (B.n + 1) * sizeof(long long));
+    memcpy(h, &hdr, sizeof hdr);
+    memcpy(h + off_pre, B.pre.data(), B.pre.size() * sizeof(long long));
+    memcpy(h + off_desc, B.d.data(), (size_t)B.n * sizeof(gnss::ReqDesc));
+    HIP_TRY(hipMemcpyAsync(w.meta.p, h, mb, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(w.stage_ev, s));
+    unsigned char *dm = (unsigned char *)w.meta.p;
+    L.hdr = (gnss::BatchHdr *)dm;
+    L.pre = (const long long *)(dm + off_pre);
+    L.reqs = (const gnss::ReqDesc *)(dm + off_desc);
+    L.n_req = B.n;
+    L.corr_pt = B.corr_pt;
+    for (int st = 0; st < gnss::kNumStages; ++st) L.total[st] = B.total[st];
+    return GNSS_OK;
 }
 
 int take_event(gnss_ctx *c, hipEvent_t *ev)
@@ -212,71 +314,74 @@ int harvest_events(gnss_ctx *c)
     return GNSS_OK;
 }
 
-// Enqueues the whole search for a validated plan on stream s.
-int run_device(gnss_ctx *c, const gnss::Plan &p, const void *d_samples, float *d_grid_out,
-               gnss_peak *d_peaks, hipStream_t s)
+// Enqueues a staged batch on stream s, with stage events when profiling.
+int launch(gnss_ctx *c, Workspace &w, const gnss::Launch &L, hipStream_t s, bool allow_profile)
 {
-    WsSizes w = ws_sizes(p);
     int rc;
-    if ((rc = ensure(c, c->F, w.F)) || (rc = ensure(c, c->G, w.G)) || (rc = ensure(c, c->Q, w.Q)) ||
-        (rc = ensure(c, c->K, w.K)) || (rc = ensure(c, c->part, w.part)))
-        return rc;
-    float *grid = d_grid_out;
-    if (!grid) {
-        if ((rc = ensure(c, c->grid, w.grid))) return rc;
-        grid = (float *)c->grid.p;
-    }
     std::array<hipEvent_t, GNSS_N_STAGES + 1> ev{};
-    if (c->profile) {
+    const bool prof = allow_profile && c->profile;
+    if (prof) {
         if (c->pending.size() >= 4096 && (rc = harvest_events(c))) return rc;
         for (auto &e : ev)
             if ((rc = take_event(c, &e))) return rc;
     }
-    auto mark = [&](int i) -> hipError_t { return c->profile ? hipEventRecord(ev[i], s) : hipSuccess; };
-    HIP_TRY(mark(0));
-    HIP_TRY(gnss::launch_wipe_fold_box(d_samples, p, c->d_lut, (int2 *)c->F.p, s));
-    HIP_TRY(mark(1));
-    HIP_TRY(gnss::launch_fft_poly((const int2 *)c->F.p, c->d_tw, (float4 *)c->G.p, p.n_vec(), s));
-    HIP_TRY(mark(2));
-    HIP_TRY(gnss::launch_corr((const float4 *)c->G.p, c->d_cs, c->d_tw, grid, p, s));
-    HIP_TRY(mark(3));
-    HIP_TRY(gnss::launch_peaks(grid, p, c->threshold, (float *)c->Q.p, (int32_t *)c->K.p,
-                               (double *)c->part.p, d_peaks, s));
-    HIP_TRY(mark(4));
-    if (c->profile) c->pending.push_back(ev);
+    HIP_TRY(gnss::launch_batch(L, c->d_lut, c->d_tw, c->d_cs, (int2 *)w.F.p, (float4 *)w.G.p, (float *)w.Q.p,
+                               (int32_t *)w.K.p, (double *)w.part.p, c->n_cu, s, prof ? ev.data() : nullptr));
+    if (prof) c->pending.push_back(ev);
     return GNSS_OK;
 }
 
+int plan_all(const gnss_request *reqs, int n, std::vector<gnss::Plan> &plans)
+{
+    if (!reqs || n < 1) return set_err(GNSS_EINVAL, "need at least one request");
+    plans.resize(n);
+    for (int i = 0; i < n; ++i) {
+        int rc = make_plan(&reqs[i], plans[i], true);
+        if (rc) {
+            std::string m = t_err;
+            return set_err(rc, "request %d: %s", i, m.c_str());
+        }
+    }
+    return GNSS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
 int ctx_init_tables(gnss_ctx *c)
 {
     const size_t lut_b = 1024 * sizeof(uint32_t);
     const size_t codes_b = (gnss::kMaxPrn + 1) * gnss::kCodeLen;
     const size_t tw_b = gnss::kTwElems * sizeof(float2);
     const size_t cs_b = (size_t)(gnss::kMaxPrn + 1) * gnss::kVec * sizeof(float4);
-    c->table_bytes = lut_b + codes_b + tw_b + cs_b;
-    if (c->budget && c->table_bytes > c->budget)
-        return set_err(GNSS_ENOMEM, "HBM budget %zu below the %zu bytes of tables", c->budget, c->table_bytes);
+    const size_t table_bytes = lut_b + codes_b + tw_b + cs_b;
+    if (c->budget && table_bytes > c->budget)
+        return set_err(GNSS_ENOMEM, "HBM budget %zu below the %zu bytes of tables", c->budget, table_bytes);
     HIP_TRY(hipMalloc(&c->d_lut, lut_b));
     HIP_TRY(hipMalloc(&c->d_codes, codes_b));
     HIP_TRY(hipMalloc(&c->d_tw, tw_b));
     HIP_TRY(hipMalloc(&c->d_cs, cs_b));
+    c->dev_bytes += table_bytes;
+    c->table_bytes = table_bytes;
     HIP_TRY(gnss::launch_lut(c->d_lut, nullptr, nullptr, c->stream));
     HIP_TRY(gnss::launch_gold_codes(c->d_codes, c->stream));
     HIP_TRY(gnss::launch_twiddles(c->d_tw, c->stream));
     HIP_TRY(gnss::launch_code_spectra(c->d_codes, c->d_tw, c->d_cs, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, c->device));
+    c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
     return GNSS_OK;
 }
 
 void ctx_free(gnss_ctx *c)
 {
     if (!c) return;
+    server_stop(c);
     int cur = -1;
-    bool switched = hipGetDevice(&cur) == hipSuccess && cur != c->device &&
-                    hipSetDevice(c->device) == hipSuccess;
+    bool switched = hipGetDevice(&cur) == hipSuccess && cur != c->device && hipSetDevice(c->device) == hipSuccess;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    for (DevBuf *b : {&c->samples, &c->F, &c->G, &c->grid, &c->Q, &c->K, &c->part, &c->peaks})
-        if (b->p) (void)hipFree(b->p);
+    release_ws(c, c->ws);
     for (auto &grp : c->pending)
         for (hipEvent_t e : grp) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
@@ -289,36 +394,33 @@ void ctx_free(gnss_ctx *c)
     delete c;
 }
 
-// Makes ctx->device current for the calling thread, remembering the previous one.
-struct DeviceGuard {
-    int prev = -1;
-    bool changed = false;
-    int rc = GNSS_OK;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess) {
-            rc = set_err(GNSS_EDEVICE, "hipGetDevice failed");
+DeviceGuard::DeviceGuard(int dev)
+{
+    if (hipGetDevice(&prev) != hipSuccess) {
+        rc = set_err(GNSS_EDEVICE, "hipGetDevice failed");
+        return;
+    }
+    if (prev != dev) {
+        hipError_t e = hipSetDevice(dev);
+        if (e != hipSuccess) {
+            rc = set_err(GNSS_EDEVICE, "hipSetDevice(%d): %s", dev, hipGetErrorString(e));
             return;
         }
-        if (prev != dev) {
-            hipError_t e = hipSetDevice(dev);
-            if (e != hipSuccess) {
-                rc = set_err(GNSS_EDEVICE, "hipSetDevice(%d): %s", dev, hipGetErrorString(e));
-                return;
-            }
-            changed = true;
-        }
+        changed = true;
     }
-    ~DeviceGuard()
-    {
-        if (changed) (void)hipSetDevice(prev);
-    }
-};
+}
 
-std::mutex g_default_mu;
-gnss_ctx *g_default = nullptr;
+DeviceGuard::~DeviceGuard()
+{
+    if (changed) (void)hipSetDevice(prev);
+}
 
-}  // namespace
+static std::mutex g_default_mu;
+static gnss_ctx *g_default = nullptr;
+
+}  // namespace gnss_rt
+
+using namespace gnss_rt;
 
 extern "C" {
 
@@ -400,6 +502,17 @@ int gnss_ctx_set(gnss_ctx *ctx, const char *key, double value)
         ctx->budget = (size_t)value;
         return GNSS_OK;
     }
+    if (!strcmp(key, "corr_ptile")) {
+        if (value != 0.0 && !gnss::corr_ptile_valid((int)value))
+            return set_err(GNSS_EINVAL, "corr_ptile must be 2, 4 or 0 (tuned)");
+        ctx->corr_pt_forced = (int)value;
+        return GNSS_OK;
+    }
+    if (!strcmp(key, "max_slots")) {
+        if (!(value >= 1.0) || value > 4096.0) return set_err(GNSS_EINVAL, "max_slots outside [1, 4096]");
+        ctx->max_slots = (int)value;
+        return GNSS_OK;
+    }
     return set_err(GNSS_EINVAL, "unknown option '%s'", key);
 }
 
@@ -428,22 +541,34 @@ int gnss_workspace_bytes(const gnss_request *req, size_t *bytes)
     gnss::Plan p;
     int rc = make_plan(req, p, false);
     if (rc) return rc;
-    WsSizes w = ws_sizes(p);
-    *bytes = w.F + w.G + w.grid + w.Q + w.K + w.part + w.peaks + sample_bytes(p.fmt, (size_t)p.n_samples);
+    BatchHost B;
+    gnss_request r = *req;
+    r.out_grid = nullptr;
+    build_batch(&p, &r, 1, 4, 2.5f, B);
+    *bytes = batch_device_bytes(B) + sample_bytes(p.fmt, (size_t)p.n_samples) + (size_t)p.n_prn * sizeof(gnss_peak);
     return GNSS_OK;
 }
 
-int gnss_acquire_device(gnss_ctx *ctx, const gnss_request *req, void *stream)
+int gnss_acquire_batch_device(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, void *stream)
 {
     if (!ctx) return set_err(GNSS_EINVAL, "ctx is null");
-    gnss::Plan p;
-    int rc = make_plan(req, p, true);
+    std::vector<gnss::Plan> plans;
+    int rc = plan_all(reqs, n_req, plans);
     if (rc) return rc;
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
     if (g.rc) return g.rc;
     hipStream_t s = (hipStream_t)stream;
-    return run_device(ctx, p, req->samples, req->out_grid, req->out_peaks, s);
+    BatchHost B;
+    build_batch(plans.data(), reqs, n_req, corr_ptile_for(ctx, plans.data(), n_req), ctx->threshold, B);
+    gnss::Launch L;
+    if ((rc = stage_batch(ctx, ctx->ws, B, s, L))) return rc;
+    return launch(ctx, ctx->ws, L, s, true);
+}
+
+int gnss_acquire_device(gnss_ctx *ctx, const gnss_request *req, void *stream)
+{
+    return gnss_acquire_batch_device(ctx, req, 1, stream);
 }
 
 int gnss_acquire(const void *samples, int32_t fmt, size_t n, double fs, double f_if,
@@ -478,22 +603,109 @@ int gnss_acquire(const void *samples, int32_t fmt, size_t n, double fs, double f
     std::lock_guard<std::mutex> lk(c->mu);
     DeviceGuard g(c->device);
     if (g.rc) return g.rc;
-    WsSizes w = ws_sizes(p);
+    Workspace &w = c->ws;
     const size_t sb = sample_bytes(fmt, n);
-    if ((rc = ensure(c, c->samples, sb)) || (rc = ensure(c, c->peaks, w.peaks)) ||
-        (rc = ensure(c, c->grid, w.grid)))
-        return rc;
-    HIP_TRY(hipMemcpyAsync(c->samples.p, samples, sb, hipMemcpyHostToDevice, c->stream));
-    rc = run_device(c, p, c->samples.p, (float *)c->grid.p, (gnss_peak *)c->peaks.p, c->stream);
-    if (rc) {
+    const size_t pb = (size_t)n_prn * sizeof(gnss_peak);
+    if ((rc = ensure(c, w.samples, sb)) || (rc = ensure(c, w.peaks, pb))) return rc;
+    HIP_TRY(hipMemcpyAsync(w.samples.p, samples, sb, hipMemcpyHostToDevice, c->stream));
+    gnss_request dr = r;
+    dr.samples = w.samples.p;
+    dr.out_grid = nullptr;  // workspace grid, copied out below
+    dr.out_peaks = (gnss_peak *)w.peaks.p;
+    BatchHost B;
+    build_batch(&p, &dr, 1, corr_ptile_for(c, &p, 1), c->threshold, B);
+    gnss::Launch L;
+    if ((rc = stage_batch(c, w, B, c->stream, L)) || (rc = launch(c, w, L, c->stream, true))) {
         (void)hipStreamSynchronize(c->stream);
         return rc;
     }
     if (out_grid)
-        HIP_TRY(hipMemcpyAsync(out_grid, c->grid.p, w.grid, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipMemcpyAsync(out_peaks, c->peaks.p, w.peaks, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipMemcpyAsync(out_grid, B.d[0].grid, (size_t)p.grid_elems() * sizeof(float), hipMemcpyDeviceToHost,
+                               c->stream));
+    HIP_TRY(hipMemcpyAsync(out_peaks, w.peaks.p, pb, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     return GNSS_OK;
+}
+
+// ---- captured batches ----------------------------------------------------
+
+int gnss_graph_create(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, gnss_graph **out)
+{
+    if (!ctx || !out) return set_err(GNSS_EINVAL, "null argument");
+    *out = nullptr;
+    std::vector<gnss::Plan> plans;
+    int rc = plan_all(reqs, n_req, plans);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    if (g.rc) return g.rc;
+    gnss_graph *gr = new (std::nothrow) gnss_graph();
+    if (!gr) return set_err(GNSS_ENOMEM, "host allocation failed");
+    gr->ctx = ctx;
+    BatchHost B;
+    build_batch(plans.data(), reqs, n_req, corr_ptile_for(ctx, plans.data(), n_req), ctx->threshold, B);
+    gr->corr_pt = B.corr_pt;
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete gr;
+        return set_err(GNSS_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+    }
+    gnss::Launch L;
+    // allocate and fill everything before capture (no allocation inside it)
+    rc = stage_batch(ctx, gr->ws, B, cs, L);
+    if (!rc) {
+        e = hipStreamSynchronize(cs);
+        if (e != hipSuccess) rc = set_err(GNSS_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    }
+    if (!rc) {
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) rc = set_err(GNSS_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+    }
+    if (!rc) {
+        // the metadata copy is part of the graph (pinned source, contents fixed)
+        const size_t mb = meta_bytes(B.n);
+        e = hipMemcpyAsync(gr->ws.meta.p, gr->ws.h_stage, mb, hipMemcpyHostToDevice, cs);
+        int rc2 = e == hipSuccess ? launch(ctx, gr->ws, L, cs, false)
+                                  : set_err(GNSS_EDEVICE, "hipMemcpyAsync: %s", hipGetErrorString(e));
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(cs, &graph);
+        if (rc2) rc = rc2;
+        else if (e != hipSuccess) rc = set_err(GNSS_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        if (!rc) {
+            e = hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) rc = set_err(GNSS_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        }
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+    (void)hipStreamDestroy(cs);
+    if (rc) {
+        if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+        release_ws(ctx, gr->ws);
+        delete gr;
+        return rc;
+    }
+    *out = gr;
+    return GNSS_OK;
+}
+
+int gnss_graph_launch(gnss_graph *graph, void *stream)
+{
+    if (!graph || !graph->exec) return set_err(GNSS_EINVAL, "graph is null");
+    DeviceGuard g(graph->ctx->device);
+    if (g.rc) return g.rc;
+    HIP_TRY(hipGraphLaunch(graph->exec, (hipStream_t)stream));
+    return GNSS_OK;
+}
+
+void gnss_graph_destroy(gnss_graph *graph)
+{
+    if (!graph) return;
+    DeviceGuard g(graph->ctx->device);
+    (void)hipDeviceSynchronize();
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    release_ws(graph->ctx, graph->ws);
+    delete graph;
 }
 
 // ---- stage entry points -------------------------------------------------
@@ -529,8 +741,7 @@ int gnss_code_replica(gnss_ctx *ctx, const int32_t *prn_list, int32_t n_prn, dou
     if (n == 0) return GNSS_OK;
     DeviceGuard g(ctx->device);
     if (g.rc) return g.rc;
-    hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(gnss::launch_code_replica(ctx->d_codes, pl, n_prn, (int64_t)fs, (int64_t)n, d_out, s));
+    HIP_TRY(gnss::launch_code_replica(ctx->d_codes, pl, n_prn, (int64_t)fs, (int64_t)n, d_out, (hipStream_t)stream));
     return GNSS_OK;
 }
 
@@ -539,8 +750,7 @@ int gnss_nco_lut(gnss_ctx *ctx, int16_t *d_cos, int16_t *d_sin, void *stream)
     if (!ctx || !d_cos || !d_sin) return set_err(GNSS_EINVAL, "null argument");
     DeviceGuard g(ctx->device);
     if (g.rc) return g.rc;
-    hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(gnss::launch_lut(nullptr, d_cos, d_sin, s));
+    HIP_TRY(gnss::launch_lut(nullptr, d_cos, d_sin, (hipStream_t)stream));
     return GNSS_OK;
 }
 
@@ -552,8 +762,7 @@ int gnss_wipe_fold(gnss_ctx *ctx, const gnss_request *req, int32_t *d_out, void 
     if (rc) return rc;
     DeviceGuard g(ctx->device);
     if (g.rc) return g.rc;
-    hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(gnss::launch_wipe_fold(req->samples, p, ctx->d_lut, d_out, s));
+    HIP_TRY(gnss::launch_wipe_fold(req->samples, p, ctx->d_lut, d_out, (hipStream_t)stream));
     return GNSS_OK;
 }
 
@@ -565,8 +774,8 @@ int gnss_fft2048(gnss_ctx *ctx, const float *d_in, float *d_out, int32_t batch, 
     if (d_in == d_out) return set_err(GNSS_EINVAL, "in-place transform is not supported");
     DeviceGuard g(ctx->device);
     if (g.rc) return g.rc;
-    hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(gnss::launch_fft_test((const float2 *)d_in, (float2 *)d_out, batch, inverse ? 1 : 0, ctx->d_tw, s));
+    HIP_TRY(gnss::launch_fft_test((const float2 *)d_in, (float2 *)d_out, batch, inverse ? 1 : 0, ctx->d_tw,
+                                  (hipStream_t)stream));
     return GNSS_OK;
 }
 
@@ -577,25 +786,41 @@ int gnss_peaks(gnss_ctx *ctx, const float *d_grid, const int32_t *prn_list, int3
     if (n_prn < 1 || n_prn > gnss::kMaxList || n_dopp < 1 || N < 3 || spc < 0)
         return set_err(GNSS_EINVAL, "bad grid shape");
     if (!isfinite(doppler_lo) || !isfinite(doppler_step)) return set_err(GNSS_EINVAL, "bad Doppler grid");
-    gnss::Plan p{};
-    p.n_prn = n_prn;
-    p.n_dopp = n_dopp;
-    p.N = N;
-    p.spc = spc;
-    p.lo = doppler_lo;
-    p.step = doppler_step;
-    for (int i = 0; i < gnss::kMaxList; ++i) p.prns.v[i] = i < n_prn ? prn_list[i] : 0;
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
     if (g.rc) return g.rc;
-    WsSizes w = ws_sizes(p);
-    int rc;
-    if ((rc = ensure(ctx, ctx->Q, w.Q)) || (rc = ensure(ctx, ctx->K, w.K)) || (rc = ensure(ctx, ctx->part, w.part)))
-        return rc;
-    hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(gnss::launch_peaks(d_grid, p, ctx->threshold, (float *)ctx->Q.p, (int32_t *)ctx->K.p,
-                               (double *)ctx->part.p, d_peaks, s));
-    return GNSS_OK;
+    // a batch of one request that runs only the detection stages
+    BatchHost B;
+    B.n = 1;
+    B.corr_pt = 4;
+    B.d.assign(1, gnss::ReqDesc{});
+    gnss::ReqDesc &d = B.d[0];
+    d.grid = (float *)d_grid;
+    d.peaks = d_peaks;
+    d.lo = doppler_lo;
+    d.step = doppler_step;
+    d.N = N;
+    d.spc = spc;
+    d.n_dopp = n_dopp;
+    d.n_prn = n_prn;
+    d.n_tau_blk = (N + gnss::kPeakThreads - 1) / gnss::kPeakThreads;
+    d.threshold = ctx->threshold;
+    for (int i = 0; i < gnss::kMaxList; ++i) d.prns[i] = i < n_prn ? prn_list[i] : 0;
+    B.grid_off.assign(1, -1);
+    const long long cnt[gnss::kNumStages] = {0, 0, 0, (long long)n_prn * d.n_tau_blk, n_prn};
+    B.pre.assign((size_t)gnss::kNumStages * 2, 0);
+    for (int st = 0; st < gnss::kNumStages; ++st) {
+        B.pre[(size_t)st * 2 + 1] = cnt[st];
+        B.total[st] = cnt[st];
+    }
+    B.F_bytes = B.G_bytes = B.grid_bytes = 0;
+    B.Q_bytes = (size_t)n_prn * N * sizeof(float);
+    B.K_bytes = (size_t)n_prn * N * sizeof(int32_t);
+    B.part_bytes = (size_t)n_prn * d.n_tau_blk * sizeof(double);
+    gnss::Launch L;
+    int rc = stage_batch(ctx, ctx->ws, B, (hipStream_t)stream, L);
+    if (rc) return rc;
+    return launch(ctx, ctx->ws, L, (hipStream_t)stream, false);
 }
 
 }  // extern "C"

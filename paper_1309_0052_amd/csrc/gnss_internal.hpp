@@ -46,15 +46,60 @@ hipError_t launch_twiddles(float2 *d_tw, hipStream_t s);
 hipError_t launch_code_spectra(const uint8_t *d_codes, const float2 *d_tw, float4 *d_cs,
                                hipStream_t s);
 
-// hot path
+// ---------------------------------------------------------------------------
+// batched hot path: every stage kernel is persistent and walks a device-
+// resident table of requests (a single request is a batch of one)
+// ---------------------------------------------------------------------------
+enum Stage { kStBox = 0, kStVec, kStCorr, kStColmax, kStPeak, kNumStages };
+constexpr int kXcds = 8;
+
+// One request as the kernels see it (device memory).
+struct ReqDesc {
+    const void *samples;
+    float *grid;          // [n_prn][n_dopp][N]
+    gnss_peak *peaks;     // [n_prn]
+    long long vec_off;    // first polyphase vector of the request in F and G
+    long long qk_off;     // offset of the request in Q and K (n_prn * N)
+    long long part_off;   // offset in the partial sums (n_prn * n_tau_blk)
+    double fs, f_if, lo, step;
+    int fmt, N, spc, n_dopp, Tc, Nnc, n_prn;
+    int n_chunks_box;     // 2048-sample chunks per (Doppler, block)
+    int n_items;          // (Doppler, phase) items = n_dopp * spc
+    int n_ptiles;         // PRN tiles of the correlation kernel
+    int n_tau_blk;        // 256-lag blocks of the detection kernels
+    float threshold;
+    int prns[kMaxList];
+};
+
+// Batch header (device memory): request count, work totals per stage and the
+// dynamic work counters (zeroed by k_reset at the start of every batch).
+struct BatchHdr {
+    int n_req;
+    int corr_pt;
+    long long total[kNumStages];
+    unsigned int counter[kNumStages * kXcds];
+};
+
+struct Launch {
+    const ReqDesc *reqs;
+    BatchHdr *hdr;
+    const long long *pre;  // [kNumStages][n_req + 1] work-item prefix sums
+    int n_req;
+    long long total[kNumStages];  // host copy (grid sizing)
+    int corr_pt;                  // PRN tile of the correlation kernel (2 or 4)
+};
+
+hipError_t launch_batch(const Launch &L, const uint32_t *d_lut, const float2 *d_tw,
+                        const float4 *d_cs, int2 *d_F, float4 *d_G, float *d_Q, int32_t *d_K,
+                        double *d_part, int n_cu, hipStream_t s, hipEvent_t *marks);
+int corr_ptile_valid(int pt);
+constexpr int kBoxChunk = 2048;
+constexpr int kPeakThreads = 256;
+
+// standalone wipe + fold (stage entry point)
 hipError_t launch_wipe_fold(const void *d_samples, const Plan &p, const uint32_t *d_lut,
                             int32_t *d_out /*[n_dopp][Nnc][N][2]*/, hipStream_t s);
-hipError_t launch_wipe_fold_box(const void *d_samples, const Plan &p, const uint32_t *d_lut,
-                                int2 *d_F, hipStream_t s);
-hipError_t launch_fft_poly(const int2 *d_F, const float2 *d_tw, float4 *d_G, int64_t n_vec,
-                           hipStream_t s);
-hipError_t launch_corr(const float4 *d_G, const float4 *d_cs, const float2 *d_tw, float *d_grid,
-                       const Plan &p, hipStream_t s);
+// detection on a caller's grid (stage entry point)
 hipError_t launch_peaks(const float *d_grid, const Plan &p, float threshold, float *d_Q,
                         int32_t *d_K, double *d_part, gnss_peak *d_peaks, hipStream_t s);
 size_t peak_scratch_part_elems(const Plan &p);

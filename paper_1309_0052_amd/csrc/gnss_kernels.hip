@@ -210,17 +210,17 @@ hipError_t launch_code_spectra(const uint8_t *d_codes, const float2 *d_tw, float
 // ===========================================================================
 struct WipeArgs {
     int fmt;
-    int N, spc, Tc, Nnc;
+    int N, Tc;
     double fs, f_if, lo, step;
 };
 
 // D_k = (uint32)(int64) llround((f_if + (lo + k*step)) * 2^32 / fs), without
 // contraction so that it rounds exactly as written.
-__device__ __forceinline__ uint32_t nco_step(const WipeArgs &a, int k)
+__device__ __forceinline__ uint32_t nco_step(double fs, double f_if, double lo, double step, int k)
 {
-    double fk = __dadd_rn(a.lo, __dmul_rn((double)k, a.step));
-    double f = __dadd_rn(a.f_if, fk);
-    double x = __ddiv_rn(__dmul_rn(f, 4294967296.0), a.fs);
+    double fk = __dadd_rn(lo, __dmul_rn((double)k, step));
+    double f = __dadd_rn(f_if, fk);
+    double x = __ddiv_rn(__dmul_rn(f, 4294967296.0), fs);
     return (uint32_t)(long long)llround(x);
 }
 
@@ -245,14 +245,14 @@ __device__ __forceinline__ void load_sample(const void *samples, int fmt, long l
 
 // y[n] = x[n] * (cosL - j sinL)[phase(n) >> 22], summed over the Tc
 // milliseconds of coherent block b at in-block offset m.
-__device__ __forceinline__ int2 wipe_fold_one(const void *samples, const WipeArgs &a,
+__device__ __forceinline__ int2 wipe_fold_one(const void *samples, int fmt, int N, int Tc,
                                               const uint32_t *lut, uint32_t D, int b, int m)
 {
     int yr = 0, yi = 0;
-    for (int c = 0; c < a.Tc; ++c) {
-        long long ng = (long long)(b * a.Tc + c) * a.N + m;
+    for (int c = 0; c < Tc; ++c) {
+        long long ng = (long long)(b * Tc + c) * N + m;
         int xr, xi;
-        load_sample(samples, a.fmt, ng, xr, xi);
+        load_sample(samples, fmt, ng, xr, xi);
         uint32_t ph = (uint32_t)(unsigned long long)ng * D;
         uint32_t e = lut[ph >> 22];
         int cs = (int)(int16_t)(e & 0xFFFFu), sn = (int)(int16_t)(e >> 16);
@@ -264,171 +264,203 @@ __device__ __forceinline__ int2 wipe_fold_one(const void *samples, const WipeArg
 
 // Standalone wipe + fold (stage entry): out[((k*Nnc + b)*N + m)*2 + {0,1}].
 __global__ __launch_bounds__(256) void k_wipe_fold(const void *samples, const uint32_t *lut,
-                                                   WipeArgs a, int2 *out)
+                                                   WipeArgs a, int Nnc, int2 *out)
 {
     __shared__ uint32_t s_lut[1024];
     for (int i = threadIdx.x; i < 1024; i += 256) s_lut[i] = lut[i];
-    const int k = blockIdx.x / a.Nnc, b = blockIdx.x % a.Nnc;
-    const uint32_t D = nco_step(a, k);
+    const int k = blockIdx.x / Nnc, b = blockIdx.x % Nnc;
+    const uint32_t D = nco_step(a.fs, a.f_if, a.lo, a.step, k);
     __syncthreads();
     int2 *dst = out + (long long)blockIdx.x * a.N;
-    for (int m = threadIdx.x; m < a.N; m += 256) dst[m] = wipe_fold_one(samples, a, s_lut, D, b, m);
+    for (int m = threadIdx.x; m < a.N; m += 256)
+        dst[m] = wipe_fold_one(samples, a.fmt, a.N, a.Tc, s_lut, D, b, m);
 }
 
 hipError_t launch_wipe_fold(const void *d_samples, const Plan &p, const uint32_t *d_lut,
                             int32_t *d_out, hipStream_t s)
 {
-    WipeArgs a{p.fmt, p.N, p.spc, p.Tc, p.Nnc, (double)p.fs_hz, p.f_if, p.lo, p.step};
+    WipeArgs a{p.fmt, p.N, p.Tc, (double)p.fs_hz, p.f_if, p.lo, p.step};
     hipLaunchKernelGGL(k_wipe_fold, dim3(p.n_dopp * p.Nnc), dim3(256), 0, s, d_samples, d_lut, a,
-                       (int2 *)d_out);
+                       p.Nnc, (int2 *)d_out);
     return hipGetLastError();
 }
 
-// Hot-path stage A1: wipe + fold, then the one-chip boxcar
+// ===========================================================================
+// batch plumbing
+// ===========================================================================
+// Request owning work item `it` of a stage: the last r with pre[r] <= it.
+__device__ __forceinline__ int find_req(const long long *pre, int n_req, long long it)
+{
+    int lo = 0, hi = n_req - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= it) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void k_reset(BatchHdr *h)
+{
+    int i = threadIdx.x;
+    if (i < kNumStages * kXcds) h->counter[i] = 0u;
+}
+
+// Dynamic work distribution.  Workgroups are dealt round-robin to the 8 XCDs;
+// a stage's items are split into 8 contiguous ranges, one per XCD, and each
+// workgroup takes the next item of its own XCD's range from that XCD's
+// counter, so items that share data (consecutive ids) run on one XCD and
+// share its L2.  When its range is exhausted a workgroup takes items from the
+// other ranges.  Returns -1 when every range is exhausted.  Called by every
+// thread of the workgroup.
+__device__ __forceinline__ long long next_item(BatchHdr *h, int stage, long long total, long long *s_item)
+{
+    const long long per = (total + kXcds - 1) / kXcds;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long found = -1;
+        const int home = blockIdx.x % kXcds;
+        for (int t = 0; t < kXcds; ++t) {
+            const int x = (home + t) % kXcds;
+            const long long lo = (long long)x * per;
+            const long long hi = min(total, lo + per);
+            if (lo >= hi) continue;
+            const unsigned int got = atomicAdd(&h->counter[stage * kXcds + x], 1u);
+            if (lo + (long long)got < hi) {
+                found = lo + (long long)got;
+                break;
+            }
+        }
+        *s_item = found;
+    }
+    __syncthreads();
+    return *s_item;
+}
+
+// ===========================================================================
+// stage A1: wipe + fold, then the one-chip boxcar
 // F[n] = sum_{t<spc} f[(n+t) mod N], written split by phase:
-// Fout[k][b][s][m] = F[spc m + s] (m < 1023), Fout[..][1023] = 0.  Each
-// workgroup covers a chunk of kBoxChunk outputs of one (Doppler, block) and
-// wipes the spc - 1 samples past it as a halo.  All integer, exact.
-constexpr int kBoxChunk = 2048;
+// F[vec(k, b, s)][m] = F[spc m + s] (m < 1023), [..][1023] = 0.  Each work item
+// covers kBoxChunk outputs of one (request, Doppler, block) and wipes the
+// spc - 1 samples past it as a halo.  All integer, exact.
+// ===========================================================================
 constexpr int kBoxRun = 8;
 __device__ __forceinline__ int bpad(int i) { return i + (i >> 3); }  // bank-conflict padding
 
-__global__ __launch_bounds__(256) void k_wipe_fold_box(const void *samples, const uint32_t *lut,
-                                                       WipeArgs a, int2 *Fout, int n_chunks)
+__global__ __launch_bounds__(256) void k_box(const ReqDesc *R, BatchHdr *H, const long long *pre,
+                                             const uint32_t *lut, int2 *F)
 {
     __shared__ int2 s_f[(kBoxChunk + kMaxSpc) + (kBoxChunk + kMaxSpc) / 8 + 8];
     __shared__ uint32_t s_lut[1024];
+    __shared__ long long s_item;
     for (int i = threadIdx.x; i < 1024; i += 256) s_lut[i] = lut[i];
-    const int chunk = blockIdx.x % n_chunks, kb = blockIdx.x / n_chunks;
-    const int k = kb / a.Nnc, b = kb % a.Nnc;
-    const uint32_t D = nco_step(a, k);
-    const int N = a.N, spc = a.spc;
-    const int n0 = chunk * kBoxChunk;
-    const int cnt = min(kBoxChunk, N - n0);
-    const int len = cnt + spc - 1;
-    __syncthreads();
-    for (int i = threadIdx.x; i < len; i += 256) {
-        int n = n0 + i;
-        if (n >= N) n -= N;
-        s_f[bpad(i)] = wipe_fold_one(samples, a, s_lut, D, b, n);
-    }
-    __syncthreads();
-    int2 *dst = Fout + (long long)kb * spc * kPolyLen;
-    const int n_runs = (cnt + kBoxRun - 1) / kBoxRun;
-    for (int r = threadIdx.x; r < n_runs; r += 256) {
-        const int i0 = r * kBoxRun;
-        int sx = 0, sy = 0;
-        for (int t = 0; t < spc; ++t) {
-            int2 v = s_f[bpad(i0 + t)];
-            sx += v.x;
-            sy += v.y;
+    const int n_req = H->n_req;
+    const long long total = H->total[kStBox];
+    const long long *pst = pre + (long long)kStBox * (n_req + 1);
+    for (;;) {
+        const long long it = next_item(H, kStBox, total, &s_item);
+        if (it < 0) break;
+        const int r = find_req(pst, n_req, it);
+        const ReqDesc &d = R[r];
+        const long long local = it - pst[r];
+        const int chunk = (int)(local % d.n_chunks_box);
+        const int kb = (int)(local / d.n_chunks_box);
+        const int k = kb / d.Nnc, b = kb % d.Nnc;
+        const int N = d.N, spc = d.spc;
+        const uint32_t D = nco_step(d.fs, d.f_if, d.lo, d.step, k);
+        const int n0 = chunk * kBoxChunk;
+        const int cnt = min(kBoxChunk, N - n0);
+        const int len = cnt + spc - 1;
+        for (int i = threadIdx.x; i < len; i += 256) {
+            int n = n0 + i;
+            if (n >= N) n -= N;
+            s_f[bpad(i)] = wipe_fold_one(d.samples, d.fmt, N, d.Tc, s_lut, D, b, n);
         }
-        const int n = n0 + i0;
-        int m = n / spc, s = n - m * spc;
+        __syncthreads();
+        int2 *dst = F + (d.vec_off + (long long)kb * spc) * kPolyLen;
+        const int n_runs = (cnt + kBoxRun - 1) / kBoxRun;
+        for (int rr = threadIdx.x; rr < n_runs; rr += 256) {
+            const int i0 = rr * kBoxRun;
+            int sx = 0, sy = 0;
+            for (int t = 0; t < spc; ++t) {
+                int2 v = s_f[bpad(i0 + t)];
+                sx += v.x;
+                sy += v.y;
+            }
+            const int n = n0 + i0;
+            int m = n / spc, s = n - m * spc;
 #pragma unroll
-        for (int j = 0; j < kBoxRun; ++j) {
-            const int i = i0 + j;
-            if (i >= cnt) break;
-            dst[s * kPolyLen + m] = make_int2(sx, sy);
-            if (i + 1 < cnt) {
-                int2 vi = s_f[bpad(i + spc)], vo = s_f[bpad(i)];
-                sx += vi.x - vo.x;
-                sy += vi.y - vo.y;
-            }
-            if (++s == spc) {
-                s = 0;
-                ++m;
+            for (int j = 0; j < kBoxRun; ++j) {
+                const int i = i0 + j;
+                if (i >= cnt) break;
+                dst[s * kPolyLen + m] = make_int2(sx, sy);
+                if (i + 1 < cnt) {
+                    int2 vi = s_f[bpad(i + spc)], vo = s_f[bpad(i)];
+                    sx += vi.x - vo.x;
+                    sy += vi.y - vo.y;
+                }
+                if (++s == spc) {
+                    s = 0;
+                    ++m;
+                }
             }
         }
+        if (chunk == 0 && threadIdx.x < spc) dst[threadIdx.x * kPolyLen + (kPolyLen - 1)] = make_int2(0, 0);
     }
-    if (chunk == 0 && threadIdx.x < spc) dst[threadIdx.x * kPolyLen + (kPolyLen - 1)] = make_int2(0, 0);
-}
-
-hipError_t launch_wipe_fold_box(const void *d_samples, const Plan &p, const uint32_t *d_lut,
-                                int2 *d_F, hipStream_t s)
-{
-    WipeArgs a{p.fmt, p.N, p.spc, p.Tc, p.Nnc, (double)p.fs_hz, p.f_if, p.lo, p.step};
-    const int n_chunks = (p.N + kBoxChunk - 1) / kBoxChunk;
-    const long long nwg = (long long)p.n_dopp * p.Nnc * n_chunks;
-    hipLaunchKernelGGL(k_wipe_fold_box, dim3((unsigned)nwg), dim3(256), 0, s, d_samples, d_lut, a,
-                       d_F, n_chunks);
-    return hipGetLastError();
 }
 
 // ===========================================================================
-// stage A2: forward 2048-point FFT of every polyphase component
+// stage A2: forward 2048-point FFT of every polyphase component (one wave
+// per vector; vectors of all requests are contiguous in F and G)
 // ===========================================================================
 __global__ __launch_bounds__(256) void k_fft_poly(const int2 *F, const float2 *tw, float4 *G,
-                                                  long long n_vec)
+                                                  const BatchHdr *H)
 {
     __shared__ float2 s_tw[kTwElems];
     __shared__ float2 s_xb[4][kXbufElems];
     stage_twiddles(s_tw, tw, threadIdx.x, 256);
     __syncthreads();
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const long long vec = (long long)blockIdx.x * 4 + w;
-    if (vec >= n_vec) return;
-    const int2 *src = F + vec * kPolyLen;
-    float2 v[32];
+    const long long n_vec = H->total[kStVec];
+    for (long long vec = (long long)blockIdx.x * 4 + w; vec < n_vec; vec += (long long)gridDim.x * 4) {
+        const int2 *src = F + vec * kPolyLen;
+        float2 v[32];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int k2b = 0; k2b < 8; ++k2b) {
-            if (k2b < 4) {
-                int2 t = src[l + 64 * u + 256 * k2b];
-                v[8 * u + k2b] = make_float2((float)t.x, (float)t.y);
-            } else {
-                v[8 * u + k2b] = make_float2(0.f, 0.f);
+            for (int k2b = 0; k2b < 8; ++k2b) {
+                if (k2b < 4) {
+                    int2 t = src[l + 64 * u + 256 * k2b];
+                    v[8 * u + k2b] = make_float2((float)t.x, (float)t.y);
+                } else {
+                    v[8 * u + k2b] = make_float2(0.f, 0.f);
+                }
             }
-        }
-    fft2048<true>(v, s_xb[w], s_tw, s_tw + kT1Elems, l);
-    float4 *dst = G + vec * kVec;
+        fft2048<true>(v, s_xb[w], s_tw, s_tw + kT1Elems, l);
+        float4 *dst = G + vec * kVec;
 #pragma unroll
-    for (int jj = 0; jj < 16; ++jj)
-        dst[jj * 64 + l] = make_float4(v[2 * jj].x, v[2 * jj].y, v[2 * jj + 1].x, v[2 * jj + 1].y);
-}
-
-hipError_t launch_fft_poly(const int2 *d_F, const float2 *d_tw, float4 *d_G, int64_t n_vec,
-                           hipStream_t s)
-{
-    long long blocks = (n_vec + 3) / 4;
-    hipLaunchKernelGGL(k_fft_poly, dim3((unsigned)blocks), dim3(256), 0, s, d_F, d_tw, d_G,
-                       (long long)n_vec);
-    return hipGetLastError();
+        for (int jj = 0; jj < 16; ++jj)
+            dst[jj * 64 + l] = make_float4(v[2 * jj].x, v[2 * jj].y, v[2 * jj + 1].x, v[2 * jj + 1].y);
+    }
 }
 
 // ===========================================================================
 // stage B: fused conj-multiply -> IFFT -> |.|^2 -> non-coherent sum
 // ===========================================================================
-struct CorrArgs {
-    PrnList prns;
-    int n_prn, n_dopp, N, spc, Nnc;
-    int n_items;   // n_dopp * spc work items (Doppler bin, phase)
-    int n_ptiles;
-};
-
-// Workgroups are dealt round-robin to the 8 XCDs; remap so that consecutive
-// logical ids (the PRN tiles of one item chunk, which read the same G) run on
-// the same XCD and share its L2.
-__device__ __forceinline__ int xcd_remap(int bid, int nwg)
-{
-    const int X = 8, q = nwg / X, r = nwg % X;
-    const int xcd = bid % X, local = bid / X;
-    return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
-}
-
 constexpr int kCorrWaves = 8;
-
 // Staging of the finished sums for the grid write: [PT][1024 q][9] floats
 // (8 waves + 1 pad, so both the per-wave writes and the per-row reads are
 // free of bank conflicts).
 constexpr int kStagePad = kCorrWaves + 1;
 
+// Work item = (request, PRN tile, chunk of kCorrWaves (Doppler, phase)
+// items); one wave per (Doppler, phase) item, looping over the blocks and the
+// tile's PT PRNs with the sums in registers.
 template <int PT>
-__global__ __launch_bounds__(64 * kCorrWaves) void k_corr(const float4 *G,
+__global__ __launch_bounds__(64 * kCorrWaves) void k_corr(const ReqDesc *R, BatchHdr *H,
+                                                          const long long *pre, const float4 *G,
                                                           const float4 *__restrict__ CS,
-                                                          const float2 *__restrict__ tw,
-                                                          float *__restrict__ grid, CorrArgs a)
+                                                          const float2 *__restrict__ tw)
 {
     constexpr int kCcBytes = PT * kVec * (int)sizeof(float4);
     constexpr int kTwBytes = kTwElems * (int)sizeof(float2);
@@ -437,240 +469,246 @@ __global__ __launch_bounds__(64 * kCorrWaves) void k_corr(const float4 *G,
     constexpr int kSmem = (kCcBytes + kTwBytes + kXbBytes) > kStageBytes ? (kCcBytes + kTwBytes + kXbBytes)
                                                                           : kStageBytes;
     __shared__ __align__(16) unsigned char smem[kSmem];
+    __shared__ long long s_item;
     float4 *s_cc = (float4 *)smem;
     float2 *s_tw = (float2 *)(smem + kCcBytes);
     float2 *s_xb = (float2 *)(smem + kCcBytes + kTwBytes);
     float *s_stage = (float *)smem;  // reused after the transforms
 
     const int tid = threadIdx.x;
-    const int logical = xcd_remap(blockIdx.x, gridDim.x);
-    const int ptile = logical % a.n_ptiles, chunk = logical / a.n_ptiles;
-    for (int i = tid; i < PT * kVec; i += 64 * kCorrWaves) {
-        int p = i / kVec, e = i - p * kVec;
-        int pi = ptile * PT + p;
-        int prn = pi < a.n_prn ? a.prns.v[pi] : 0;
-        s_cc[i] = CS[(long long)prn * kVec + e];
-    }
-    stage_twiddles(s_tw, tw, tid, 64 * kCorrWaves);
-    __syncthreads();
-
     const int w = tid >> 6, l = tid & 63;
-    const int item = chunk * kCorrWaves + w;
-    const bool active = item < a.n_items;
-    const int k = item / a.spc, s = item - k * a.spc;
+    const int n_req = H->n_req;
+    const long long total = H->total[kStCorr];
+    const long long *pst = pre + (long long)kStCorr * (n_req + 1);
+    for (;;) {
+        const long long it = next_item(H, kStCorr, total, &s_item);
+        if (it < 0) break;
+        const int r = find_req(pst, n_req, it);
+        const ReqDesc &d = R[r];
+        const long long local = it - pst[r];
+        const int ptile = (int)(local % d.n_ptiles), chunk = (int)(local / d.n_ptiles);
+        // code spectra of the tile's PRNs and the twiddles (the staging area of
+        // the previous item's write is overwritten here: the barrier inside
+        // next_item separates them)
+        for (int i = tid; i < PT * kVec; i += 64 * kCorrWaves) {
+            int p = i / kVec, e = i - p * kVec;
+            int pi = ptile * PT + p;
+            int prn = pi < d.n_prn ? d.prns[pi] : 0;
+            s_cc[i] = CS[(long long)prn * kVec + e];
+        }
+        stage_twiddles(s_tw, tw, tid, 64 * kCorrWaves);
+        __syncthreads();
 
-    float acc[PT][16];
-#pragma unroll
-    for (int p = 0; p < PT; ++p)
-#pragma unroll
-        for (int i = 0; i < 16; ++i) acc[p][i] = 0.f;
+        const int item = chunk * kCorrWaves + w;
+        const bool active = item < d.n_items;
+        const int spc = d.spc;
+        const int k = item / spc, s = item - k * spc;
 
-    if (active) {
-        const float4 *gk = G + ((long long)k * a.Nnc * a.spc + s) * kVec;
-        float2 *xb = s_xb + w * kXbufElems;
-        for (int b = 0; b < a.Nnc; ++b) {
-            const float4 *gp = gk + (long long)b * a.spc * kVec;
-            // PRN slots past n_prn hold the all-zero spectrum of row 0; they are
-            // computed (no branch in the loop) but never written.
+        float acc[PT][16];
 #pragma unroll
-            for (int p = 0; p < PT; ++p) {
-                // the block spectrum is re-read for every PRN of the tile (L1/L2
-                // hits after the first) rather than pinned in registers
-                float2 z[32];
-                const float4 *gq = gp;
-                asm volatile("" : "+v"(gq));
-                phase_barrier();
+        for (int p = 0; p < PT; ++p)
 #pragma unroll
-                for (int jj = 0; jj < 16; ++jj) {
-                    float4 t = gq[jj * 64 + l];
-                    float4 c = s_cc[p * kVec + jj * 64 + l];
-                    z[2 * jj] = c_mul(make_float2(t.x, t.y), make_float2(c.x, c.y));
-                    z[2 * jj + 1] = c_mul(make_float2(t.z, t.w), make_float2(c.z, c.w));
-                }
-                phase_barrier();
-                ifft2048<true>(z, xb, s_tw, s_tw + kT1Elems, l);
-                phase_barrier();
+            for (int i = 0; i < 16; ++i) acc[p][i] = 0.f;
+
+        if (active) {
+            const float4 *gk = G + (d.vec_off + (long long)k * d.Nnc * spc + s) * kVec;
+            float2 *xb = s_xb + w * kXbufElems;
+            for (int b = 0; b < d.Nnc; ++b) {
+                const float4 *gp = gk + (long long)b * spc * kVec;
+                // PRN slots past n_prn hold the all-zero spectrum of row 0; they are
+                // computed (no branch in the loop) but never written.
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                for (int p = 0; p < PT; ++p) {
+                    // the block spectrum is re-read for every PRN of the tile (L1/L2
+                    // hits after the first) rather than pinned in registers
+                    float2 z[32];
+                    const float4 *gq = gp;
+                    asm volatile("" : "+v"(gq));
+                    phase_barrier();
 #pragma unroll
-                    for (int k2b = 0; k2b < 4; ++k2b) {
-                        float2 r = z[8 * u + k2b];
-                        acc[p][4 * u + k2b] = fmaf(r.x, r.x, fmaf(r.y, r.y, acc[p][4 * u + k2b]));
+                    for (int jj = 0; jj < 16; ++jj) {
+                        float4 t = gq[jj * 64 + l];
+                        float4 c = s_cc[p * kVec + jj * 64 + l];
+                        z[2 * jj] = c_mul(make_float2(t.x, t.y), make_float2(c.x, c.y));
+                        z[2 * jj + 1] = c_mul(make_float2(t.z, t.w), make_float2(c.z, c.w));
                     }
+                    phase_barrier();
+                    ifft2048<true>(z, xb, s_tw, s_tw + kT1Elems, l);
+                    phase_barrier();
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int k2b = 0; k2b < 4; ++k2b) {
+                            float2 rv = z[8 * u + k2b];
+                            acc[p][4 * u + k2b] = fmaf(rv.x, rv.x, fmaf(rv.y, rv.y, acc[p][4 * u + k2b]));
+                        }
+                }
             }
         }
-    }
 
-    // Grid write.  P = |IFFT|^2 * 2^-46 (2^-22 for the unnormalised 2048-point
-    // IFFT, 2^-24 for the LUT scale).  Lag tau = spc*q + s interleaves the
-    // waves' phases, so the sums are staged in LDS and written as contiguous
-    // runs of consecutive tau.
-    __syncthreads();
+        // Grid write.  P = |IFFT|^2 * 2^-46 (2^-22 for the unnormalised
+        // 2048-point IFFT, 2^-24 for the LUT scale).  Lag tau = spc*q + s
+        // interleaves the waves' phases, so the sums are staged in LDS and
+        // written as contiguous runs of consecutive tau.
+        __syncthreads();
 #pragma unroll
-    for (int p = 0; p < PT; ++p)
+        for (int p = 0; p < PT; ++p)
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int k2b = 0; k2b < 4; ++k2b) {
-                int q = l + 64 * u + 256 * k2b;
-                s_stage[(p * 1024 + q) * kStagePad + w] = acc[p][4 * u + k2b] * 0x1p-46f;
+                for (int k2b = 0; k2b < 4; ++k2b) {
+                    int q = l + 64 * u + 256 * k2b;
+                    s_stage[(p * 1024 + q) * kStagePad + w] = acc[p][4 * u + k2b] * 0x1p-46f;
+                }
+        __syncthreads();
+        const int first = chunk * kCorrWaves;
+        const int n_items_here = min(kCorrWaves, d.n_items - first);
+        int wa = 0;
+        while (wa < n_items_here) {
+            const int ka = (first + wa) / spc, sa = (first + wa) - ka * spc;
+            const int ns = min(spc - sa, n_items_here - wa);  // consecutive phases of bin ka
+            const int cnt = kCodeLen * ns;
+            for (int p = 0; p < PT; ++p) {
+                const int pi = ptile * PT + p;
+                if (pi >= d.n_prn) break;
+                float *row = d.grid + ((long long)pi * d.n_dopp + ka) * d.N + sa;
+                const float *st = s_stage + p * 1024 * kStagePad + wa;
+                for (int idx = tid; idx < cnt; idx += 64 * kCorrWaves) {
+                    const int q = idx / ns, j = idx - q * ns;
+                    row[(long long)spc * q + j] = st[q * kStagePad + j];
+                }
             }
-    __syncthreads();
-    const int first = chunk * kCorrWaves;
-    const int n_items_here = min(kCorrWaves, a.n_items - first);
-    int wa = 0;
-    while (wa < n_items_here) {
-        const int ka = (first + wa) / a.spc, sa = (first + wa) - ka * a.spc;
-        int ns = min(a.spc - sa, n_items_here - wa);  // consecutive phases of Doppler bin ka
-        const int total = kCodeLen * ns;
-        for (int p = 0; p < PT; ++p) {
-            const int pi = ptile * PT + p;
-            if (pi >= a.n_prn) break;
-            float *row = grid + ((long long)pi * a.n_dopp + ka) * a.N + sa;
-            const float *st = s_stage + p * 1024 * kStagePad + wa;
-            for (int idx = tid; idx < total; idx += 64 * kCorrWaves) {
-                const int q = idx / ns, j = idx - q * ns;
-                row[(long long)a.spc * q + j] = st[q * kStagePad + j];
-            }
+            wa += ns;
         }
-        wa += ns;
     }
 }
 
-constexpr int kCorrPT = 4;
-
-hipError_t launch_corr(const float4 *d_G, const float4 *d_cs, const float2 *d_tw, float *d_grid,
-                       const Plan &p, hipStream_t s)
-{
-    CorrArgs a;
-    a.prns = p.prns;
-    a.n_prn = p.n_prn;
-    a.n_dopp = p.n_dopp;
-    a.N = p.N;
-    a.spc = p.spc;
-    a.Nnc = p.Nnc;
-    a.n_items = p.n_dopp * p.spc;
-    a.n_ptiles = (p.n_prn + kCorrPT - 1) / kCorrPT;
-    const int n_chunks = (a.n_items + kCorrWaves - 1) / kCorrWaves;
-    const long long nwg = (long long)n_chunks * a.n_ptiles;
-    hipLaunchKernelGGL(k_corr<kCorrPT>, dim3((unsigned)nwg), dim3(64 * kCorrWaves), 0, s, d_G,
-                       d_cs, d_tw, d_grid, a);
-    return hipGetLastError();
-}
+int corr_ptile_valid(int pt) { return pt == 2 || pt == 4; }
 
 // ===========================================================================
 // detection: column max over Doppler, argmax, second peak, mean; refinement
 // ===========================================================================
-constexpr int kPeakThreads = 256;
-
-size_t peak_scratch_part_elems(const Plan &p)
-{
-    return (size_t)p.n_prn * ((p.N + kPeakThreads - 1) / kPeakThreads);
-}
-
-// Q[p][tau] = max_k P (lowest k on ties), K = that k; part = per-block sum of P (FP64).
-__global__ __launch_bounds__(kPeakThreads) void k_colmax(const float *grid, int n_dopp, int N,
-                                                         float *Q, int32_t *K, double *part)
+// Work item = (request, PRN, block of 256 lags).  Q[tau] = max_k P (lowest k
+// on ties), K = that k; part = the block's FP64 sum of P (summed in a fixed
+// tree, so the mean does not depend on scheduling).
+__global__ __launch_bounds__(kPeakThreads) void k_colmax(const ReqDesc *R, BatchHdr *H,
+                                                         const long long *pre, float *Q, int32_t *K,
+                                                         double *part)
 {
     __shared__ double red[kPeakThreads];
-    const int p = blockIdx.y, tau = blockIdx.x * kPeakThreads + threadIdx.x;
-    double colsum = 0.0;
-    if (tau < N) {
-        const float *col = grid + (long long)p * n_dopp * N + tau;
-        float best = col[0];
-        int kb = 0;
-        colsum = (double)best;
-        for (int k = 1; k < n_dopp; ++k) {
-            float v = col[(long long)k * N];
-            colsum += (double)v;
-            if (v > best) {
-                best = v;
-                kb = k;
+    const int n_req = H->n_req;
+    const long long total = H->total[kStColmax];
+    const long long *pst = pre + (long long)kStColmax * (n_req + 1);
+    for (long long it = blockIdx.x; it < total; it += gridDim.x) {
+        const int r = find_req(pst, n_req, it);
+        const ReqDesc &d = R[r];
+        const long long local = it - pst[r];
+        const int p = (int)(local / d.n_tau_blk), blk = (int)(local % d.n_tau_blk);
+        const int N = d.N, tau = blk * kPeakThreads + threadIdx.x;
+        double colsum = 0.0;
+        if (tau < N) {
+            const float *col = d.grid + (long long)p * d.n_dopp * N + tau;
+            float best = col[0];
+            int kb = 0;
+            colsum = (double)best;
+            for (int k = 1; k < d.n_dopp; ++k) {
+                float v = col[(long long)k * N];
+                colsum += (double)v;
+                if (v > best) {
+                    best = v;
+                    kb = k;
+                }
             }
+            Q[d.qk_off + (long long)p * N + tau] = best;
+            K[d.qk_off + (long long)p * N + tau] = kb;
         }
-        Q[(long long)p * N + tau] = best;
-        K[(long long)p * N + tau] = kb;
-    }
-    red[threadIdx.x] = colsum;
-    __syncthreads();
-    for (int st = kPeakThreads / 2; st > 0; st >>= 1) {
-        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
         __syncthreads();
+        red[threadIdx.x] = colsum;
+        __syncthreads();
+        for (int st = kPeakThreads / 2; st > 0; st >>= 1) {
+            if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[d.part_off + (long long)p * d.n_tau_blk + blk] = red[0];
     }
-    if (threadIdx.x == 0) part[(long long)p * gridDim.x + blockIdx.x] = red[0];
 }
 
-struct PeakArgs {
-    PrnList prns;
-    int n_dopp, N, spc, n_parts;
-    float threshold;
-};
-
-__global__ __launch_bounds__(kPeakThreads) void k_peak(const float *Q, const int32_t *K,
-                                                       const double *part, PeakArgs a,
-                                                       gnss_peak *out)
+// Work item = (request, PRN): argmax (lowest tau on ties), second peak outside
+// +-spc (circular), mean, ratio test.
+__global__ __launch_bounds__(kPeakThreads) void k_peak(const ReqDesc *R, BatchHdr *H,
+                                                       const long long *pre, const float *Q,
+                                                       const int32_t *K, const double *part)
 {
     __shared__ float sv[kPeakThreads];
     __shared__ int st[kPeakThreads];
-    const int p = blockIdx.x, tid = threadIdx.x;
-    const float *q = Q + (long long)p * a.N;
-    // argmax, lowest tau on ties
-    float bv = -INFINITY;
-    int bt = 0x7fffffff;
-    for (int tau = tid; tau < a.N; tau += kPeakThreads) {
-        float v = q[tau];
-        if (v > bv) {
-            bv = v;
-            bt = tau;
-        }
-    }
-    sv[tid] = bv;
-    st[tid] = bt;
-    __syncthreads();
-    for (int s = kPeakThreads / 2; s > 0; s >>= 1) {
-        if (tid < s) {
-            float v2 = sv[tid + s];
-            int t2 = st[tid + s];
-            if (v2 > sv[tid] || (v2 == sv[tid] && t2 < st[tid])) {
-                sv[tid] = v2;
-                st[tid] = t2;
+    const int tid = threadIdx.x;
+    const int n_req = H->n_req;
+    const long long total = H->total[kStPeak];
+    const long long *pst = pre + (long long)kStPeak * (n_req + 1);
+    for (long long it = blockIdx.x; it < total; it += gridDim.x) {
+        const int r = find_req(pst, n_req, it);
+        const ReqDesc &d = R[r];
+        const int p = (int)(it - pst[r]);
+        const int N = d.N;
+        const float *q = Q + d.qk_off + (long long)p * N;
+        float bv = -INFINITY;
+        int bt = 0x7fffffff;
+        for (int tau = tid; tau < N; tau += kPeakThreads) {
+            float v = q[tau];
+            if (v > bv) {
+                bv = v;
+                bt = tau;
             }
         }
         __syncthreads();
-    }
-    const float peak = sv[0];
-    // a grid with no ordered maximum (all NaN) leaves tau* unset: keep it in range
-    const int tstar = (st[0] >= 0 && st[0] < a.N) ? st[0] : 0;
-    __syncthreads();
-    // second peak outside +-spc (circular)
-    float m2 = -INFINITY;
-    for (int tau = tid; tau < a.N; tau += kPeakThreads) {
-        int d = abs(tau - tstar);
-        d = min(d, a.N - d);
-        if (d > a.spc) m2 = fmaxf(m2, q[tau]);
-    }
-    sv[tid] = m2;
-    __syncthreads();
-    for (int s = kPeakThreads / 2; s > 0; s >>= 1) {
-        if (tid < s) sv[tid] = fmaxf(sv[tid], sv[tid + s]);
+        sv[tid] = bv;
+        st[tid] = bt;
         __syncthreads();
-    }
-    if (tid == 0) {
-        float second = sv[0] == -INFINITY ? 0.f : sv[0];
-        double sum = 0.0;
-        for (int i = 0; i < a.n_parts; ++i) sum += part[(long long)p * a.n_parts + i];
-        gnss_peak r;
-        r.prn = a.prns.v[p];
-        r.doppler_bin = K[(long long)p * a.N + tstar];
-        r.code_phase = tstar;
-        r.peak = peak;
-        r.second = second;
-        r.mean = (float)(sum / ((double)a.n_dopp * (double)a.N));
-        r.ratio = second > 0.f ? peak / second : INFINITY;
-        r.detected = r.ratio >= a.threshold ? 1 : 0;
-        r.doppler_hz = 0.0;
-        r.code_phase_frac = (double)tstar;
-        out[p] = r;
+        for (int s = kPeakThreads / 2; s > 0; s >>= 1) {
+            if (tid < s) {
+                float v2 = sv[tid + s];
+                int t2 = st[tid + s];
+                if (v2 > sv[tid] || (v2 == sv[tid] && t2 < st[tid])) {
+                    sv[tid] = v2;
+                    st[tid] = t2;
+                }
+            }
+            __syncthreads();
+        }
+        const float peak = sv[0];
+        // a grid with no ordered maximum (all NaN) leaves tau* unset: keep it in range
+        const int tstar = (st[0] >= 0 && st[0] < N) ? st[0] : 0;
+        __syncthreads();
+        float m2 = -INFINITY;
+        for (int tau = tid; tau < N; tau += kPeakThreads) {
+            int dd = abs(tau - tstar);
+            dd = min(dd, N - dd);
+            if (dd > d.spc) m2 = fmaxf(m2, q[tau]);
+        }
+        sv[tid] = m2;
+        __syncthreads();
+        for (int s = kPeakThreads / 2; s > 0; s >>= 1) {
+            if (tid < s) sv[tid] = fmaxf(sv[tid], sv[tid + s]);
+            __syncthreads();
+        }
+        if (tid == 0) {
+            float second = sv[0] == -INFINITY ? 0.f : sv[0];
+            double sum = 0.0;
+            for (int i = 0; i < d.n_tau_blk; ++i) sum += part[d.part_off + (long long)p * d.n_tau_blk + i];
+            gnss_peak rr;
+            rr.prn = d.prns[p];
+            rr.doppler_bin = K[d.qk_off + (long long)p * N + tstar];
+            rr.code_phase = tstar;
+            rr.peak = peak;
+            rr.second = second;
+            rr.mean = (float)(sum / ((double)d.n_dopp * (double)N));
+            rr.ratio = second > 0.f ? peak / second : INFINITY;
+            rr.detected = rr.ratio >= d.threshold ? 1 : 0;
+            rr.doppler_hz = 0.0;
+            rr.code_phase_frac = (double)tstar;
+            d.peaks[p] = rr;
+        }
+        __syncthreads();
     }
 }
 
@@ -681,39 +719,110 @@ __device__ __forceinline__ double parabola(double ym, double y0, double yp)
     return 0.5 * (ym - yp) / den;
 }
 
-// FP64 sub-bin refinement (the only FP64 arithmetic on the hot path).
-__global__ void k_interp(const float *grid, int n_prn, int n_dopp, int N, double lo, double step,
-                         gnss_peak *out)
+// FP64 sub-bin refinement (the only FP64 arithmetic on the hot path); one
+// thread per (request, PRN).
+__global__ void k_interp(const ReqDesc *R, BatchHdr *H, const long long *pre)
 {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n_prn) return;
-    gnss_peak r = out[p];
-    const float *G = grid + (long long)p * n_dopp * N;
-    const int k = r.doppler_bin, t = r.code_phase;
-    double y0 = G[(long long)k * N + t];
-    double dc = parabola(G[(long long)k * N + (t - 1 + N) % N], y0, G[(long long)k * N + (t + 1) % N]);
-    double dd = 0.0;
-    if (k > 0 && k < n_dopp - 1) dd = parabola(G[(long long)(k - 1) * N + t], y0, G[(long long)(k + 1) * N + t]);
-    double fk = __dadd_rn(lo, __dmul_rn((double)k, step));
-    out[p].doppler_hz = __dadd_rn(fk, __dmul_rn(dd, step));
-    out[p].code_phase_frac = __dadd_rn((double)t, dc);
+    const int n_req = H->n_req;
+    const long long total = H->total[kStPeak];
+    const long long *pst = pre + (long long)kStPeak * (n_req + 1);
+    for (long long it = (long long)blockIdx.x * blockDim.x + threadIdx.x; it < total;
+         it += (long long)gridDim.x * blockDim.x) {
+        const int r = find_req(pst, n_req, it);
+        const ReqDesc &d = R[r];
+        const int p = (int)(it - pst[r]);
+        gnss_peak rr = d.peaks[p];
+        const int N = d.N, nd = d.n_dopp;
+        const float *Gp = d.grid + (long long)p * nd * N;
+        const int k = rr.doppler_bin, t = rr.code_phase;
+        double y0 = Gp[(long long)k * N + t];
+        double dc = parabola(Gp[(long long)k * N + (t - 1 + N) % N], y0, Gp[(long long)k * N + (t + 1) % N]);
+        double dd = 0.0;
+        if (k > 0 && k < nd - 1) dd = parabola(Gp[(long long)(k - 1) * N + t], y0, Gp[(long long)(k + 1) * N + t]);
+        double fk = __dadd_rn(d.lo, __dmul_rn((double)k, d.step));
+        d.peaks[p].doppler_hz = __dadd_rn(fk, __dmul_rn(dd, d.step));
+        d.peaks[p].code_phase_frac = __dadd_rn((double)t, dc);
+    }
 }
 
-hipError_t launch_peaks(const float *d_grid, const Plan &p, float threshold, float *d_Q,
-                        int32_t *d_K, double *d_part, gnss_peak *d_peaks, hipStream_t s)
+// ===========================================================================
+// launch of a whole batch (or of its detection stages only)
+// ===========================================================================
+template <typename K>
+static int occupancy(K kernel, int threads, int n_cu)
 {
-    const int nblk = (p.N + kPeakThreads - 1) / kPeakThreads;
-    hipLaunchKernelGGL(k_colmax, dim3(nblk, p.n_prn), dim3(kPeakThreads), 0, s, d_grid, p.n_dopp,
-                       p.N, d_Q, d_K, d_part);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    PeakArgs a{p.prns, p.n_dopp, p.N, p.spc, nblk, threshold};
-    hipLaunchKernelGGL(k_peak, dim3(p.n_prn), dim3(kPeakThreads), 0, s, d_Q, d_K, d_part, a, d_peaks);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_interp, dim3((p.n_prn + 63) / 64), dim3(64), 0, s, d_grid, p.n_prn,
-                       p.n_dopp, p.N, p.lo, p.step, d_peaks);
-    return hipGetLastError();
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return per_cu * n_cu;
+}
+
+static unsigned grid_for(long long work, long long cap)
+{
+    long long g = work < cap ? work : cap;
+    if (g < kXcds) g = kXcds;  // every XCD range gets a workgroup
+    return (unsigned)g;
+}
+
+hipError_t launch_batch(const Launch &L, const uint32_t *d_lut, const float2 *d_tw,
+                        const float4 *d_cs, int2 *d_F, float4 *d_G, float *d_Q, int32_t *d_K,
+                        double *d_part, int n_cu, hipStream_t s, hipEvent_t *marks)
+{
+    hipError_t e;
+    auto mark = [&](int i) -> hipError_t { return marks ? hipEventRecord(marks[i], s) : hipSuccess; };
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, L.hdr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = mark(0)) != hipSuccess) return e;
+    if (L.total[kStBox] > 0) {
+        static int cap = 0;
+        if (!cap) cap = occupancy(k_box, 256, n_cu);
+        hipLaunchKernelGGL(k_box, dim3(grid_for(L.total[kStBox], cap)), dim3(256), 0, s, L.reqs, L.hdr,
+                           L.pre, d_lut, d_F);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if ((e = mark(1)) != hipSuccess) return e;
+    if (L.total[kStVec] > 0) {
+        static int cap = 0;
+        if (!cap) cap = occupancy(k_fft_poly, 256, n_cu);
+        hipLaunchKernelGGL(k_fft_poly, dim3(grid_for((L.total[kStVec] + 3) / 4, cap)), dim3(256), 0, s,
+                           d_F, d_tw, d_G, L.hdr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if ((e = mark(2)) != hipSuccess) return e;
+    if (L.total[kStCorr] > 0) {
+        if (L.corr_pt == 2) {
+            static int cap = 0;
+            if (!cap) cap = occupancy(k_corr<2>, 64 * kCorrWaves, n_cu);
+            hipLaunchKernelGGL(k_corr<2>, dim3(grid_for(L.total[kStCorr], cap)), dim3(64 * kCorrWaves), 0, s,
+                               L.reqs, L.hdr, L.pre, d_G, d_cs, d_tw);
+        } else {
+            static int cap = 0;
+            if (!cap) cap = occupancy(k_corr<4>, 64 * kCorrWaves, n_cu);
+            hipLaunchKernelGGL(k_corr<4>, dim3(grid_for(L.total[kStCorr], cap)), dim3(64 * kCorrWaves), 0, s,
+                               L.reqs, L.hdr, L.pre, d_G, d_cs, d_tw);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if ((e = mark(3)) != hipSuccess) return e;
+    {
+        static int cap = 0;
+        if (!cap) cap = occupancy(k_colmax, kPeakThreads, n_cu);
+        hipLaunchKernelGGL(k_colmax, dim3(grid_for(L.total[kStColmax], cap)), dim3(kPeakThreads), 0, s,
+                           L.reqs, L.hdr, L.pre, d_Q, d_K, d_part);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_peak, dim3(grid_for(L.total[kStPeak], 4LL * n_cu)), dim3(kPeakThreads), 0, s,
+                           L.reqs, L.hdr, L.pre, d_Q, d_K, d_part);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_interp, dim3((unsigned)((L.total[kStPeak] + 63) / 64 > 0 ? (L.total[kStPeak] + 63) / 64 : 1)),
+                           dim3(64), 0, s, L.reqs, L.hdr, L.pre);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return mark(4);
+}
+
+size_t peak_scratch_part_elems(const Plan &p)
+{
+    return (size_t)p.n_prn * ((p.N + kPeakThreads - 1) / kPeakThreads);
 }
 
 // ===========================================================================

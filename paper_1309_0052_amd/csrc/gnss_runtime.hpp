@@ -1,0 +1,130 @@
+// gnss_runtime.hpp -- host runtime objects shared by the C ABI, the batch
+// graphs, the serving loop and the autotuner.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "gnss_internal.hpp"
+
+namespace gnss_rt {
+
+int set_err(int code, const char *fmt, ...);
+extern thread_local std::string t_err;
+
+#define HIP_TRY(expr)                                                                                \
+    do {                                                                                             \
+        hipError_t e_ = (expr);                                                                      \
+        if (e_ != hipSuccess)                                                                        \
+            return ::gnss_rt::set_err(GNSS_EDEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                                      __FILE__, __LINE__);                                           \
+    } while (0)
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+// Device buffers of one in-flight batch and the pinned staging of its
+// metadata.
+struct Workspace {
+    DevBuf F, G, Q, K, part, grid, meta, samples, peaks;
+    void *h_stage = nullptr;
+    size_t h_stage_cap = 0;
+    hipEvent_t stage_ev = nullptr;
+};
+
+// A laid-out batch on the host.
+struct BatchHost {
+    int n = 0;
+    int corr_pt = 4;
+    std::vector<gnss::ReqDesc> d;
+    std::vector<long long> pre;
+    std::vector<long long> grid_off;
+    long long total[gnss::kNumStages] = {0, 0, 0, 0, 0};
+    size_t F_bytes = 0, G_bytes = 0, Q_bytes = 0, K_bytes = 0, part_bytes = 0, grid_bytes = 0;
+};
+
+struct Ticket;
+struct Server;
+
+}  // namespace gnss_rt
+
+struct gnss_ctx {
+    int device = 0;
+    int n_cu = 1;
+    size_t budget = 0;      // 0: unlimited
+    size_t dev_bytes = 0;   // device bytes held by this context (tables + workspaces)
+    size_t table_bytes = 0; // of which the constant tables
+    int precision = GNSS_FP32;
+    float threshold = 2.5f;
+    int corr_pt_forced = 0; // 0: tuned / default
+    int max_slots = 64;     // requests per served batch
+    hipStream_t stream = nullptr;
+    // tables
+    uint32_t *d_lut = nullptr;  // [1024] packed cos16 | sin16 << 16
+    uint8_t *d_codes = nullptr; // [38][1023], row = PRN
+    float2 *d_tw = nullptr;     // twiddles
+    float4 *d_cs = nullptr;     // [38][1024] code spectra, storage order
+    gnss_rt::Workspace ws;      // synchronous and device-buffer calls
+    // autotuned PRN tile per sample-rate signature
+    std::map<std::string, int> tuned_pt;
+    // per-stage timing
+    bool profile = false;
+    std::vector<hipEvent_t> event_pool;
+    std::vector<std::array<hipEvent_t, GNSS_N_STAGES + 1>> pending;
+    double stage_ms[GNSS_N_STAGES] = {0, 0, 0, 0};
+    int64_t stage_n[GNSS_N_STAGES] = {0, 0, 0, 0};
+    gnss_rt::Server *server = nullptr;  // serving loop, created on first submit
+    std::mutex mu;      // serialises calls that use ws / timing state
+    std::mutex mem_mu;  // dev_bytes accounting
+};
+
+struct gnss_graph {
+    gnss_ctx *ctx = nullptr;
+    gnss_rt::Workspace ws;
+    hipGraphExec_t exec = nullptr;
+    int corr_pt = 4;
+};
+
+namespace gnss_rt {
+
+struct DeviceGuard {
+    int prev = -1;
+    bool changed = false;
+    int rc = GNSS_OK;
+    explicit DeviceGuard(int dev);
+    ~DeviceGuard();
+};
+
+size_t sample_bytes(int fmt, size_t n);
+int ensure(gnss_ctx *c, DevBuf &b, size_t bytes);
+void release(gnss_ctx *c, DevBuf &b);
+void release_ws(gnss_ctx *c, Workspace &w);
+int make_plan(const gnss_request *r, gnss::Plan &p, bool need_outputs);
+int plan_all(const gnss_request *reqs, int n, std::vector<gnss::Plan> &plans);
+void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int corr_pt, float threshold,
+                 BatchHost &B);
+size_t meta_bytes(int n);
+size_t batch_device_bytes(const BatchHost &B);
+int stage_batch(gnss_ctx *c, Workspace &w, BatchHost &B, hipStream_t s, gnss::Launch &L);
+int launch(gnss_ctx *c, Workspace &w, const gnss::Launch &L, hipStream_t s, bool allow_profile);
+
+// autotuner lookup: the PRN tile for a batch of these plans
+int corr_ptile_for(gnss_ctx *c, const gnss::Plan *plans, int n);
+std::string rate_signature(const gnss::Plan *plans, int n);
+
+// serving loop
+void server_stop(gnss_ctx *c);
+
+}  // namespace gnss_rt

@@ -196,3 +196,38 @@ def weak_complex_int8(code_fn, seed: int = 2):
     planted = _draw_planted(rng, 8, range(1, 33), fs // 1000, 7500.0, 28.0, 40.0, True)
     snap = make_snapshot(seed, CPLX_I8, fs, 0.0, 100.0, planted, code_fn)
     return snap, Search(list(range(1, 33)), -7500.0, 7500.0, 125.0, 4, 25)
+
+
+def batch_workload(code_fn, seed: int = 4, n: int = 256, ms_range=(20, 200), rates=None,
+                   prn_range=(8, 32), window_khz=(2.0, 10.0), planted_range=(1, 6),
+                   cn0_range=(30.0, 45.0)):
+    """Heterogeneous snapshots for batched search: lengths U{20..200} ms, fs
+    uniform over {4.092, 8.184, 16.368} MHz, format uniform over real 2-bit
+    (f_IF = fs/4) and complex int8 (f_IF = 0), PRN subsets of U{8..32} PRNs
+    from 1-32, Doppler window +-W with W ~ U[2, 10] kHz snapped to 500 Hz,
+    1-6 planted PRNs inside the subset at C/N0 U[30, 45] dB-Hz with Doppler
+    inside the window; searched with 1 ms coherent x L non-coherent blocks,
+    500 Hz bins.  Returns a list of (Snapshot, Search)."""
+    rates = rates or [4092000, 8184000, 16368000]
+    rng = np.random.default_rng([seed, 4])
+    out = []
+    for i in range(n):
+        L = int(rng.integers(ms_range[0], ms_range[1] + 1))
+        fs = int(rates[int(rng.integers(0, len(rates)))])
+        cplx = bool(rng.integers(0, 2))
+        fmt = CPLX_I8 if cplx else REAL_I8
+        f_if = 0.0 if cplx else fs / 4.0
+        n_prn = int(rng.integers(prn_range[0], prn_range[1] + 1))
+        prns = sorted(int(p) for p in rng.choice(np.arange(1, 33), size=n_prn, replace=False))
+        W = float(np.round(rng.uniform(*window_khz) * 2.0) / 2.0 * 1000.0)
+        n_pl = int(rng.integers(planted_range[0], min(planted_range[1], n_prn) + 1))
+        pl_prns = rng.choice(np.asarray(prns), size=n_pl, replace=False)
+        planted = [Planted(prn=int(p), code_phase=int(rng.integers(0, fs // 1000)),
+                           doppler_hz=float(rng.uniform(-0.9 * W, 0.9 * W)),
+                           cn0_dbhz=float(rng.uniform(*cn0_range)),
+                           carrier_phase=float(rng.uniform(0.0, 2.0 * np.pi)))
+                   for p in pl_prns]
+        snap = make_snapshot(int(rng.integers(0, 2 ** 31)), fmt, fs, f_if, float(L), planted,
+                             code_fn)
+        out.append((snap, Search(prns, -W, W, 500.0, 1, L)))
+    return out
