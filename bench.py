@@ -29,8 +29,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (256 CU x 2.4 GHz)
+# MI355X vector peaks (256 CU x 2.4 GHz): FP32 with packed FP32 instructions,
+# and FP16 with packed FP16 instructions, both 256 flop/clock/CU
+PEAK_VALU_TFLOPS = {"fp32": 157.3, "fp16": 157.3}
 PEAK_HBM_GBS = 8000.0
+DTYPE = {"fp32": "f32", "fp16": "f16"}
+CORR_KERNEL = {"fp32": "k_corr", "fp16": "k_corr_h"}
 
 
 def kernel_source_hash() -> str:
@@ -114,6 +118,13 @@ def main():
     ap.add_argument("--serve-kind", default="mixed", choices=["mixed", "strong"],
                     help="serve: heterogeneous batch-style requests or strong-signal snapshots")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget")
+    ap.add_argument("--corr-ptile", type=int, default=0, choices=[0, 2, 4],
+                    help="PRN tile of the correlation kernel; 0: autotuned for the workload")
+    ap.add_argument("--persistent", type=int, default=-1, choices=[-1, 0, 1],
+                    help="correlation grid: 1 occupancy-sized with work counters, 0 one workgroup "
+                         "per item, -1 the library default")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16"],
+                    help="fp16: packed FP16 transforms, FP32 power and block sums")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -132,7 +143,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    ctx = G.Context(0)
+    prec = G.GNSS_FP16 if args.precision == "fp16" else G.GNSS_FP32
+    ctx = G.Context(0, precision=prec)
+    if args.corr_ptile:
+        ctx.set("corr_ptile", args.corr_ptile)
+    if args.persistent >= 0:
+        ctx.set("persistent", args.persistent)
     stream = torch.cuda.current_stream()
 
     def code_fn(prn):
@@ -163,6 +179,7 @@ def main():
     req = G.make_request(d_x.data_ptr(), snap.fmt, snap.n, snap.fs_hz, snap.f_if_hz, srch.prns,
                          srch.lo, srch.hi, srch.step, srch.T_coh, srch.N_noncoh,
                          d_grid.data_ptr(), d_pk.data_ptr())
+    pt = args.corr_ptile or ctx.autotune([req], os.path.join("/tmp", "gnss_autotune.txt"))
     ctx.set("profile", 1)
     for _ in range(args.warmup):
         ctx.acquire_device(req, stream)
@@ -196,10 +213,12 @@ def main():
     flops_unit = 5.0 * N * math.log2(N) + 10.0 * N
     achieved = units * flops_unit / (corr_ms / 1e3) / 1e12
     wl = args.workload
-    traffic = read_traffic("corr", wl)
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                "traffic": traffic, "kernel": "k_corr", "avg_launch_ms": round(corr_ms, 4),
+    kern = CORR_KERNEL[args.precision]
+    traffic = read_traffic(kern[2:], wl)
+    peak = PEAK_VALU_TFLOPS[args.precision]
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                "traffic": traffic, "kernel": kern, "avg_launch_ms": round(corr_ms, 4),
                 "flops_per_launch": units * flops_unit}
 
     out = {
@@ -213,11 +232,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": DTYPE[args.precision],
         "data": "synthetic",
         "config": {"workload": desc, "n_prn": n_prn, "n_doppler": nd, "code_phases": N,
                    "T_coh_ms": srch.T_coh, "N_noncoh": srch.N_noncoh,
-                   "cells_per_snapshot": cells},
+                   "cells_per_snapshot": cells, "corr_ptile": pt, "precision": args.precision},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "min": float(lat.min()), "max": float(lat.max())},
         "wall_s": wall_s,
@@ -263,7 +282,7 @@ def run_batch(args, G, torch, ctx, code_fn):
                                    srch.N_noncoh, g.data_ptr(), pk.data_ptr()))
         cells += _cells(srch, snap.fs_hz)
     torch.cuda.synchronize()
-    pt = ctx.autotune(reqs, os.path.join("/tmp", "gnss_autotune.txt"))
+    pt = args.corr_ptile or ctx.autotune(reqs, os.path.join("/tmp", "gnss_autotune.txt"))
     graph = ctx.graph(reqs)
     for _ in range(args.warmup):
         graph.launch(stream)
@@ -303,18 +322,20 @@ def run_batch(args, G, torch, ctx, code_fn):
         "metric": "search cells/s (PRNxDopplerxphasexms) + p50/p99 latency/snapshot",
         "value": cells / (ms_step / 1e3), "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "vs_baseline": None, "dtype": DTYPE[args.precision], "data": "synthetic",
         "config": {"workload": "heterogeneous batch of %d snapshots, 20-200 ms, fs in {4.092, 8.184, "
                                "16.368} MHz, 8-32 PRNs, +-2-10 kHz windows, 1 ms coh; one hipGraph "
                                "launch per step" % len(items),
-                   "snapshots": len(items), "cells_per_step": cells, "corr_ptile": pt},
+                   "snapshots": len(items), "cells_per_step": cells, "corr_ptile": pt,
+                   "precision": args.precision},
         "snapshots_per_s": len(items) / (ms_step / 1e3),
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "wall_s": wall_s, "generate_s": t_gen,
         "stages_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in stages.items()},
-        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                     "traffic": None, "kernel": "k_corr", "avg_launch_ms": round(corr_ms, 4)},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_VALU_TFLOPS[args.precision],
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_VALU_TFLOPS[args.precision], 4),
+                     "traffic": read_traffic(CORR_KERNEL[args.precision][2:], "batch"),
+                     "kernel": CORR_KERNEL[args.precision], "avg_launch_ms": round(corr_ms, 4)},
         "planted_recovered": [found, total],
         "source_hash": kernel_source_hash(),
     }
@@ -345,7 +366,8 @@ def run_serve(args, G, torch, ctx, code_fn):
     results = []
     rng = np.random.default_rng(5)
     for rate in rates:
-        sctx = G.Context(0, hbm_budget_bytes=int(args.budget_gb * (1 << 30)))
+        sctx = G.Context(0, hbm_budget_bytes=int(args.budget_gb * (1 << 30)),
+                         precision=G.GNSS_FP16 if args.precision == "fp16" else G.GNSS_FP32)
         n_total = args.serve_warmup + args.serve_n
         gaps = rng.exponential(1.0 / rate, n_total)
         sched = np.cumsum(gaps)
@@ -407,7 +429,7 @@ def run_serve(args, G, torch, ctx, code_fn):
         "metric": "search cells/s (PRNxDopplerxphasexms) + p50/p99 latency/snapshot",
         "value": top["cells_per_s"], "unit": "cells/s", "n_gpus": 1, "steps": int(args.serve_n),
         "warmup": int(args.serve_warmup), "ms_per_step": top["effective_running_time_ms"],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[args.precision],
         "data": "synthetic",
         "config": {"workload": "served open-loop Poisson arrivals of %s, HBM budget %.0f GB"
                                % (kind, args.budget_gb), "rates_req_s": rates},

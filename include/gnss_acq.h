@@ -60,7 +60,9 @@ extern "C" {
                                    bits, 00:+1 01:+3 10:-1 11:-3                      */
 
 /* ---- precision --------------------------------------------------------- */
-#define GNSS_FP32 0
+#define GNSS_FP32 0  /* FP32 transforms and power                             */
+#define GNSS_FP16 1  /* packed FP16 transforms with per-vector power-of-two
+                        scaling; FP32 |.|^2 and block sums                    */
 
 /* One detection result per requested PRN (Sec. 3: coarse Doppler and code
  * phase; refined values come from the FP64 parabolas). */
@@ -116,8 +118,13 @@ void gnss_ctx_destroy(gnss_ctx *ctx);
 /* Context options: "threshold" (detection ratio, > 0), "hbm_budget" (bytes,
  * 0 = unlimited; device memory of tables and workspaces), "profile" (1:
  * record per-stage HIP events, see gnss_stage_times; 0: off), "corr_ptile"
- * (PRNs per correlation workgroup: 2 or 4; 0 = autotuned, default 4),
- * "max_slots" (requests per served batch, 1..4096).  Errors: GNSS_EINVAL. */
+ * (PRNs per correlation workgroup: 2 or 4; 0 = autotuned, default 2),
+ * "persistent" (grid of the correlation kernel, the dominant one: 1, the
+ * default, an occupancy-sized grid whose workgroups take items from per-XCD
+ * work counters and then from the other XCDs' ranges; 0 one workgroup per
+ * item; the other stages always run one workgroup per item), "max_slots"
+ * (requests per served batch, 1..4096).
+ * Errors: GNSS_EINVAL. */
 int gnss_ctx_set(gnss_ctx *ctx, const char *key, double value);
 
 /* Device bytes the context's workspace needs for a request (does not
@@ -137,8 +144,8 @@ int gnss_acquire_device(gnss_ctx *ctx, const gnss_request *req, void *stream);
 
 /* Batched acquisition on device buffers: n_req requests of any lengths,
  * sample rates, PRN lists and Doppler windows searched by one pass of the
- * persistent stage kernels (the batch mode of the paper's Listing 3(b),
- * applied to whole requests).  Each request as for gnss_acquire_device.
+ * stage kernels over a device table of the requests (the batch mode of the
+ * paper's Listing 3(b), applied to whole requests).  Each request as for gnss_acquire_device.
  * Results are identical to running each request alone.  Errors: as
  * gnss_acquire_device; a bad request reports its index. */
 int gnss_acquire_batch_device(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, void *stream);

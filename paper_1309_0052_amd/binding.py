@@ -29,6 +29,7 @@ GNSS_REAL_I8 = 0
 GNSS_CPLX_I8 = 1
 GNSS_REAL_2BIT_PACKED = 2
 GNSS_FP32 = 0
+GNSS_FP16 = 1
 
 EXPORTED = [
     "gnss_acquire", "gnss_ctx_create", "gnss_ctx_destroy", "gnss_ctx_set",
@@ -39,6 +40,10 @@ EXPORTED = [
     "gnss_wait",
 ]
 
+GNSS_STAGE_WIPE_FOLD = 0
+GNSS_STAGE_FFT = 1
+GNSS_STAGE_CORR = 2
+GNSS_STAGE_DETECT = 3
 GNSS_N_STAGES = 4
 STAGE_NAMES = ["wipe_fold", "fft", "corr", "detect"]
 

@@ -22,8 +22,15 @@
 // holds registers (2 jj, 2 jj + 1) of lane l.
 // Natural order (inverse output / forward input): lane l, register 8 u + k2b
 // holds index l + 64 u + 256 k2b.
+//
+// Every pass is written once for two element types: float2 (one FP32
+// transform) and hc2 (two FP16 transforms side by side: the low halves of
+// re/im belong to one transform and the high halves to the other, so each
+// packed FP16 instruction advances both).  Both are 8 bytes, so the LDS
+// exchanges are the same for both.
 #pragma once
 
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -76,6 +83,31 @@ __device__ __forceinline__ float2 c_mulc(float2 a, float2 b)  // a * conj(b)
     return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -a.x * b.y));
 }
 
+// Two complex FP16 values of two transforms: (re.x + i im.x) and (re.y + i im.y).
+// A twiddle in this type carries the same value in both halves.
+struct hc2 {
+    __half2 re, im;
+};
+static_assert(sizeof(hc2) == sizeof(float2), "hc2 shares the float2 LDS layout");
+
+__device__ __forceinline__ hc2 make_hc2(__half2 re, __half2 im)
+{
+    hc2 r;
+    r.re = re;
+    r.im = im;
+    return r;
+}
+__device__ __forceinline__ hc2 c_add(hc2 a, hc2 b) { return make_hc2(__hadd2(a.re, b.re), __hadd2(a.im, b.im)); }
+__device__ __forceinline__ hc2 c_sub(hc2 a, hc2 b) { return make_hc2(__hsub2(a.re, b.re), __hsub2(a.im, b.im)); }
+__device__ __forceinline__ hc2 c_mul(hc2 a, hc2 w)
+{
+    return make_hc2(__hfma2(a.re, w.re, __hneg2(__hmul2(a.im, w.im))), __hfma2(a.re, w.im, __hmul2(a.im, w.re)));
+}
+__device__ __forceinline__ hc2 c_mulc(hc2 a, hc2 w)  // a * conj(w)
+{
+    return make_hc2(__hfma2(a.re, w.re, __hmul2(a.im, w.im)), __hfma2(a.im, w.re, __hneg2(__hmul2(a.re, w.im))));
+}
+
 // a * W_N^K with W_N = exp(+2 pi i / N) (inverse) or exp(-2 pi i / N) (forward)
 template <int N, int K, bool INV>
 __device__ __forceinline__ float2 tw(float2 a)
@@ -105,14 +137,45 @@ __device__ __forceinline__ float2 tw(float2 a)
     }
 }
 
+template <int N, int K, bool INV>
+__device__ __forceinline__ hc2 tw(hc2 a)
+{
+    constexpr int k = ((K % N) + N) % N;
+    if constexpr (k == 0) {
+        return a;
+    } else if constexpr (2 * k == N) {
+        return make_hc2(__hneg2(a.re), __hneg2(a.im));
+    } else if constexpr (4 * k == N) {
+        return INV ? make_hc2(__hneg2(a.im), a.re) : make_hc2(a.im, __hneg2(a.re));
+    } else if constexpr (4 * k == 3 * N) {
+        return INV ? make_hc2(a.im, __hneg2(a.re)) : make_hc2(__hneg2(a.im), a.re);
+    } else if constexpr ((8 * k) % N == 0) {
+        constexpr int oct = 8 * k / N;
+        constexpr bool cpos = (oct == 1 || oct == 7);
+        constexpr bool spos = ((oct == 1 || oct == 3) == INV);
+        const __half2 r = __float2half2_rn(0.70710678118654752440f);
+        // (x + i y)(cs + i sn) r with cs, sn = +-1
+        const __half2 re = cpos ? (spos ? __hsub2(a.re, a.im) : __hadd2(a.re, a.im))
+                                : (spos ? __hneg2(__hadd2(a.re, a.im)) : __hsub2(a.im, a.re));
+        const __half2 im = cpos ? (spos ? __hadd2(a.re, a.im) : __hsub2(a.im, a.re))
+                                : (spos ? __hsub2(a.re, a.im) : __hneg2(__hadd2(a.re, a.im)));
+        return make_hc2(__hmul2(re, r), __hmul2(im, r));
+    } else {
+        constexpr double th = ct_angle(K, N);
+        constexpr float c = (float)ct_cos(th);
+        constexpr float s = (float)(INV ? ct_sin(th) : -ct_sin(th));
+        return c_mul(a, make_hc2(__float2half2_rn(c), __float2half2_rn(s)));
+    }
+}
+
 // ---------------------------------------------------------------------------
 // small DFTs in registers (natural order in and out)
 // ---------------------------------------------------------------------------
-template <bool INV>
-__device__ __forceinline__ void dft4(float2 &a0, float2 &a1, float2 &a2, float2 &a3)
+template <bool INV, typename T>
+__device__ __forceinline__ void dft4(T &a0, T &a1, T &a2, T &a3)
 {
-    float2 t0 = c_add(a0, a2), t1 = c_sub(a0, a2);
-    float2 t2 = c_add(a1, a3), t3 = tw<4, 1, INV>(c_sub(a1, a3));
+    T t0 = c_add(a0, a2), t1 = c_sub(a0, a2);
+    T t2 = c_add(a1, a3), t3 = tw<4, 1, INV>(c_sub(a1, a3));
     a0 = c_add(t0, t2);
     a2 = c_sub(t0, t2);
     a1 = c_add(t1, t3);
@@ -120,10 +183,10 @@ __device__ __forceinline__ void dft4(float2 &a0, float2 &a1, float2 &a2, float2 
 }
 
 // 4-point DFT of (a0, a1, 0, 0)
-template <bool INV>
-__device__ __forceinline__ void dft4_half(float2 &a0, float2 &a1, float2 &a2, float2 &a3)
+template <bool INV, typename T>
+__device__ __forceinline__ void dft4_half(T &a0, T &a1, T &a2, T &a3)
 {
-    float2 x0 = a0, x1 = a1, t3 = tw<4, 1, INV>(x1);
+    T x0 = a0, x1 = a1, t3 = tw<4, 1, INV>(x1);
     a0 = c_add(x0, x1);
     a2 = c_sub(x0, x1);
     a1 = c_add(x0, t3);
@@ -132,11 +195,11 @@ __device__ __forceinline__ void dft4_half(float2 &a0, float2 &a1, float2 &a2, fl
 
 // 8-point DFT on registers a[OFF .. OFF+8).  PRUNE_IN: inputs 4..7 are zero.
 // PRUNE_OUT: only outputs 0..3 are needed (4..7 are left unspecified).
-template <bool INV, bool PRUNE_IN, bool PRUNE_OUT, int OFF, int LEN>
-__device__ __forceinline__ void dft8(float2 (&a)[LEN])
+template <bool INV, bool PRUNE_IN, bool PRUNE_OUT, int OFF, typename T, int LEN>
+__device__ __forceinline__ void dft8(T (&a)[LEN])
 {
-    float2 e0 = a[OFF + 0], e1 = a[OFF + 2], e2 = a[OFF + 4], e3 = a[OFF + 6];
-    float2 o0 = a[OFF + 1], o1 = a[OFF + 3], o2 = a[OFF + 5], o3 = a[OFF + 7];
+    T e0 = a[OFF + 0], e1 = a[OFF + 2], e2 = a[OFF + 4], e3 = a[OFF + 6];
+    T o0 = a[OFF + 1], o1 = a[OFF + 3], o2 = a[OFF + 5], o3 = a[OFF + 7];
     if constexpr (PRUNE_IN) {
         dft4_half<INV>(e0, e1, e2, e3);
         dft4_half<INV>(o0, o1, o2, o3);
@@ -160,10 +223,10 @@ __device__ __forceinline__ void dft8(float2 (&a)[LEN])
 }
 
 // 16-point DFT on registers a[OFF .. OFF+16): 4 x 4 four-step.
-template <bool INV, int OFF, int LEN>
-__device__ __forceinline__ void dft16(float2 (&a)[LEN])
+template <bool INV, int OFF, typename T, int LEN>
+__device__ __forceinline__ void dft16(T (&a)[LEN])
 {
-    float2 y[16];
+    T y[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) y[i] = a[OFF + i];
     // DFT over n1 of y[4 n1 + n2] -> y[4 k1 + n2]
@@ -226,9 +289,10 @@ __device__ __forceinline__ void phase_barrier()
 
 // I3: (lane l, reg 16h + k1) holds Y[n2 = l + 64h][k1]
 //  -> (lane l, reg 16h' + m1) holds Y[8 m1 + (l & 7)][(l >> 3) + 8h']
-__device__ __forceinline__ void transpose_a_inv(float2 (&v)[32], float2 *xb, int l)
+template <typename T>
+__device__ __forceinline__ void transpose_a_inv(T (&v)[32], T *xb, int l)
 {
-    float2 nv[32];
+    T nv[32];
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
 #pragma unroll
@@ -236,7 +300,7 @@ __device__ __forceinline__ void transpose_a_inv(float2 (&v)[32], float2 *xb, int
 #pragma unroll
             for (int kk = 0; kk < 8; ++kk) xb[kk * kStrideA + l + 64 * h] = v[16 * h + 8 * half + kk];
         lds_fence();
-        const float2 *src = xb + (l >> 3) * kStrideA + (l & 7);
+        const T *src = xb + (l >> 3) * kStrideA + (l & 7);
 #pragma unroll
         for (int m1 = 0; m1 < 16; ++m1) nv[16 * half + m1] = src[8 * m1];
         lds_fence();
@@ -246,12 +310,13 @@ __device__ __forceinline__ void transpose_a_inv(float2 (&v)[32], float2 *xb, int
 }
 
 // adjoint of transpose_a_inv
-__device__ __forceinline__ void transpose_a_fwd(float2 (&v)[32], float2 *xb, int l)
+template <typename T>
+__device__ __forceinline__ void transpose_a_fwd(T (&v)[32], T *xb, int l)
 {
-    float2 nv[32];
+    T nv[32];
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
-        float2 *dst = xb + (l >> 3) * kStrideA + (l & 7);
+        T *dst = xb + (l >> 3) * kStrideA + (l & 7);
 #pragma unroll
         for (int m1 = 0; m1 < 16; ++m1) dst[8 * m1] = v[16 * half + m1];
         lds_fence();
@@ -267,9 +332,10 @@ __device__ __forceinline__ void transpose_a_fwd(float2 (&v)[32], float2 *xb, int
 
 // I6: (lane l, reg 16h' + k2a) holds Y'[k1 = (l >> 3) + 8h'][m2 = l & 7][k2a]
 //  -> (lane l, reg 8u + m2) holds Y'[k1 = l & 15][m2][k2a = (l >> 4) + 4u]
-__device__ __forceinline__ void transpose_b_inv(float2 (&v)[32], float2 *xb, int l)
+template <typename T>
+__device__ __forceinline__ void transpose_b_inv(T (&v)[32], T *xb, int l)
 {
-    float2 nv[32];
+    T nv[32];
 #pragma unroll
     for (int hb = 0; hb < 2; ++hb) {
 #pragma unroll
@@ -290,9 +356,10 @@ __device__ __forceinline__ void transpose_b_inv(float2 (&v)[32], float2 *xb, int
 }
 
 // adjoint of transpose_b_inv
-__device__ __forceinline__ void transpose_b_fwd(float2 (&v)[32], float2 *xb, int l)
+template <typename T>
+__device__ __forceinline__ void transpose_b_fwd(T (&v)[32], T *xb, int l)
 {
-    float2 nv[32];
+    T nv[32];
 #pragma unroll
     for (int hb = 0; hb < 2; ++hb) {
 #pragma unroll
@@ -326,9 +393,8 @@ constexpr int kTwElems = kT1Elems + kT2Elems;
 // ---------------------------------------------------------------------------
 // Inverse: storage order in, natural order out (unnormalised).
 // PRUNE_OUT: only natural indices with k2b < 4 (i.e. < 1024) are produced.
-template <bool PRUNE_OUT>
-__device__ __forceinline__ void ifft2048(float2 (&v)[32], float2 *xb, const float2 *t1,
-                                         const float2 *t2, int l)
+template <bool PRUNE_OUT, typename T>
+__device__ __forceinline__ void ifft2048(T (&v)[32], T *xb, const T *t1, const T *t2, int l)
 {
     dft16<true, 0>(v);
     dft16<true, 16>(v);
@@ -346,7 +412,7 @@ __device__ __forceinline__ void ifft2048(float2 (&v)[32], float2 *xb, const floa
     phase_barrier();
 #pragma unroll
     for (int k2a = 1; k2a < 16; ++k2a) {
-        float2 w = t2[k2a * 8 + (l & 7)];
+        const T w = t2[k2a * 8 + (l & 7)];
         v[k2a] = c_mul(v[k2a], w);
         v[16 + k2a] = c_mul(v[16 + k2a], w);
     }
@@ -361,9 +427,8 @@ __device__ __forceinline__ void ifft2048(float2 (&v)[32], float2 *xb, const floa
 
 // Forward: natural order in, storage order out.
 // PRUNE_IN: natural indices >= 1024 (k2b >= 4) are zero on input.
-template <bool PRUNE_IN>
-__device__ __forceinline__ void fft2048(float2 (&v)[32], float2 *xb, const float2 *t1,
-                                        const float2 *t2, int l)
+template <bool PRUNE_IN, typename T>
+__device__ __forceinline__ void fft2048(T (&v)[32], T *xb, const T *t1, const T *t2, int l)
 {
     dft8<false, PRUNE_IN, false, 0>(v);
     dft8<false, PRUNE_IN, false, 8>(v);
@@ -374,7 +439,7 @@ __device__ __forceinline__ void fft2048(float2 (&v)[32], float2 *xb, const float
     phase_barrier();
 #pragma unroll
     for (int k2a = 1; k2a < 16; ++k2a) {
-        float2 w = t2[k2a * 8 + (l & 7)];
+        const T w = t2[k2a * 8 + (l & 7)];
         v[k2a] = c_mulc(v[k2a], w);
         v[16 + k2a] = c_mulc(v[16 + k2a], w);
     }

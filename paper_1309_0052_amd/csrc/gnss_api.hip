@@ -23,6 +23,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <new>
 
 namespace gnss_rt {
@@ -164,8 +165,9 @@ static long long cdiv(long long a, long long b) { return (a + b - 1) / b; }
 // per stage and workspace sizes.  Device pointers of the request (samples,
 // grid, peaks) are copied; null grids get offsets in the workspace grid.
 void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int corr_pt,
-                 float threshold, BatchHost &B)
+                 float threshold, int precision, BatchHost &B)
 {
+    const int corr_w = precision == GNSS_FP16 ? gnss::kCorrWavesH : gnss::kCorrWaves;
     B.d.assign(n, gnss::ReqDesc{});
     B.pre.assign((size_t)gnss::kNumStages * (n + 1), 0);
     B.grid_off.assign(n, -1);
@@ -203,7 +205,7 @@ void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int c
         }
         const long long cnt[gnss::kNumStages] = {
             (long long)p.n_dopp * p.Nnc * d.n_chunks_box, p.n_vec(),
-            (long long)d.n_ptiles * cdiv(d.n_items, 8), (long long)p.n_prn * d.n_tau_blk, (long long)p.n_prn};
+            (long long)d.n_ptiles * cdiv(d.n_items, corr_w), (long long)p.n_prn * d.n_tau_blk, (long long)p.n_prn};
         for (int st = 0; st < gnss::kNumStages; ++st) {
             B.pre[(size_t)st * (n + 1) + r] = tot[st];
             tot[st] += cnt[st];
@@ -218,8 +220,9 @@ void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int c
     }
     B.n = n;
     B.corr_pt = corr_pt;
+    B.precision = precision;
     B.F_bytes = (size_t)vec * gnss::kPolyLen * sizeof(int2);
-    B.G_bytes = (size_t)vec * gnss::kVec * sizeof(float4);
+    B.G_bytes = gnss::g_bytes(vec, precision);
     B.Q_bytes = (size_t)qk * sizeof(float);
     B.K_bytes = (size_t)qk * sizeof(int32_t);
     B.part_bytes = (size_t)part * sizeof(double);
@@ -282,6 +285,8 @@ int stage_batch(gnss_ctx *c, Workspace &w, BatchHost &B, hipStream_t s, gnss::La
     L.reqs = (const gnss::ReqDesc *)(dm + off_desc);
     L.n_req = B.n;
     L.corr_pt = B.corr_pt;
+    L.persistent = c->persistent;
+    L.precision = B.precision;
     for (int st = 0; st < gnss::kNumStages; ++st) L.total[st] = B.total[st];
     return GNSS_OK;
 }
@@ -325,8 +330,9 @@ int launch(gnss_ctx *c, Workspace &w, const gnss::Launch &L, hipStream_t s, bool
         for (auto &e : ev)
             if ((rc = take_event(c, &e))) return rc;
     }
-    HIP_TRY(gnss::launch_batch(L, c->d_lut, c->d_tw, c->d_cs, (int2 *)w.F.p, (float4 *)w.G.p, (float *)w.Q.p,
-                               (int32_t *)w.K.p, (double *)w.part.p, c->n_cu, s, prof ? ev.data() : nullptr));
+    const gnss::Tables T{c->d_lut, c->d_tw, c->d_cs, c->d_tw_h, c->d_cs_h, c->cs_exp};
+    HIP_TRY(gnss::launch_batch(L, T, (int2 *)w.F.p, w.G.p, (float *)w.Q.p, (int32_t *)w.K.p, (double *)w.part.p,
+                               c->n_cu, s, prof ? ev.data() : nullptr));
     if (prof) c->pending.push_back(ev);
     return GNSS_OK;
 }
@@ -354,7 +360,8 @@ int ctx_init_tables(gnss_ctx *c)
     const size_t codes_b = (gnss::kMaxPrn + 1) * gnss::kCodeLen;
     const size_t tw_b = gnss::kTwElems * sizeof(float2);
     const size_t cs_b = (size_t)(gnss::kMaxPrn + 1) * gnss::kVec * sizeof(float4);
-    const size_t table_bytes = lut_b + codes_b + tw_b + cs_b;
+    const bool h = c->precision == GNSS_FP16;
+    const size_t table_bytes = lut_b + codes_b + tw_b + cs_b + (h ? gnss::kTwHBytes + gnss::kCsHBytes : 0);
     if (c->budget && table_bytes > c->budget)
         return set_err(GNSS_ENOMEM, "HBM budget %zu below the %zu bytes of tables", c->budget, table_bytes);
     HIP_TRY(hipMalloc(&c->d_lut, lut_b));
@@ -368,6 +375,21 @@ int ctx_init_tables(gnss_ctx *c)
     HIP_TRY(gnss::launch_twiddles(c->d_tw, c->stream));
     HIP_TRY(gnss::launch_code_spectra(c->d_codes, c->d_tw, c->d_cs, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
+    if (h) {
+        // common exponent of the FP16 code spectra: max |C| * 2^-cs_exp <= 1
+        std::vector<float4> cs((size_t)(gnss::kMaxPrn + 1) * gnss::kVec);
+        HIP_TRY(hipMemcpy(cs.data(), c->d_cs, cs_b, hipMemcpyDeviceToHost));
+        double m = 0.0;
+        for (const float4 &v : cs)
+            m = std::max(m, std::max(std::hypot((double)v.x, (double)v.y), std::hypot((double)v.z, (double)v.w)));
+        int e = 0;
+        while (std::ldexp(1.0, e) < m * (1.0 + 0x1p-10)) ++e;
+        c->cs_exp = e;
+        HIP_TRY(hipMalloc(&c->d_tw_h, gnss::kTwHBytes));
+        HIP_TRY(hipMalloc(&c->d_cs_h, gnss::kCsHBytes));
+        HIP_TRY(gnss::launch_tables_h(c->d_cs, c->d_tw_h, c->d_cs_h, c->cs_exp, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    }
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, c->device));
     c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
@@ -389,6 +411,8 @@ void ctx_free(gnss_ctx *c)
     if (c->d_codes) (void)hipFree(c->d_codes);
     if (c->d_tw) (void)hipFree(c->d_tw);
     if (c->d_cs) (void)hipFree(c->d_cs);
+    if (c->d_tw_h) (void)hipFree(c->d_tw_h);
+    if (c->d_cs_h) (void)hipFree(c->d_cs_h);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     if (switched) (void)hipSetDevice(cur);
     delete c;
@@ -443,7 +467,8 @@ int gnss_ctx_create(gnss_ctx **out, int device, size_t hbm_budget_bytes, int pre
 {
     if (!out) return set_err(GNSS_EINVAL, "out is null");
     *out = nullptr;
-    if (precision != GNSS_FP32) return set_err(GNSS_EINVAL, "precision %d is not supported", precision);
+    if (precision != GNSS_FP32 && precision != GNSS_FP16)
+        return set_err(GNSS_EINVAL, "precision %d is not GNSS_FP32 or GNSS_FP16", precision);
     int count = 0;
     hipError_t e = hipGetDeviceCount(&count);
     if (e != hipSuccess || count < 1) {
@@ -508,6 +533,11 @@ int gnss_ctx_set(gnss_ctx *ctx, const char *key, double value)
         ctx->corr_pt_forced = (int)value;
         return GNSS_OK;
     }
+    if (!strcmp(key, "persistent")) {
+        if (value != 0.0 && value != 1.0) return set_err(GNSS_EINVAL, "persistent must be 0 or 1");
+        ctx->persistent = (int)value;
+        return GNSS_OK;
+    }
     if (!strcmp(key, "max_slots")) {
         if (!(value >= 1.0) || value > 4096.0) return set_err(GNSS_EINVAL, "max_slots outside [1, 4096]");
         ctx->max_slots = (int)value;
@@ -544,7 +574,7 @@ int gnss_workspace_bytes(const gnss_request *req, size_t *bytes)
     BatchHost B;
     gnss_request r = *req;
     r.out_grid = nullptr;
-    build_batch(&p, &r, 1, 4, 2.5f, B);
+    build_batch(&p, &r, 1, 2, 2.5f, GNSS_FP32, B);  // FP32 needs the most
     *bytes = batch_device_bytes(B) + sample_bytes(p.fmt, (size_t)p.n_samples) + (size_t)p.n_prn * sizeof(gnss_peak);
     return GNSS_OK;
 }
@@ -560,7 +590,7 @@ int gnss_acquire_batch_device(gnss_ctx *ctx, const gnss_request *reqs, int32_t n
     if (g.rc) return g.rc;
     hipStream_t s = (hipStream_t)stream;
     BatchHost B;
-    build_batch(plans.data(), reqs, n_req, corr_ptile_for(ctx, plans.data(), n_req), ctx->threshold, B);
+    build_batch(plans.data(), reqs, n_req, corr_ptile_for(ctx, plans.data(), n_req), ctx->threshold, ctx->precision, B);
     gnss::Launch L;
     if ((rc = stage_batch(ctx, ctx->ws, B, s, L))) return rc;
     return launch(ctx, ctx->ws, L, s, true);
@@ -613,7 +643,7 @@ int gnss_acquire(const void *samples, int32_t fmt, size_t n, double fs, double f
     dr.out_grid = nullptr;  // workspace grid, copied out below
     dr.out_peaks = (gnss_peak *)w.peaks.p;
     BatchHost B;
-    build_batch(&p, &dr, 1, corr_ptile_for(c, &p, 1), c->threshold, B);
+    build_batch(&p, &dr, 1, corr_ptile_for(c, &p, 1), c->threshold, c->precision, B);
     gnss::Launch L;
     if ((rc = stage_batch(c, w, B, c->stream, L)) || (rc = launch(c, w, L, c->stream, true))) {
         (void)hipStreamSynchronize(c->stream);
@@ -643,7 +673,7 @@ int gnss_graph_create(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, gn
     if (!gr) return set_err(GNSS_ENOMEM, "host allocation failed");
     gr->ctx = ctx;
     BatchHost B;
-    build_batch(plans.data(), reqs, n_req, corr_ptile_for(ctx, plans.data(), n_req), ctx->threshold, B);
+    build_batch(plans.data(), reqs, n_req, corr_ptile_for(ctx, plans.data(), n_req), ctx->threshold, ctx->precision, B);
     gr->corr_pt = B.corr_pt;
     hipStream_t cs = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
@@ -792,7 +822,7 @@ int gnss_peaks(gnss_ctx *ctx, const float *d_grid, const int32_t *prn_list, int3
     // a batch of one request that runs only the detection stages
     BatchHost B;
     B.n = 1;
-    B.corr_pt = 4;
+    B.corr_pt = 2;
     B.d.assign(1, gnss::ReqDesc{});
     gnss::ReqDesc &d = B.d[0];
     d.grid = (float *)d_grid;

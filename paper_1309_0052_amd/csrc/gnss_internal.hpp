@@ -16,6 +16,8 @@ constexpr int kMaxSpc = 16;            // samples per chip: fs <= 16.368 MHz
 constexpr int kMaxN = kCodeLen * kMaxSpc;
 constexpr int kVec = 1024;             // float4 per storage-order spectrum (2048 complex)
 constexpr int kPolyLen = 1024;         // int2 per polyphase component (1023 + 1 zero)
+constexpr int kCorrWaves = 8;          // waves per FP32 correlation workgroup
+constexpr int kCorrWavesH = 4;         // waves per FP16 correlation workgroup
 
 struct PrnList {
     int32_t v[kMaxList];
@@ -45,6 +47,23 @@ hipError_t launch_lut(uint32_t *d_lut_packed, int16_t *d_cos, int16_t *d_sin, hi
 hipError_t launch_twiddles(float2 *d_tw, hipStream_t s);
 hipError_t launch_code_spectra(const uint8_t *d_codes, const float2 *d_tw, float4 *d_cs,
                                hipStream_t s);
+// FP16 tables: packed twiddles and the code spectra scaled by 2^-cs_exp
+hipError_t launch_tables_h(const float4 *d_cs, void *d_tw_h, void *d_cs_h, int cs_exp, hipStream_t s);
+constexpr size_t kTwHBytes = 2176 * 8;                      // hc2 twiddles
+constexpr size_t kCsHBytes = (size_t)(kMaxPrn + 1) * 8192;  // [38][2048] half2
+
+// Bytes of the block spectra of n_vec polyphase vectors: FP32 float4
+// storage order; FP16 packed half2 (re, im), followed by one int exponent per
+// vector.
+inline size_t g_spectra_bytes(long long n_vec, int precision)
+{
+    return precision == GNSS_FP16 ? (size_t)n_vec * 8192 : (size_t)n_vec * kVec * 16;
+}
+inline size_t g_bytes(long long n_vec, int precision)
+{
+    return precision == GNSS_FP16 ? g_spectra_bytes(n_vec, precision) + (((size_t)n_vec * 4 + 255) & ~(size_t)255)
+                                  : g_spectra_bytes(n_vec, precision);
+}
 
 // ---------------------------------------------------------------------------
 // batched hot path: every stage kernel is persistent and walks a device-
@@ -87,10 +106,21 @@ struct Launch {
     int n_req;
     long long total[kNumStages];  // host copy (grid sizing)
     int corr_pt;                  // PRN tile of the correlation kernel (2 or 4)
+    int persistent;               // correlation kernel: 1 occupancy-sized grid with work counters, 0 a workgroup per item
+    int precision;                // GNSS_FP32 / GNSS_FP16
 };
 
-hipError_t launch_batch(const Launch &L, const uint32_t *d_lut, const float2 *d_tw,
-                        const float4 *d_cs, int2 *d_F, float4 *d_G, float *d_Q, int32_t *d_K,
+// Device-resident tables of a context.
+struct Tables {
+    const uint32_t *lut;
+    const float2 *tw;
+    const float4 *cs;
+    const void *tw_h;  // FP16 path only
+    const void *cs_h;
+    int cs_exp;
+};
+
+hipError_t launch_batch(const Launch &L, const Tables &T, int2 *d_F, void *d_G, float *d_Q, int32_t *d_K,
                         double *d_part, int n_cu, hipStream_t s, hipEvent_t *marks);
 int corr_ptile_valid(int pt);
 constexpr int kBoxChunk = 2048;
@@ -100,8 +130,6 @@ constexpr int kPeakThreads = 256;
 hipError_t launch_wipe_fold(const void *d_samples, const Plan &p, const uint32_t *d_lut,
                             int32_t *d_out /*[n_dopp][Nnc][N][2]*/, hipStream_t s);
 // detection on a caller's grid (stage entry point)
-hipError_t launch_peaks(const float *d_grid, const Plan &p, float threshold, float *d_Q,
-                        int32_t *d_K, double *d_part, gnss_peak *d_peaks, hipStream_t s);
 size_t peak_scratch_part_elems(const Plan &p);
 
 // test entry: natural-order batched 2048-point transforms

@@ -33,6 +33,26 @@
 
 namespace gnss {
 
+// Device pointers of a request live in the request table, so the compiler
+// cannot tell that they address global memory; these casts let it use global
+// (not flat) loads and stores for them.
+#define GNSS_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GNSS_GLOBAL T *gmem(T *p)
+{
+    return (GNSS_GLOBAL T *)p;
+}
+
+// A workgroup-uniform 64-bit value in scalar registers.
+__device__ __forceinline__ long long uniform64(long long v)
+{
+    const unsigned long long u = (unsigned long long)v;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+
 // ===========================================================================
 // C/A codes (IS-GPS-200 Table 3-Ia), G2-delay construction
 // ===========================================================================
@@ -227,14 +247,14 @@ __device__ __forceinline__ uint32_t nco_step(double fs, double f_if, double lo, 
 __device__ __forceinline__ void load_sample(const void *samples, int fmt, long long n, int &xr, int &xi)
 {
     if (fmt == GNSS_CPLX_I8) {
-        char2 v = ((const char2 *)samples)[n];
-        xr = v.x;
-        xi = v.y;
+        const uint32_t v = ((const GNSS_GLOBAL uint16_t *)samples)[n];  // I in the low byte
+        xr = (int)(int8_t)(v & 0xFFu);
+        xi = (int)(int8_t)(v >> 8);
     } else if (fmt == GNSS_REAL_I8) {
-        xr = ((const int8_t *)samples)[n];
+        xr = ((const GNSS_GLOBAL int8_t *)samples)[n];
         xi = 0;
     } else {
-        uint32_t byte = ((const uint8_t *)samples)[n >> 2];
+        uint32_t byte = ((const GNSS_GLOBAL uint8_t *)samples)[n >> 2];
         uint32_t code = (byte >> (2 * (uint32_t)(n & 3))) & 3u;
         // 00:+1 01:+3 10:-1 11:-3
         int mag = (code & 1u) ? 3 : 1;
@@ -306,15 +326,32 @@ __global__ void k_reset(BatchHdr *h)
     if (i < kNumStages * kXcds) h->counter[i] = 0u;
 }
 
-// Dynamic work distribution.  Workgroups are dealt round-robin to the 8 XCDs;
-// a stage's items are split into 8 contiguous ranges, one per XCD, and each
+// Work distribution.  A stage launched with at least one workgroup per item
+// runs one item per workgroup; the ids are dealt so that each XCD (workgroups
+// go to the 8 XCDs round-robin) takes a contiguous range of items, which share
+// data through that XCD's L2.  A persistent launch (fewer workgroups than
+// items) instead splits the items into 8 contiguous ranges, one per XCD; each
 // workgroup takes the next item of its own XCD's range from that XCD's
-// counter, so items that share data (consecutive ids) run on one XCD and
-// share its L2.  When its range is exhausted a workgroup takes items from the
-// other ranges.  Returns -1 when every range is exhausted.  Called by every
-// thread of the workgroup.
-__device__ __forceinline__ long long next_item(BatchHdr *h, int stage, long long total, long long *s_item)
+// counter and, once that range is exhausted, takes items from the others.
+// Returns -1 when no item is left.  Called by every thread of the workgroup;
+// `first` is true on the first call.
+__device__ __forceinline__ long long xcd_remap(long long bid, long long nwg)
 {
+    const long long q = nwg / kXcds, r = nwg % kXcds;
+    const long long xcd = bid % kXcds, local = bid / kXcds;
+    return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+}
+
+__device__ __forceinline__ long long next_item(BatchHdr *h, int stage, long long total, long long *s_item,
+                                               bool &first)
+{
+    if ((long long)gridDim.x >= total) {
+        if (!first) return -1;
+        first = false;
+        const long long id = xcd_remap(blockIdx.x, gridDim.x);
+        return id < total ? id : -1;
+    }
+    first = false;
     const long long per = (total + kXcds - 1) / kXcds;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -334,7 +371,7 @@ __device__ __forceinline__ long long next_item(BatchHdr *h, int stage, long long
         *s_item = found;
     }
     __syncthreads();
-    return *s_item;
+    return uniform64(*s_item);
 }
 
 // ===========================================================================
@@ -347,7 +384,7 @@ __device__ __forceinline__ long long next_item(BatchHdr *h, int stage, long long
 constexpr int kBoxRun = 8;
 __device__ __forceinline__ int bpad(int i) { return i + (i >> 3); }  // bank-conflict padding
 
-__global__ __launch_bounds__(256) void k_box(const ReqDesc *R, BatchHdr *H, const long long *pre,
+__global__ __launch_bounds__(256) void k_box(const ReqDesc *__restrict__ R, BatchHdr *H, const long long *pre,
                                              const uint32_t *lut, int2 *F)
 {
     __shared__ int2 s_f[(kBoxChunk + kMaxSpc) + (kBoxChunk + kMaxSpc) / 8 + 8];
@@ -357,8 +394,9 @@ __global__ __launch_bounds__(256) void k_box(const ReqDesc *R, BatchHdr *H, cons
     const int n_req = H->n_req;
     const long long total = H->total[kStBox];
     const long long *pst = pre + (long long)kStBox * (n_req + 1);
+    bool first = true;
     for (;;) {
-        const long long it = next_item(H, kStBox, total, &s_item);
+        const long long it = next_item(H, kStBox, total, &s_item, first);
         if (it < 0) break;
         const int r = find_req(pst, n_req, it);
         const ReqDesc &d = R[r];
@@ -447,17 +485,57 @@ __global__ __launch_bounds__(256) void k_fft_poly(const int2 *F, const float2 *t
 // ===========================================================================
 // stage B: fused conj-multiply -> IFFT -> |.|^2 -> non-coherent sum
 // ===========================================================================
-constexpr int kCorrWaves = 8;
-// Staging of the finished sums for the grid write: [PT][1024 q][9] floats
-// (8 waves + 1 pad, so both the per-wave writes and the per-row reads are
-// free of bank conflicts).
 constexpr int kStagePad = kCorrWaves + 1;
+
+// Grid write of a correlation work item.  P = |IFFT|^2 * scale (2^-22 for the
+// unnormalised 2048-point IFFT and 2^-24 for the LUT scale, times the FP16
+// path's code-spectrum scaling).  Lag tau = spc*q + s interleaves the waves'
+// phases, so the sums are staged in LDS ([PT][1024 q][W + 1] floats: both the
+// per-wave writes and the per-row reads are free of bank conflicts) and
+// written as contiguous runs of consecutive tau.
+template <int PT, int W>
+__device__ __forceinline__ void store_tile(const float (&acc)[PT][16], float *s_stage, const ReqDesc &d,
+                                           int ptile, int chunk, int w, int l, int tid, float scale)
+{
+    constexpr int kPad = W + 1;
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < PT; ++p)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int k2b = 0; k2b < 4; ++k2b) {
+                int q = l + 64 * u + 256 * k2b;
+                s_stage[(p * 1024 + q) * kPad + w] = acc[p][4 * u + k2b] * scale;
+            }
+    __syncthreads();
+    const int spc = d.spc;
+    const int first = chunk * W;
+    const int n_items_here = min(W, d.n_items - first);
+    int wa = 0;
+    while (wa < n_items_here) {
+        const int ka = (first + wa) / spc, sa = (first + wa) - ka * spc;
+        const int ns = min(spc - sa, n_items_here - wa);  // consecutive phases of bin ka
+        const int cnt = kCodeLen * ns;
+        for (int p = 0; p < PT; ++p) {
+            const int pi = ptile * PT + p;
+            if (pi >= d.n_prn) break;
+            GNSS_GLOBAL float *row = gmem(d.grid) + ((long long)pi * d.n_dopp + ka) * d.N + sa;
+            const float *st = s_stage + p * 1024 * kPad + wa;
+            for (int idx = tid; idx < cnt; idx += 64 * W) {
+                const int q = idx / ns, j = idx - q * ns;
+                row[(long long)spc * q + j] = st[q * kPad + j];
+            }
+        }
+        wa += ns;
+    }
+}
 
 // Work item = (request, PRN tile, chunk of kCorrWaves (Doppler, phase)
 // items); one wave per (Doppler, phase) item, looping over the blocks and the
 // tile's PT PRNs with the sums in registers.
 template <int PT>
-__global__ __launch_bounds__(64 * kCorrWaves) void k_corr(const ReqDesc *R, BatchHdr *H,
+__global__ __launch_bounds__(64 * kCorrWaves) void k_corr(const ReqDesc *__restrict__ R, BatchHdr *H,
                                                           const long long *pre, const float4 *G,
                                                           const float4 *__restrict__ CS,
                                                           const float2 *__restrict__ tw)
@@ -480,16 +558,17 @@ __global__ __launch_bounds__(64 * kCorrWaves) void k_corr(const ReqDesc *R, Batc
     const int n_req = H->n_req;
     const long long total = H->total[kStCorr];
     const long long *pst = pre + (long long)kStCorr * (n_req + 1);
+    bool first = true;
     for (;;) {
-        const long long it = next_item(H, kStCorr, total, &s_item);
+        const long long it = next_item(H, kStCorr, total, &s_item, first);
         if (it < 0) break;
         const int r = find_req(pst, n_req, it);
         const ReqDesc &d = R[r];
         const long long local = it - pst[r];
         const int ptile = (int)(local % d.n_ptiles), chunk = (int)(local / d.n_ptiles);
-        // code spectra of the tile's PRNs and the twiddles (the staging area of
-        // the previous item's write is overwritten here: the barrier inside
-        // next_item separates them)
+        // code spectra of the tile's PRNs and the twiddles (in a persistent
+        // launch this overwrites the staging area of the previous item's
+        // write: the barrier inside next_item separates them)
         for (int i = tid; i < PT * kVec; i += 64 * kCorrWaves) {
             int p = i / kVec, e = i - p * kVec;
             int pi = ptile * PT + p;
@@ -546,44 +625,280 @@ __global__ __launch_bounds__(64 * kCorrWaves) void k_corr(const ReqDesc *R, Batc
             }
         }
 
-        // Grid write.  P = |IFFT|^2 * 2^-46 (2^-22 for the unnormalised
-        // 2048-point IFFT, 2^-24 for the LUT scale).  Lag tau = spc*q + s
-        // interleaves the waves' phases, so the sums are staged in LDS and
-        // written as contiguous runs of consecutive tau.
-        __syncthreads();
-#pragma unroll
-        for (int p = 0; p < PT; ++p)
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int k2b = 0; k2b < 4; ++k2b) {
-                    int q = l + 64 * u + 256 * k2b;
-                    s_stage[(p * 1024 + q) * kStagePad + w] = acc[p][4 * u + k2b] * 0x1p-46f;
-                }
-        __syncthreads();
-        const int first = chunk * kCorrWaves;
-        const int n_items_here = min(kCorrWaves, d.n_items - first);
-        int wa = 0;
-        while (wa < n_items_here) {
-            const int ka = (first + wa) / spc, sa = (first + wa) - ka * spc;
-            const int ns = min(spc - sa, n_items_here - wa);  // consecutive phases of bin ka
-            const int cnt = kCodeLen * ns;
-            for (int p = 0; p < PT; ++p) {
-                const int pi = ptile * PT + p;
-                if (pi >= d.n_prn) break;
-                float *row = d.grid + ((long long)pi * d.n_dopp + ka) * d.N + sa;
-                const float *st = s_stage + p * 1024 * kStagePad + wa;
-                for (int idx = tid; idx < cnt; idx += 64 * kCorrWaves) {
-                    const int q = idx / ns, j = idx - q * ns;
-                    row[(long long)spc * q + j] = st[q * kStagePad + j];
-                }
-            }
-            wa += ns;
-        }
+        store_tile<PT, kCorrWaves>(acc, s_stage, d, ptile, chunk, w, l, tid, 0x1p-46f);
     }
 }
 
 int corr_ptile_valid(int pt) { return pt == 2 || pt == 4; }
+
+// ===========================================================================
+// FP16 path: packed half-precision transforms with block floating point
+// ===========================================================================
+// Scaling.  Each polyphase vector g is scaled by 2^-e (e per vector, from its
+// l1 norm) so that ||g 2^-e||_1 <= 32, and every code spectrum by the common
+// 2^-ecs with max|C 2^-ecs| <= 1.  Then every intermediate stays below 2^15:
+// all forward-transform values are bounded by the l1 norm (<= 32); the
+// spectrum product by 32; the inverse transform's radix-16 outputs by 16*32
+// and 256*32, the radix-8 partial sums by 4*256*32 = 2^15; and its outputs
+// (the correlation times 2048 * 2^-ecs) by 2^(16 - ecs).  The scale factors
+// are exact powers of two; |.|^2 and the sum over blocks are FP32.
+constexpr int kL1Exp = 5;  // ||g 2^-e||_1 <= 2^5
+
+// Smallest e with s * 2^-e <= 2^kL1Exp for a float sum s of non-negative
+// terms (the factor covers the rounding of that sum).
+__device__ __forceinline__ int l1_exponent(float s)
+{
+    if (!(s > 0.f)) return 0;
+    int x;
+    (void)frexpf(s * (1.f + 0x1p-10f), &x);  // s' < 2^x
+    return x - kL1Exp;
+}
+
+// Sum over the wave; every lane gets the same value (each butterfly level adds
+// the same two operands on both partner lanes).
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t h2_bits(__half2 h) { return __builtin_bit_cast(uint32_t, h); }
+__device__ __forceinline__ __half2 bits_h2(uint32_t u) { return __builtin_bit_cast(__half2, u); }
+
+// hc2 twiddles: the T1/T2 tables of the FP32 path rounded to FP16 from the
+// exact angle, each value in both halves.
+__global__ void k_twiddles_h(hc2 *tw)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double s, c;
+    int e;
+    double den;
+    if (i < kT1Elems) {
+        int hk = i >> 6, l = i & 63;
+        int h = hk >> 4, k1 = hk & 15;
+        e = ((l + 64 * h) * k1) & 2047;
+        den = 1024.0;
+    } else if (i < kTwElems) {
+        int j = i - kT1Elems;
+        int k2a = j >> 3, m2 = j & 7;
+        e = (m2 * k2a) & 127;
+        den = 64.0;
+    } else {
+        return;
+    }
+    sincospi((double)e / den, &s, &c);
+    // one rounding, double -> FP16 (round to nearest even)
+    const __half hc = __builtin_bit_cast(__half, (_Float16)c), hs = __builtin_bit_cast(__half, (_Float16)s);
+    tw[i] = make_hc2(__halves2half2(hc, hc), __halves2half2(hs, hs));
+}
+
+// FP16 code spectra: CSh[prn] = conj(C) * 2^-ecs as (re, im) half2 in the
+// packed storage order (uint4 unit 64 jj + l holds registers 4 jj .. 4 jj + 3
+// of lane l), from the FP32 spectra.
+__global__ void k_code_spectra_h(const float4 *cs, uint4 *csh, int ecs)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;  // prn * 512 + 64 jj + l
+    if (i >= (kMaxPrn + 1) * 512) return;
+    const int prn = i >> 9, unit = i & 511, jj = unit >> 6, l = unit & 63;
+    const float sc = ldexpf(1.f, -ecs);
+    const float4 *src = cs + (long long)prn * kVec;
+    const float4 a = src[(2 * jj) * 64 + l], b = src[(2 * jj + 1) * 64 + l];
+    csh[i] = make_uint4(h2_bits(__floats2half2_rn(a.x * sc, a.y * sc)), h2_bits(__floats2half2_rn(a.z * sc, a.w * sc)),
+                        h2_bits(__floats2half2_rn(b.x * sc, b.y * sc)), h2_bits(__floats2half2_rn(b.z * sc, b.w * sc)));
+}
+
+hipError_t launch_tables_h(const float4 *d_cs, void *d_tw_h, void *d_cs_h, int cs_exp, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_twiddles_h, dim3((kTwElems + 255) / 256), dim3(256), 0, s, (hc2 *)d_tw_h);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_code_spectra_h, dim3(((kMaxPrn + 1) * 512 + 255) / 256), dim3(256), 0, s, d_cs,
+                       (uint4 *)d_cs_h, cs_exp);
+    return hipGetLastError();
+}
+
+__device__ __forceinline__ void stage_twiddles_h(hc2 *s_tw, const hc2 *tw, int tid, int nthreads)
+{
+    for (int i = tid; i < kTwElems; i += nthreads) s_tw[i] = tw[i];
+}
+
+// Forward transforms, two polyphase vectors per wave (the low and high
+// halves).  Output: Gh[vec] in the packed storage order and the vector's
+// exponent E[vec].
+__global__ __launch_bounds__(256) void k_fft_poly_h(const int2 *F, const hc2 *tw, uint4 *Gh, int *E,
+                                                    const BatchHdr *H)
+{
+    __shared__ hc2 s_tw[kTwElems];
+    __shared__ hc2 s_xb[4][kXbufElems];
+    stage_twiddles_h(s_tw, tw, threadIdx.x, 256);
+    __syncthreads();
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const long long n_vec = H->total[kStVec];
+    const long long n_pair = (n_vec + 1) / 2;
+    for (long long pr = (long long)blockIdx.x * 4 + w; pr < n_pair; pr += (long long)gridDim.x * 4) {
+        const long long va = 2 * pr, vb = va + 1;
+        const bool has_b = vb < n_vec;
+        const int2 *sa = F + va * kPolyLen, *sb = F + vb * kPolyLen;
+        int2 a[16], b[16];
+        float na = 0.f, nb = 0.f;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int k2b = 0; k2b < 4; ++k2b) {
+                const int idx = l + 64 * u + 256 * k2b;
+                a[4 * u + k2b] = sa[idx];
+                b[4 * u + k2b] = has_b ? sb[idx] : make_int2(0, 0);
+                na += fabsf((float)a[4 * u + k2b].x) + fabsf((float)a[4 * u + k2b].y);
+                nb += fabsf((float)b[4 * u + k2b].x) + fabsf((float)b[4 * u + k2b].y);
+            }
+        const int ea = l1_exponent(wave_sum(na)), eb = l1_exponent(wave_sum(nb));
+        const float fa = ldexpf(1.f, -ea), fb = ldexpf(1.f, -eb);
+        hc2 v[32];
+        const __half2 zero = __floats2half2_rn(0.f, 0.f);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int k2b = 0; k2b < 8; ++k2b) {
+                if (k2b < 4) {
+                    const int2 x = a[4 * u + k2b], y = b[4 * u + k2b];
+                    v[8 * u + k2b] = make_hc2(__floats2half2_rn((float)x.x * fa, (float)y.x * fb),
+                                              __floats2half2_rn((float)x.y * fa, (float)y.y * fb));
+                } else {
+                    v[8 * u + k2b] = make_hc2(zero, zero);
+                }
+            }
+        fft2048<true>(v, s_xb[w], s_tw, s_tw + kT1Elems, l);
+        uint4 *ga = Gh + va * 512, *gb = Gh + vb * 512;
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) {
+            const hc2 *q = v + 4 * jj;
+            ga[jj * 64 + l] = make_uint4(h2_bits(__lows2half2(q[0].re, q[0].im)), h2_bits(__lows2half2(q[1].re, q[1].im)),
+                                         h2_bits(__lows2half2(q[2].re, q[2].im)), h2_bits(__lows2half2(q[3].re, q[3].im)));
+            if (has_b)
+                gb[jj * 64 + l] = make_uint4(h2_bits(__highs2half2(q[0].re, q[0].im)), h2_bits(__highs2half2(q[1].re, q[1].im)),
+                                             h2_bits(__highs2half2(q[2].re, q[2].im)), h2_bits(__highs2half2(q[3].re, q[3].im)));
+        }
+        if (l == 0) {
+            E[va] = ea;
+            if (has_b) E[vb] = eb;
+        }
+    }
+}
+
+// (g.re + i g.im) * c for both transforms of c
+__device__ __forceinline__ hc2 c_mul_bcast(__half2 g, hc2 c)
+{
+    const __half2 gr = __low2half2(g), gi = __high2half2(g);
+    return make_hc2(__hfma2(gr, c.re, __hneg2(__hmul2(gi, c.im))), __hfma2(gr, c.im, __hmul2(gi, c.re)));
+}
+
+// FP16 correlation: as k_corr, with the tile's PRNs in pairs, one packed
+// inverse transform per pair and block.  Work item = (request, PRN tile,
+// chunk of kCorrWavesH (Doppler, phase) items).
+template <int PT>
+__global__ __launch_bounds__(64 * kCorrWavesH) void k_corr_h(const ReqDesc *__restrict__ R, BatchHdr *H,
+                                                             const long long *pre, const uint4 *Gh,
+                                                             const int *E, const uint4 *__restrict__ CSh,
+                                                             const hc2 *__restrict__ tw, float out_scale)
+{
+    static_assert(PT % 2 == 0, "PRNs go in pairs");
+    constexpr int NP = PT / 2;
+    constexpr int W = kCorrWavesH;
+    constexpr int kCcBytes = NP * 1024 * (int)sizeof(uint4);
+    constexpr int kTwBytes = kTwElems * (int)sizeof(hc2);
+    constexpr int kXbBytes = W * kXbufElems * (int)sizeof(hc2);
+    constexpr int kStageBytes = PT * 1024 * (W + 1) * (int)sizeof(float);
+    constexpr int kSmem = (kCcBytes + kTwBytes + kXbBytes) > kStageBytes ? (kCcBytes + kTwBytes + kXbBytes)
+                                                                          : kStageBytes;
+    __shared__ __align__(16) unsigned char smem[kSmem];
+    __shared__ long long s_item;
+    uint4 *s_cc = (uint4 *)smem;  // unit 64 jj2 + l: registers 2 jj2, 2 jj2 + 1 of lane l (hc2 each)
+    hc2 *s_tw = (hc2 *)(smem + kCcBytes);
+    hc2 *s_xb = (hc2 *)(smem + kCcBytes + kTwBytes);
+    float *s_stage = (float *)smem;
+
+    const int tid = threadIdx.x;
+    const int w = tid >> 6, l = tid & 63;
+    const int n_req = H->n_req;
+    const long long total = H->total[kStCorr];
+    const long long *pst = pre + (long long)kStCorr * (n_req + 1);
+    bool first = true;
+    for (;;) {
+        const long long it = next_item(H, kStCorr, total, &s_item, first);
+        if (it < 0) break;
+        const int r = find_req(pst, n_req, it);
+        const ReqDesc &d = R[r];
+        const long long local = it - pst[r];
+        const int ptile = (int)(local % d.n_ptiles), chunk = (int)(local / d.n_ptiles);
+        for (int i = tid; i < NP * 1024; i += 64 * W) {
+            const int pp = i >> 10, unit = i & 1023, jj2 = unit >> 6, ll = unit & 63;
+            const int pa = ptile * PT + 2 * pp, pb = pa + 1;
+            const int prn_a = pa < d.n_prn ? d.prns[pa] : 0, prn_b = pb < d.n_prn ? d.prns[pb] : 0;
+            const uint4 ca = CSh[(long long)prn_a * 512 + (jj2 >> 1) * 64 + ll];
+            const uint4 cb = CSh[(long long)prn_b * 512 + (jj2 >> 1) * 64 + ll];
+            const uint32_t a0 = (jj2 & 1) ? ca.z : ca.x, a1 = (jj2 & 1) ? ca.w : ca.y;
+            const uint32_t b0 = (jj2 & 1) ? cb.z : cb.x, b1 = (jj2 & 1) ? cb.w : cb.y;
+            s_cc[i] = make_uint4(h2_bits(__lows2half2(bits_h2(a0), bits_h2(b0))), h2_bits(__highs2half2(bits_h2(a0), bits_h2(b0))),
+                                 h2_bits(__lows2half2(bits_h2(a1), bits_h2(b1))), h2_bits(__highs2half2(bits_h2(a1), bits_h2(b1))));
+        }
+        stage_twiddles_h(s_tw, tw, tid, 64 * W);
+        __syncthreads();
+
+        const int item = chunk * W + w;
+        const bool active = item < d.n_items;
+        const int spc = d.spc;
+        const int k = item / spc, s = item - k * spc;
+
+        float acc[PT][16];
+#pragma unroll
+        for (int p = 0; p < PT; ++p)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[p][i] = 0.f;
+
+        if (active) {
+            const long long v0 = d.vec_off + (long long)k * d.Nnc * spc + s;
+            hc2 *xb = s_xb + w * kXbufElems;
+            for (int b = 0; b < d.Nnc; ++b) {
+                const long long vec = v0 + (long long)b * spc;
+                const float sc = ldexpf(1.f, 2 * E[vec]);
+#pragma unroll
+                for (int pp = 0; pp < NP; ++pp) {
+                    const uint4 *gq = Gh + vec * 512;
+                    asm volatile("" : "+v"(gq));
+                    phase_barrier();
+                    hc2 z[32];
+#pragma unroll
+                    for (int jj = 0; jj < 8; ++jj) {
+                        const uint4 g = gq[jj * 64 + l];
+                        const uint4 c0 = s_cc[pp * 1024 + (2 * jj) * 64 + l];
+                        const uint4 c1 = s_cc[pp * 1024 + (2 * jj + 1) * 64 + l];
+                        z[4 * jj + 0] = c_mul_bcast(bits_h2(g.x), make_hc2(bits_h2(c0.x), bits_h2(c0.y)));
+                        z[4 * jj + 1] = c_mul_bcast(bits_h2(g.y), make_hc2(bits_h2(c0.z), bits_h2(c0.w)));
+                        z[4 * jj + 2] = c_mul_bcast(bits_h2(g.z), make_hc2(bits_h2(c1.x), bits_h2(c1.y)));
+                        z[4 * jj + 3] = c_mul_bcast(bits_h2(g.w), make_hc2(bits_h2(c1.z), bits_h2(c1.w)));
+                    }
+                    phase_barrier();
+                    ifft2048<true>(z, xb, s_tw, s_tw + kT1Elems, l);
+                    phase_barrier();
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int k2b = 0; k2b < 4; ++k2b) {
+                            const hc2 o = z[8 * u + k2b];
+                            const float2 re = __half22float2(o.re), im = __half22float2(o.im);
+                            const float ta = fmaf(re.x, re.x, im.x * im.x);
+                            const float tb = fmaf(re.y, re.y, im.y * im.y);
+                            acc[2 * pp][4 * u + k2b] = fmaf(ta, sc, acc[2 * pp][4 * u + k2b]);
+                            acc[2 * pp + 1][4 * u + k2b] = fmaf(tb, sc, acc[2 * pp + 1][4 * u + k2b]);
+                        }
+                }
+            }
+        }
+
+        store_tile<PT, W>(acc, s_stage, d, ptile, chunk, w, l, tid, out_scale);
+    }
+}
 
 // ===========================================================================
 // detection: column max over Doppler, argmax, second peak, mean; refinement
@@ -591,7 +906,7 @@ int corr_ptile_valid(int pt) { return pt == 2 || pt == 4; }
 // Work item = (request, PRN, block of 256 lags).  Q[tau] = max_k P (lowest k
 // on ties), K = that k; part = the block's FP64 sum of P (summed in a fixed
 // tree, so the mean does not depend on scheduling).
-__global__ __launch_bounds__(kPeakThreads) void k_colmax(const ReqDesc *R, BatchHdr *H,
+__global__ __launch_bounds__(kPeakThreads) void k_colmax(const ReqDesc *__restrict__ R, BatchHdr *H,
                                                          const long long *pre, float *Q, int32_t *K,
                                                          double *part)
 {
@@ -607,7 +922,7 @@ __global__ __launch_bounds__(kPeakThreads) void k_colmax(const ReqDesc *R, Batch
         const int N = d.N, tau = blk * kPeakThreads + threadIdx.x;
         double colsum = 0.0;
         if (tau < N) {
-            const float *col = d.grid + (long long)p * d.n_dopp * N + tau;
+            const GNSS_GLOBAL float *col = gmem(d.grid) + (long long)p * d.n_dopp * N + tau;
             float best = col[0];
             int kb = 0;
             colsum = (double)best;
@@ -635,7 +950,7 @@ __global__ __launch_bounds__(kPeakThreads) void k_colmax(const ReqDesc *R, Batch
 
 // Work item = (request, PRN): argmax (lowest tau on ties), second peak outside
 // +-spc (circular), mean, ratio test.
-__global__ __launch_bounds__(kPeakThreads) void k_peak(const ReqDesc *R, BatchHdr *H,
+__global__ __launch_bounds__(kPeakThreads) void k_peak(const ReqDesc *__restrict__ R, BatchHdr *H,
                                                        const long long *pre, const float *Q,
                                                        const int32_t *K, const double *part)
 {
@@ -721,7 +1036,7 @@ __device__ __forceinline__ double parabola(double ym, double y0, double yp)
 
 // FP64 sub-bin refinement (the only FP64 arithmetic on the hot path); one
 // thread per (request, PRN).
-__global__ void k_interp(const ReqDesc *R, BatchHdr *H, const long long *pre)
+__global__ void k_interp(const ReqDesc *__restrict__ R, BatchHdr *H, const long long *pre)
 {
     const int n_req = H->n_req;
     const long long total = H->total[kStPeak];
@@ -731,17 +1046,18 @@ __global__ void k_interp(const ReqDesc *R, BatchHdr *H, const long long *pre)
         const int r = find_req(pst, n_req, it);
         const ReqDesc &d = R[r];
         const int p = (int)(it - pst[r]);
-        gnss_peak rr = d.peaks[p];
+        gnss_peak *pk = d.peaks + p;
+        gnss_peak rr = *pk;
         const int N = d.N, nd = d.n_dopp;
-        const float *Gp = d.grid + (long long)p * nd * N;
+        const GNSS_GLOBAL float *Gp = gmem(d.grid) + (long long)p * nd * N;
         const int k = rr.doppler_bin, t = rr.code_phase;
         double y0 = Gp[(long long)k * N + t];
         double dc = parabola(Gp[(long long)k * N + (t - 1 + N) % N], y0, Gp[(long long)k * N + (t + 1) % N]);
         double dd = 0.0;
         if (k > 0 && k < nd - 1) dd = parabola(Gp[(long long)(k - 1) * N + t], y0, Gp[(long long)(k + 1) * N + t]);
         double fk = __dadd_rn(d.lo, __dmul_rn((double)k, d.step));
-        d.peaks[p].doppler_hz = __dadd_rn(fk, __dmul_rn(dd, d.step));
-        d.peaks[p].code_phase_frac = __dadd_rn((double)t, dc);
+        pk->doppler_hz = __dadd_rn(fk, __dmul_rn(dd, d.step));
+        pk->code_phase_frac = __dadd_rn((double)t, dc);
     }
 }
 
@@ -757,18 +1073,29 @@ static int occupancy(K kernel, int threads, int n_cu)
     return per_cu * n_cu;
 }
 
-static unsigned grid_for(long long work, long long cap)
+// Grid of a stage with `work` items: one workgroup per item, or, for a
+// persistent launch (or a stage too large for one grid), `cap` workgroups
+// that take items from the work counters.  At least one workgroup per XCD.
+static unsigned grid_for(long long work, long long cap, bool persistent)
 {
-    long long g = work < cap ? work : cap;
-    if (g < kXcds) g = kXcds;  // every XCD range gets a workgroup
+    long long g = work;
+    if ((persistent && g > cap) || g > 0x7fffffffLL) g = cap;
+    if (g < kXcds) g = kXcds;
     return (unsigned)g;
 }
 
-hipError_t launch_batch(const Launch &L, const uint32_t *d_lut, const float2 *d_tw,
-                        const float4 *d_cs, int2 *d_F, float4 *d_G, float *d_Q, int32_t *d_K,
+hipError_t launch_batch(const Launch &L, const Tables &T, int2 *d_F, void *d_G, float *d_Q, int32_t *d_K,
                         double *d_part, int n_cu, hipStream_t s, hipEvent_t *marks)
 {
+    const uint32_t *d_lut = T.lut;
+    const float2 *d_tw = T.tw;
+    const float4 *d_cs = T.cs;
+    const bool h = L.precision == GNSS_FP16;
+    // FP16: packed spectra, then the per-vector exponents
+    uint4 *d_Gh = (uint4 *)d_G;
+    int *d_E = (int *)((char *)d_G + g_spectra_bytes(L.total[kStVec], GNSS_FP16));
     hipError_t e;
+    const bool pers = L.persistent != 0;
     auto mark = [&](int i) -> hipError_t { return marks ? hipEventRecord(marks[i], s) : hipSuccess; };
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, L.hdr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -776,30 +1103,50 @@ hipError_t launch_batch(const Launch &L, const uint32_t *d_lut, const float2 *d_
     if (L.total[kStBox] > 0) {
         static int cap = 0;
         if (!cap) cap = occupancy(k_box, 256, n_cu);
-        hipLaunchKernelGGL(k_box, dim3(grid_for(L.total[kStBox], cap)), dim3(256), 0, s, L.reqs, L.hdr,
-                           L.pre, d_lut, d_F);
+        hipLaunchKernelGGL(k_box, dim3(grid_for(L.total[kStBox], cap, false)), dim3(256), 0, s, L.reqs,
+                           L.hdr, L.pre, d_lut, d_F);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if ((e = mark(1)) != hipSuccess) return e;
-    if (L.total[kStVec] > 0) {
+    if (L.total[kStVec] > 0 && !h) {
         static int cap = 0;
         if (!cap) cap = occupancy(k_fft_poly, 256, n_cu);
-        hipLaunchKernelGGL(k_fft_poly, dim3(grid_for((L.total[kStVec] + 3) / 4, cap)), dim3(256), 0, s,
-                           d_F, d_tw, d_G, L.hdr);
+        hipLaunchKernelGGL(k_fft_poly, dim3(grid_for((L.total[kStVec] + 3) / 4, cap, false)), dim3(256), 0,
+                           s, d_F, d_tw, (float4 *)d_G, L.hdr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else if (L.total[kStVec] > 0) {
+        static int cap = 0;
+        if (!cap) cap = occupancy(k_fft_poly_h, 256, n_cu);
+        hipLaunchKernelGGL(k_fft_poly_h, dim3(grid_for((L.total[kStVec] + 7) / 8, cap, false)), dim3(256), 0,
+                           s, d_F, (const hc2 *)T.tw_h, d_Gh, d_E, L.hdr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if ((e = mark(2)) != hipSuccess) return e;
-    if (L.total[kStCorr] > 0) {
+    if (L.total[kStCorr] > 0 && h) {
+        const float osc = ldexpf(1.f, 2 * T.cs_exp - 46);
+        if (L.corr_pt == 2) {
+            static int cap = 0;
+            if (!cap) cap = occupancy(k_corr_h<2>, 64 * kCorrWavesH, n_cu);
+            hipLaunchKernelGGL(k_corr_h<2>, dim3(grid_for(L.total[kStCorr], cap, pers)), dim3(64 * kCorrWavesH),
+                               0, s, L.reqs, L.hdr, L.pre, d_Gh, d_E, (const uint4 *)T.cs_h, (const hc2 *)T.tw_h, osc);
+        } else {
+            static int cap = 0;
+            if (!cap) cap = occupancy(k_corr_h<4>, 64 * kCorrWavesH, n_cu);
+            hipLaunchKernelGGL(k_corr_h<4>, dim3(grid_for(L.total[kStCorr], cap, pers)), dim3(64 * kCorrWavesH),
+                               0, s, L.reqs, L.hdr, L.pre, d_Gh, d_E, (const uint4 *)T.cs_h, (const hc2 *)T.tw_h, osc);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else if (L.total[kStCorr] > 0) {
         if (L.corr_pt == 2) {
             static int cap = 0;
             if (!cap) cap = occupancy(k_corr<2>, 64 * kCorrWaves, n_cu);
-            hipLaunchKernelGGL(k_corr<2>, dim3(grid_for(L.total[kStCorr], cap)), dim3(64 * kCorrWaves), 0, s,
-                               L.reqs, L.hdr, L.pre, d_G, d_cs, d_tw);
+            hipLaunchKernelGGL(k_corr<2>, dim3(grid_for(L.total[kStCorr], cap, pers)), dim3(64 * kCorrWaves),
+                               0, s, L.reqs, L.hdr, L.pre, (const float4 *)d_G, d_cs, d_tw);
         } else {
             static int cap = 0;
             if (!cap) cap = occupancy(k_corr<4>, 64 * kCorrWaves, n_cu);
-            hipLaunchKernelGGL(k_corr<4>, dim3(grid_for(L.total[kStCorr], cap)), dim3(64 * kCorrWaves), 0, s,
-                               L.reqs, L.hdr, L.pre, d_G, d_cs, d_tw);
+            hipLaunchKernelGGL(k_corr<4>, dim3(grid_for(L.total[kStCorr], cap, pers)), dim3(64 * kCorrWaves),
+                               0, s, L.reqs, L.hdr, L.pre, (const float4 *)d_G, d_cs, d_tw);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
@@ -807,14 +1154,15 @@ hipError_t launch_batch(const Launch &L, const uint32_t *d_lut, const float2 *d_
     {
         static int cap = 0;
         if (!cap) cap = occupancy(k_colmax, kPeakThreads, n_cu);
-        hipLaunchKernelGGL(k_colmax, dim3(grid_for(L.total[kStColmax], cap)), dim3(kPeakThreads), 0, s,
+        hipLaunchKernelGGL(k_colmax, dim3(grid_for(L.total[kStColmax], cap, false)), dim3(kPeakThreads), 0, s,
                            L.reqs, L.hdr, L.pre, d_Q, d_K, d_part);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_peak, dim3(grid_for(L.total[kStPeak], 4LL * n_cu)), dim3(kPeakThreads), 0, s,
-                           L.reqs, L.hdr, L.pre, d_Q, d_K, d_part);
+        hipLaunchKernelGGL(k_peak, dim3(grid_for(L.total[kStPeak], 4LL * n_cu, false)), dim3(kPeakThreads), 0,
+                           s, L.reqs, L.hdr, L.pre, d_Q, d_K, d_part);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_interp, dim3((unsigned)((L.total[kStPeak] + 63) / 64 > 0 ? (L.total[kStPeak] + 63) / 64 : 1)),
-                           dim3(64), 0, s, L.reqs, L.hdr, L.pre);
+        const long long ni = (L.total[kStPeak] + 63) / 64;
+        hipLaunchKernelGGL(k_interp, dim3((unsigned)(ni < 1 ? 1 : ni > 65536 ? 65536 : ni)), dim3(64), 0, s,
+                           L.reqs, L.hdr, L.pre);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return mark(4);

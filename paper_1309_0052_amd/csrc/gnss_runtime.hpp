@@ -47,7 +47,8 @@ struct Workspace {
 // A laid-out batch on the host.
 struct BatchHost {
     int n = 0;
-    int corr_pt = 4;
+    int corr_pt = 2;
+    int precision = GNSS_FP32;
     std::vector<gnss::ReqDesc> d;
     std::vector<long long> pre;
     std::vector<long long> grid_off;
@@ -69,6 +70,7 @@ struct gnss_ctx {
     int precision = GNSS_FP32;
     float threshold = 2.5f;
     int corr_pt_forced = 0; // 0: tuned / default
+    int persistent = 1;     // correlation grid: 1 occupancy-sized with work counters, 0 one workgroup per item
     int max_slots = 64;     // requests per served batch
     hipStream_t stream = nullptr;
     // tables
@@ -76,6 +78,9 @@ struct gnss_ctx {
     uint8_t *d_codes = nullptr; // [38][1023], row = PRN
     float2 *d_tw = nullptr;     // twiddles
     float4 *d_cs = nullptr;     // [38][1024] code spectra, storage order
+    void *d_tw_h = nullptr;     // FP16 contexts: packed twiddles
+    void *d_cs_h = nullptr;     //   code spectra * 2^-cs_exp, packed storage order
+    int cs_exp = 0;
     gnss_rt::Workspace ws;      // synchronous and device-buffer calls
     // autotuned PRN tile per sample-rate signature
     std::map<std::string, int> tuned_pt;
@@ -94,7 +99,7 @@ struct gnss_graph {
     gnss_ctx *ctx = nullptr;
     gnss_rt::Workspace ws;
     hipGraphExec_t exec = nullptr;
-    int corr_pt = 4;
+    int corr_pt = 2;
 };
 
 namespace gnss_rt {
@@ -114,7 +119,7 @@ void release_ws(gnss_ctx *c, Workspace &w);
 int make_plan(const gnss_request *r, gnss::Plan &p, bool need_outputs);
 int plan_all(const gnss_request *reqs, int n, std::vector<gnss::Plan> &plans);
 void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int corr_pt, float threshold,
-                 BatchHost &B);
+                 int precision, BatchHost &B);
 size_t meta_bytes(int n);
 size_t batch_device_bytes(const BatchHost &B);
 int stage_batch(gnss_ctx *c, Workspace &w, BatchHost &B, hipStream_t s, gnss::Launch &L);

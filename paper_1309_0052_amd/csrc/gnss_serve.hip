@@ -215,7 +215,7 @@ static int run_slot_once(gnss_ctx *c, Slot &sl)
         plans[i] = t->plan;
     }
     BatchHost B;
-    build_batch(plans.data(), reqs.data(), n, corr_ptile_for(c, plans.data(), n), c->threshold, B);
+    build_batch(plans.data(), reqs.data(), n, corr_ptile_for(c, plans.data(), n), c->threshold, c->precision, B);
     gnss::Launch L;
     if ((rc = stage_batch(c, sl.ws, B, sl.stream, L)) || (rc = launch(c, sl.ws, L, sl.stream, false))) return rc;
     HIP_TRY(hipMemcpyAsync(sl.h_peaks, sl.peaks.p, pb, hipMemcpyDeviceToHost, sl.stream));
@@ -380,7 +380,7 @@ int corr_ptile_for(gnss_ctx *c, const gnss::Plan *plans, int n)
 {
     if (c->corr_pt_forced) return c->corr_pt_forced;
     auto it = c->tuned_pt.find(rate_signature(plans, n));
-    return it != c->tuned_pt.end() ? it->second : 4;
+    return it != c->tuned_pt.end() ? it->second : 2;
 }
 
 static std::string device_key(int dev)
@@ -435,7 +435,7 @@ int gnss_submit(gnss_ctx *ctx, const gnss_request *req, uint64_t *ticket)
     t->sample_bytes = sample_bytes(p.fmt, (size_t)p.n_samples);
     BatchHost B;
     gnss_request r1 = *req;
-    build_batch(&p, &r1, 1, corr_ptile_for(ctx, &p, 1), ctx->threshold, B);
+    build_batch(&p, &r1, 1, corr_ptile_for(ctx, &p, 1), ctx->threshold, ctx->precision, B);
     t->need_bytes = batch_device_bytes(B) + t->sample_bytes + (size_t)p.n_prn * sizeof(gnss_peak) +
                     (req->out_grid ? (size_t)p.grid_elems() * sizeof(float) : 0);
     if (t->need_bytes > slot_budget(ctx))
@@ -517,7 +517,8 @@ int gnss_autotune(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, const 
     DeviceGuard g(ctx->device);
     if (g.rc) return g.rc;
     const std::string sig = rate_signature(plans.data(), n_req);
-    const std::string key = device_key(ctx->device) + "/" + sig;
+    const std::string key =
+        device_key(ctx->device) + (ctx->precision == GNSS_FP16 ? "/fp16/" : "/fp32/") + sig;
     std::map<std::string, int> cache;
     if (cache_path) cache_read(cache_path, cache);
     auto hit = cache.find(key);
@@ -532,7 +533,7 @@ int gnss_autotune(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, const 
         for (int pt : {2, 4}) {
             std::lock_guard<std::mutex> lk(ctx->mu);
             BatchHost B;
-            build_batch(plans.data(), reqs, n_req, pt, ctx->threshold, B);
+            build_batch(plans.data(), reqs, n_req, pt, ctx->threshold, ctx->precision, B);
             gnss::Launch L;
             if ((rc = stage_batch(ctx, ctx->ws, B, ctx->stream, L))) break;
             double ms_min = 1e30;

@@ -41,8 +41,11 @@ def assert_grid_close(P_gpu, P_ref, tol: float = GRID_TOL) -> float:
     return worst
 
 
-def compare_detections(gpu_peaks, ref_peaks, P_ref, threshold: float = 2.5):
-    """Returns the number of near-tie exemptions; raises on a real mismatch."""
+def compare_detections(gpu_peaks, ref_peaks, P_ref, threshold: float = 2.5, tie_rel: float = TIE_REL,
+                       value_rel: float = 1e-4):
+    """Returns the number of near-tie exemptions; raises on a real mismatch.
+    tie_rel: relative width of a near tie; value_rel: tolerance on the peak
+    and mean values."""
     exempt = 0
     for i, r in enumerate(ref_peaks):
         g = gpu_peaks[i]
@@ -50,14 +53,14 @@ def compare_detections(gpu_peaks, ref_peaks, P_ref, threshold: float = 2.5):
         same_cell = int(g["doppler_bin"]) == r.doppler_bin and int(g["code_phase"]) == r.code_phase
         same_det = bool(g["detected"]) == r.detected
         if same_cell:
-            assert abs(float(g["peak"]) - r.peak) <= 1e-4 * r.peak, (r.prn, g["peak"], r.peak)
-        assert abs(float(g["mean"]) - r.mean) <= 1e-4 * r.mean, (r.prn, g["mean"], r.mean)
+            assert abs(float(g["peak"]) - r.peak) <= value_rel * r.peak, (r.prn, g["peak"], r.peak)
+        assert abs(float(g["mean"]) - r.mean) <= value_rel * r.mean, (r.prn, g["mean"], r.mean)
         if same_cell and same_det:
             continue
         flat = np.asarray(P_ref[i], np.float64).ravel()
         v2, v1 = np.partition(flat, -2)[-2:]
-        near_cell = (v1 - v2) <= TIE_REL * v1
-        near_thr = abs(r.ratio - threshold) <= TIE_REL * threshold
+        near_cell = (v1 - v2) <= tie_rel * v1
+        near_thr = abs(r.ratio - threshold) <= tie_rel * threshold
         if (same_cell and near_thr) or near_cell:
             exempt += 1
             continue

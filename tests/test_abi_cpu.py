@@ -28,6 +28,14 @@ def test_every_declared_function_is_exported():
     assert set(names) == set(G.EXPORTED)
 
 
+def test_header_constants_match_binding():
+    text = open(os.path.join(ROOT, "include", "gnss_acq.h")).read()
+    consts = re.findall(r"^#define (GNSS_[A-Z0-9_]+) \(?(-?\d+)\)?", text, flags=re.M)
+    assert len(consts) >= 16
+    for name, val in consts:
+        assert getattr(G, name) == int(val), name
+
+
 def test_peak_struct_layout():
     assert ctypes.sizeof(G.gnss_peak) == 48
     assert G.gnss_peak.doppler_hz.offset == 32

@@ -266,13 +266,10 @@ def _run_device(ctx, snap, srch, grid_out=True):
     return grid, pk
 
 
-def test_strong_workload_full_size(ctx):
-    snap, srch = synth.strong_real_2bit(O.ca_code, seed=1)
+def test_strong_workload_full_size(ctx, strong_case):
+    snap, srch, nd, P = strong_case
     log("strong workload: real 2-bit 4.092 MHz, 32 PRN x 21 bins x 10 ms")
     grid, pk = _run_device(ctx, snap, srch)
-    nd = O.n_doppler(srch.lo, srch.hi, srch.step)
-    P = O.grid_fft(snap.samples, snap.fmt, snap.fs_hz, snap.f_if_hz, srch.prns, srch.lo, srch.step,
-                   nd, srch.T_coh, srch.N_noncoh)
     worst = assert_grid_close(grid, P)
     ref = O.peaks(P, srch.prns, 4, 2.5, srch.lo, srch.step)
     exempt = compare_detections(pk, ref, P)
@@ -291,14 +288,10 @@ def test_strong_workload_full_size(ctx):
 
 
 @pytest.mark.timeout(600)
-def test_weak_workload_full_size(ctx):
-    snap, srch = synth.weak_complex_int8(O.ca_code, seed=2)
+def test_weak_workload_full_size(ctx, weak_case):
+    snap, srch, nd, P = weak_case
     log("weak workload: complex int8 16.368 MHz, 32 PRN x 121 bins x 25 x 4 ms")
     grid, pk = _run_device(ctx, snap, srch)
-    log("  gpu done; oracle (FP64 FFT route) ...")
-    nd = O.n_doppler(srch.lo, srch.hi, srch.step)
-    P = O.grid_fft(snap.samples, snap.fmt, snap.fs_hz, snap.f_if_hz, srch.prns, srch.lo, srch.step,
-                   nd, srch.T_coh, srch.N_noncoh)
     worst = assert_grid_close(grid, P)
     ref = O.peaks(P, srch.prns, 16, 2.5, srch.lo, srch.step)
     exempt = compare_detections(pk, ref, P)
