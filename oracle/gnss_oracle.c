@@ -317,3 +317,72 @@ int orc_cells_direct(const void *samples, int fmt, int64_t n_samples, int64_t fs
     }
     return failed ? ORC_ENOMEM : ORC_OK;
 }
+
+/* ---------------------------------------------------------------------------
+ * Tracking correlators (the tracking channel of Fig. 3: carrier and code NCOs,
+ * the first mixing stage, then time-domain correlation with the code replica,
+ * Sec. 3).  The paper shows the channel only as a figure; the reading here is
+ * the usual early / prompt / late correlator set, with the NCOs in fixed point
+ * so that every result is an exact integer:
+ *
+ *   channel c: PRN, carrier step D (uint32, cycles * 2^32 per sample) and
+ *   initial phase phi0 (uint32, cycles * 2^32 at sample 0); code phase q0 and
+ *   code step R (int64, chips * 2^32 at sample 0 and per sample); early-late
+ *   offset dl (int64, chips * 2^32).
+ *   For global sample n:
+ *     phase(n) = (uint32)(phi0 + n * D),  y[n] = x[n] * (cosL - j sinL)[phase(n) >> 22]
+ *     q(n) = q0 + n * R
+ *     chip_X(n) = floor((q(n) + off_X) / 2^32) mod 1023 (mathematical mod),
+ *       off_E = +dl (replica advanced), off_P = 0, off_L = -dl
+ *     X_e = sum over n in epoch e of y[n] * (1 - 2 code[chip_X(n)])
+ *   Epoch e covers samples [start + e*len, start + (e+1)*len).
+ *   out[c][e][X][re, im], X = 0 early, 1 prompt, 2 late, int64.
+ * With phi0 = 0 the carrier and mixing are those of the acquisition oracle.
+ * ------------------------------------------------------------------------- */
+int orc_track(const void *samples, int fmt, int64_t n_samples, int n_ch, const int32_t *prn,
+              const uint32_t *D, const uint32_t *phi0, const int64_t *q0, const int64_t *R,
+              const int64_t *dl, int64_t start, int64_t len, int n_epochs, int64_t *out,
+              int nthreads)
+{
+    int16_t cosL[1024], sinL[1024];
+    if (!samples || !prn || !D || !phi0 || !q0 || !R || !dl || !out) return ORC_EINVAL;
+    if (fmt < 0 || fmt > 2 || n_ch < 1 || start < 0 || len < 1 || n_epochs < 1) return ORC_EINVAL;
+    if (start + len * (int64_t)n_epochs > n_samples) return ORC_EINVAL;
+    for (int c = 0; c < n_ch; c++)
+        if (prn[c] < 1 || prn[c] > 37) return ORC_EINVAL;
+    orc_lut(cosL, sinL);
+    (void)nthreads;
+#pragma omp parallel for schedule(dynamic) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int64_t ce = 0; ce < (int64_t)n_ch * n_epochs; ce++) {
+        const int c = (int)(ce / n_epochs), e = (int)(ce % n_epochs);
+        uint8_t code[1023];
+        orc_ca_code(prn[c], code);
+        int64_t acc[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+        const int64_t off[3] = {dl[c], 0, -dl[c]};
+        for (int64_t i = 0; i < len; i++) {
+            const int64_t n = start + (int64_t)e * len + i;
+            const uint32_t ph = (uint32_t)(phi0[c] + (uint32_t)((uint64_t)n * (uint64_t)D[c]));
+            const int idx = (int)(ph >> 22);
+            const int64_t cs = cosL[idx], sn = sinL[idx];
+            int64_t xr, xi;
+            orc_sample(samples, fmt, n, &xr, &xi);
+            const int64_t yr = xr * cs + xi * sn, yi = xi * cs - xr * sn;
+            const int64_t q = q0[c] + n * R[c];
+            for (int x = 0; x < 3; x++) {
+                int64_t v = q + off[x];
+                int64_t chip = v >= 0 ? v / 4294967296LL : -((-v + 4294967295LL) / 4294967296LL);
+                chip %= 1023;
+                if (chip < 0) chip += 1023;
+                const int64_t s = 1 - 2 * (int64_t)code[chip];
+                acc[x][0] += s * yr;
+                acc[x][1] += s * yi;
+            }
+        }
+        int64_t *o = out + ce * 6;
+        for (int x = 0; x < 3; x++) {
+            o[2 * x] = acc[x][0];
+            o[2 * x + 1] = acc[x][1];
+        }
+    }
+    return ORC_OK;
+}

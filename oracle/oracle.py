@@ -67,8 +67,10 @@ def _load():
         lib.orc_cells_direct.argtypes = [vp, ctypes.c_int, i64, i64, dbl, vp, ctypes.c_int,
                                          dbl, dbl, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                          vp, i64, vp, ctypes.c_int]
+        lib.orc_track.argtypes = [vp, ctypes.c_int, i64, ctypes.c_int, vp, vp, vp, vp, vp, vp, i64,
+                                  i64, ctypes.c_int, vp, ctypes.c_int]
         for f in (lib.orc_ca_code, lib.orc_code_replica, lib.orc_wipe, lib.orc_wipe_fold,
-                  lib.orc_grid_direct, lib.orc_cells_direct):
+                  lib.orc_grid_direct, lib.orc_cells_direct, lib.orc_track):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -297,3 +299,52 @@ def samples_per_chip(fs_hz: int) -> int:
     if fs_hz % CHIP_RATE_HZ:
         raise ValueError("fs is not a multiple of the chip rate")
     return int(fs_hz) // CHIP_RATE_HZ
+
+
+# ---------------------------------------------------------------------------
+# tracking correlators (Fig. 3)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Channel:
+    """One tracking channel in physical units."""
+    prn: int
+    carrier_hz: float          # carrier to remove: IF + Doppler
+    carrier_phase: float       # cycles at sample 0, [0, 1)
+    code_phase: float          # chips at sample 0, [0, 1023)
+    code_rate: float           # chips per second
+    spacing: float            # early-late offset, chips, (0, 1]
+
+
+def track_fixed(ch: Channel, fs_hz: int):
+    """Fixed-point NCO words of a channel: (D, phi0, q0, R, dl).  Each is the
+    value times 2^32 rounded half away from zero (llround), computed in IEEE
+    double as written: carrier step from carrier_hz * 2^32 / fs."""
+    D = int(np.int64(_llround(ch.carrier_hz * 4294967296.0 / float(fs_hz)))) & 0xFFFFFFFF
+    phi0 = int(np.int64(_llround(ch.carrier_phase * 4294967296.0))) & 0xFFFFFFFF
+    q0 = _llround(ch.code_phase * 4294967296.0)
+    R = _llround(ch.code_rate * 4294967296.0 / float(fs_hz))
+    dl = _llround(ch.spacing * 4294967296.0)
+    return D, phi0, q0, R, dl
+
+
+def _llround(x: float) -> int:
+    return int(math.floor(x + 0.5)) if x >= 0 else -int(math.floor(-x + 0.5))
+
+
+def track(samples, fmt, fs_hz, channels, start, length, n_epochs, threads: int | None = None):
+    """Early/prompt/late correlators, int64 [n_ch][n_epochs][3][2] (re, im)."""
+    s = np.ascontiguousarray(samples)
+    words = [track_fixed(c, fs_hz) for c in channels]
+    prn = np.ascontiguousarray([c.prn for c in channels], np.int32)
+    D = np.ascontiguousarray([w[0] for w in words], np.uint32)
+    phi0 = np.ascontiguousarray([w[1] for w in words], np.uint32)
+    q0 = np.ascontiguousarray([w[2] for w in words], np.int64)
+    R = np.ascontiguousarray([w[3] for w in words], np.int64)
+    dl = np.ascontiguousarray([w[4] for w in words], np.int64)
+    out = np.zeros((len(channels), n_epochs, 3, 2), np.int64)
+    _check(_load().orc_track(_ptr(s), int(fmt), n_samples_of(s, fmt), len(channels), _ptr(prn),
+                             _ptr(D), _ptr(phi0), _ptr(q0), _ptr(R), _ptr(dl), int(start),
+                             int(length), int(n_epochs), _ptr(out), int(threads or n_threads())),
+           "track")
+    return out
