@@ -33,6 +33,8 @@ if ROOT not in sys.path:
 # and FP16 with packed FP16 instructions, both 256 flop/clock/CU
 PEAK_VALU_TFLOPS = {"fp32": 157.3, "fp16": 157.3}
 PEAK_HBM_GBS = 8000.0
+# integer VALU: 256 CU x 64 lanes x 2.4 GHz, a multiply-add counted as 2 ops
+PEAK_INT_TOPS = 78.6
 DTYPE = {"fp32": "f32", "fp16": "f16"}
 CORR_KERNEL = {"fp32": "k_corr", "fp16": "k_corr_h"}
 
@@ -110,11 +112,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="weak", choices=["weak", "strong", "batch", "serve"])
+    ap.add_argument("--workload", default="weak", choices=["weak", "strong", "batch", "serve", "track"])
     ap.add_argument("--batch-n", type=int, default=256, help="snapshots in the batch workload")
     ap.add_argument("--rates", default="50,200,800", help="serve: Poisson arrival rates, req/s")
-    ap.add_argument("--serve-n", type=int, default=300, help="serve: timed requests per rate")
-    ap.add_argument("--serve-warmup", type=int, default=40, help="serve: untimed requests per rate")
+    ap.add_argument("--serve-n", type=int, default=2000, help="serve: timed requests per rate")
+    ap.add_argument("--serve-warmup", type=int, default=200, help="serve: untimed requests per rate")
     ap.add_argument("--serve-kind", default="mixed", choices=["mixed", "strong"],
                     help="serve: heterogeneous batch-style requests or strong-signal snapshots")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget")
@@ -166,6 +168,8 @@ def main():
 
     if args.workload == "batch":
         return run_batch(args, G, torch, ctx, code_fn)
+    if args.workload == "track":
+        return run_track(args, G, torch, ctx, code_fn)
     if args.workload == "serve":
         return run_serve(args, G, torch, ctx, code_fn)
 
@@ -376,6 +380,7 @@ def run_serve(args, G, torch, ctx, code_fn):
         done_at = np.zeros(n_total)
         batch_sizes = np.zeros(n_total, np.int64)
         tickets = [None] * n_total
+        refused = np.zeros(n_total, bool)
         outs = [None] * n_total
         ready = threading.Semaphore(0)
         errors = []
@@ -383,6 +388,8 @@ def run_serve(args, G, torch, ctx, code_fn):
         def collector():
             for i in range(n_total):
                 ready.acquire()
+                if tickets[i] is None:  # refused at submission
+                    continue
                 try:
                     info = sctx.wait(tickets[i], 600.0)
                     # completion time from the library's own clock of the ticket
@@ -407,23 +414,33 @@ def run_serve(args, G, torch, ctx, code_fn):
                 time.sleep(min(0.0005, sched[i] - now))
             outs[i] = (pk, req)
             submit_at[i] = time.perf_counter()
-            tickets[i] = sctx.submit(req)
+            try:
+                tickets[i] = sctx.submit(req)
+            except G.GnssError as e:
+                if e.code != G.GNSS_ENOMEM:
+                    raise
+                refused[i] = True  # larger than a batch slot's share of the HBM budget
             ready.release()
         th.join()
         sctx.close()
         if errors:
             raise SystemExit("serving errors: %s" % errors[:3])
         w = args.serve_warmup
-        lat = (done_at[w:] - t0) - sched[w:]
-        span = done_at[w:].max() - (t0 + sched[w])
-        cells = float(sum(prepared[j][4] for j in picks[w:]))
-        results.append({"rate_req_s": rate, "requests": int(args.serve_n),
+        ok = ~refused[w:]
+        lat = ((done_at[w:] - t0) - sched[w:])[ok]
+        span = done_at[w:][ok].max() - (t0 + sched[w])
+        n_ok = int(ok.sum())
+        cells = float(sum(prepared[j][4] for j, good in zip(picks[w:], ok) if good))
+        results.append({"rate_req_s": rate, "requests": int(args.serve_n), "refused": int((~ok).sum()),
                         "p50_ms": float(np.percentile(lat, 50) * 1e3),
                         "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                        "snapshots_per_s": float(args.serve_n / span),
+                        "snapshots_per_s": float(n_ok / span),
                         "cells_per_s": cells / span,
-                        "effective_running_time_ms": float(span / args.serve_n * 1e3),
-                        "mean_batch": float(batch_sizes[w:].mean())})
+                        "effective_running_time_ms": float(span / n_ok * 1e3),
+                        "mean_batch": float(batch_sizes[w:][ok].mean())})
+        print("serve rate %.0f req/s: p50 %.1f ms, p99 %.1f ms, %.0f snapshots/s, %d refused"
+              % (rate, results[-1]["p50_ms"], results[-1]["p99_ms"], results[-1]["snapshots_per_s"],
+                 results[-1]["refused"]), file=sys.stderr, flush=True)
     top = results[-1]
     out = {
         "metric": "search cells/s (PRNxDopplerxphasexms) + p50/p99 latency/snapshot",
@@ -431,12 +448,105 @@ def run_serve(args, G, torch, ctx, code_fn):
         "warmup": int(args.serve_warmup), "ms_per_step": top["effective_running_time_ms"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[args.precision],
         "data": "synthetic",
-        "config": {"workload": "served open-loop Poisson arrivals of %s, HBM budget %.0f GB"
-                               % (kind, args.budget_gb), "rates_req_s": rates},
+        "config": {"workload": "served open-loop Poisson arrivals of %s, HBM budget %g GB"
+                               % (kind, args.budget_gb), "rates_req_s": rates, "precision": args.precision,
+                   "budget_gb": args.budget_gb, "kind": args.serve_kind},
         "latency_ms": {"p50": top["p50_ms"], "p99": top["p99_ms"]},
         "serving": results,
         "source_hash": kernel_source_hash(),
     }
+    print(json.dumps(out), flush=True)
+
+
+def run_track(args, G, torch, ctx, code_fn):
+    """Early/prompt/late tracking correlators: 32 records x 12 channels x
+    100 ms at 16.368 MHz complex int8, 1 ms epochs, one launch per step."""
+    import numpy as np
+    import synth
+
+    fs, ms, n_rec, n_ch = 16368000, 100.0, 32, 12
+    f_l1 = 1575.42e6
+    rng = np.random.default_rng(9)
+    t_gen = time.perf_counter()
+    recs = []
+    for i in range(n_rec):
+        prns = rng.choice(np.arange(1, 33), size=n_ch, replace=False)
+        pl = [synth.Planted(prn=int(p), code_phase=int(rng.integers(0, fs // 1000)),
+                            doppler_hz=float(rng.uniform(-4000, 4000)), cn0_dbhz=float(rng.uniform(35, 48)),
+                            carrier_phase=float(rng.uniform(0, 2 * np.pi)), nav_bits=True,
+                            nav_phase_ms=int(rng.integers(0, 20))) for p in prns[:8]]
+        snap = synth.make_snapshot(900 + i, synth.CPLX_I8, fs, 0.0, ms, pl, code_fn)
+        chans = []
+        for j, p in enumerate(prns):
+            if j < len(pl):  # a channel on each planted satellite's true parameters
+                f_d = pl[j].doppler_hz
+                cp = (1023.0 - pl[j].code_phase / 16.0) % 1023.0
+            else:
+                f_d = float(rng.uniform(-4000, 4000))
+                cp = float(rng.uniform(0, 1023))
+            chans.append((int(p), f_d, 0.0, cp, 1023000.0 * (1 + f_d / f_l1), 0.5))
+        recs.append((snap, chans))
+    t_gen = time.perf_counter() - t_gen
+    epoch, n_ep = fs // 1000, int(ms)
+    bufs, reqs = [], []
+    for snap, chans in recs:
+        x = torch.from_numpy(np.ascontiguousarray(snap.samples)).cuda()
+        o = torch.zeros(n_ch * n_ep * 6, dtype=torch.int64, device="cuda")
+        bufs.append((x, o))
+        reqs.append(G.make_track_request(x.data_ptr(), snap.fmt, snap.n, fs, chans, 0, epoch, n_ep, o.data_ptr()))
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        ctx.track_device(reqs, stream)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(args.steps):
+        ctx.track_device(reqs, stream)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t0
+    lat = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
+    ms_step = ev[0].elapsed_time(ev[-1]) / args.steps
+    units = n_rec * n_ch * epoch * n_ep  # sample-channels per step
+    # algorithmic integer ops per sample-channel: carrier mixing (4 multiplies,
+    # 2 adds) and three complex correlator accumulations (+-y: 6 adds)
+    ops_unit = 12.0
+    achieved = units * ops_unit / (ms_step / 1e3) / 1e12
+    # the planted channels' prompt power against their early/late
+    o = bufs[0][1].cpu().numpy().reshape(n_ch, n_ep, 3, 2).astype(np.float64)
+    pw = (o ** 2).sum(axis=3).sum(axis=1)
+    out = {
+        "metric": "correlator sample-channels/s (early/prompt/late)", "value": units / (ms_step / 1e3),
+        "unit": "sample-channels/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32/int64", "data": "synthetic",
+        "config": {"workload": "tracking correlators: %d records x %d channels x %d ms, 16.368 MHz complex "
+                               "int8, 1 ms epochs, spacing 0.5 chip; one launch per step" % (n_rec, n_ch, n_ep),
+                   "records": n_rec, "channels": n_ch, "epochs": n_ep},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "wall_s": wall_s, "generate_s": t_gen,
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_INT_TOPS, "unit": "Tops/s",
+                     "frac": round(achieved / PEAK_INT_TOPS, 4), "traffic": read_traffic("track", "track"),
+                     "kernel": "k_track", "avg_launch_ms": round(ms_step, 4)},
+        "planted_prompt_over_early_late": float(np.min(pw[:8, 1] / np.maximum(pw[:8, 0], pw[:8, 2]))),
+        "source_hash": kernel_source_hash(),
+    }
+    if not args.no_cpu_baseline:
+        # the oracle over whole records (all channels, all epochs) until the time target
+        import oracle as O
+        threads = O.n_threads()
+        done, t1 = 0, time.perf_counter()
+        while done == 0 or (time.perf_counter() - t1 < args.cpu_seconds and done < 4 * n_rec):
+            snap, chans = recs[done % n_rec]
+            O.track(snap.samples, snap.fmt, fs, [O.Channel(*c) for c in chans], 0, epoch, n_ep, threads=threads)
+            done += 1
+        dt = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": done * n_ch * epoch * n_ep / dt, "unit": "sample-channels/s",
+                               "cores": threads, "kind": "oracle",
+                               "sample": "%d records x %d channels x %d ms (the workload's own records), %.1f s"
+                                         % (done, n_ch, n_ep, dt)}
+    ctx.close()
     print(json.dumps(out), flush=True)
 
 

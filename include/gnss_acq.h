@@ -235,6 +235,56 @@ int gnss_peaks(gnss_ctx *ctx, const float *d_grid, const int32_t *prn_list, int3
                int32_t n_dopp, int32_t N, int32_t spc, double doppler_lo, double doppler_step,
                gnss_peak *d_peaks, void *stream);
 
+/* ---- tracking correlators ----------------------------------------------- */
+/* One tracking channel (the tracking channel of Fig. 3: carrier and code
+ * NCOs, first mixing stage, time-domain correlation with the code replica;
+ * Sec. 3 names that correlation as the tracking loops' main cost).  The
+ * paper gives no further detail; the correlators are the usual early /
+ * prompt / late set.  Values are physical; the library turns each into a
+ * fixed-point word (value * 2^32 rounded half away from zero, in IEEE double
+ * as written; the carrier step is carrier_hz * 2^32 / fs), so results are
+ * exact integers:
+ *   carrier phase(n) = (uint32)(phi0 + n * D), y[n] = x[n] * (cosL - j sinL)[phase >> 22]
+ *   (the LUT of gnss_nco_lut); code phase q(n) = q0 + n * R (chips * 2^32);
+ *   chip_X(n) = floor((q(n) + off_X) / 2^32) mod 1023 with off = +dl (early),
+ *   0 (prompt), -dl (late); X_e = sum over epoch e of y[n] (1 - 2 code[chip_X(n)]). */
+typedef struct gnss_channel {
+    int32_t prn;           /* 1..37                                              */
+    double carrier_hz;     /* carrier to remove (IF + Doppler), Hz               */
+    double carrier_phase;  /* cycles at the record's first sample, [0, 1)        */
+    double code_phase;     /* chips at the record's first sample, [0, 1023)      */
+    double code_rate;      /* chips per second, (0, 1023 fs / 256]               */
+    double spacing;        /* early / late offset from prompt, chips, (0, 1]     */
+} gnss_channel;
+
+/* A batch entry: one record, its channels and the epochs to correlate.
+ * Epoch e covers samples [start + e epoch_len, start + (e + 1) epoch_len). */
+typedef struct gnss_track_request {
+    const void *samples;          /* record (host for gnss_track, device for _device) */
+    int32_t fmt;                  /* sample format, as for gnss_request               */
+    size_t n;                     /* samples in the record                            */
+    double fs;                    /* sample rate, Hz                                  */
+    const gnss_channel *channels; /* host memory, n_channels entries (1..256)        */
+    int32_t n_channels;
+    int64_t start;                /* first sample of epoch 0                          */
+    int32_t epoch_len;            /* samples per epoch, 1..2^24                       */
+    int32_t n_epochs;             /* >= 1; start + n_epochs epoch_len <= n            */
+    int64_t *out;                 /* [n_channels][n_epochs][3][2] int64: early,
+                                     prompt, late, each (re, im)                      */
+} gnss_track_request;
+
+/* Synchronous tracking correlators on host buffers (default context, locked;
+ * thread-safe).  Errors: GNSS_EINVAL (a bad field, or a code phase that would
+ * pass 2^30 chips over the record), GNSS_ENOMEM, GNSS_EDEVICE. */
+int gnss_track(const gnss_track_request *req);
+
+/* Tracking correlators of n_req requests (device samples and outputs) in one
+ * launch, one workgroup per (request, epoch), enqueued on `stream` (NULL =
+ * the HIP null stream); returns without waiting.  Calls on one context must
+ * not overlap on different streams.  Errors: as gnss_track; a bad request
+ * reports its index. */
+int gnss_track_device(gnss_ctx *ctx, const gnss_track_request *reqs, int32_t n_req, void *stream);
+
 /* ---- per-stage device timing -------------------------------------------- */
 #define GNSS_STAGE_WIPE_FOLD 0  /* carrier NCO, mixing, fold, boxcar, polyphase */
 #define GNSS_STAGE_FFT 1        /* forward FFT of the mixed blocks              */

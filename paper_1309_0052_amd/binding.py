@@ -37,7 +37,7 @@ EXPORTED = [
     "gnss_nco_lut", "gnss_wipe_fold", "gnss_fft2048", "gnss_peaks", "gnss_stage_times",
     "gnss_strerror", "gnss_last_error", "gnss_acquire_batch_device", "gnss_graph_create",
     "gnss_graph_launch", "gnss_graph_destroy", "gnss_autotune", "gnss_submit", "gnss_poll",
-    "gnss_wait",
+    "gnss_wait", "gnss_track", "gnss_track_device",
 ]
 
 GNSS_STAGE_WIPE_FOLD = 0
@@ -78,6 +78,20 @@ class gnss_request(ctypes.Structure):
                 ("out_peaks", ctypes.c_void_p)]
 
 
+class gnss_channel(ctypes.Structure):
+    _fields_ = [("prn", ctypes.c_int32), ("carrier_hz", ctypes.c_double),
+                ("carrier_phase", ctypes.c_double), ("code_phase", ctypes.c_double),
+                ("code_rate", ctypes.c_double), ("spacing", ctypes.c_double)]
+
+
+class gnss_track_request(ctypes.Structure):
+    _fields_ = [("samples", ctypes.c_void_p), ("fmt", ctypes.c_int32), ("n", ctypes.c_size_t),
+                ("fs", ctypes.c_double), ("channels", ctypes.POINTER(gnss_channel)),
+                ("n_channels", ctypes.c_int32), ("start", ctypes.c_int64),
+                ("epoch_len", ctypes.c_int32), ("n_epochs", ctypes.c_int32),
+                ("out", ctypes.c_void_p)]
+
+
 class gnss_ticket_info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("batch_size", ctypes.c_int32),
                 ("queued_s", ctypes.c_double), ("run_s", ctypes.c_double),
@@ -115,6 +129,8 @@ def _load() -> ctypes.CDLL:
         "gnss_poll": [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int),
                       ctypes.POINTER(gnss_ticket_info)],
         "gnss_wait": [vp, ctypes.c_uint64, dbl, ctypes.POINTER(gnss_ticket_info)],
+        "gnss_track": [ctypes.POINTER(gnss_track_request)],
+        "gnss_track_device": [vp, ctypes.POINTER(gnss_track_request), i32, vp],
         "gnss_strerror": [ctypes.c_int],
         "gnss_last_error": [],
     }
@@ -215,6 +231,44 @@ def make_request(samples_ptr: int, fmt: int, n: int, fs: float, f_if: float, prn
     return r
 
 
+def make_track_request(samples_ptr: int, fmt: int, n: int, fs: float, channels, start: int,
+                       epoch_len: int, n_epochs: int, out_ptr: int | None):
+    """Builds a gnss_track_request.  channels: sequence of objects with prn,
+    carrier_hz, carrier_phase, code_phase, code_rate, spacing (or tuples in
+    that order); the channel array is kept alive on the returned object."""
+    arr = (gnss_channel * len(channels))()
+    for i, c in enumerate(channels):
+        v = c if isinstance(c, (tuple, list)) else (c.prn, c.carrier_hz, c.carrier_phase, c.code_phase,
+                                                     c.code_rate, c.spacing)
+        arr[i] = gnss_channel(int(v[0]), float(v[1]), float(v[2]), float(v[3]), float(v[4]), float(v[5]))
+    r = gnss_track_request()
+    r.samples = samples_ptr
+    r.fmt = int(fmt)
+    r.n = int(n)
+    r.fs = float(fs)
+    r.channels = ctypes.cast(arr, ctypes.POINTER(gnss_channel))
+    r.n_channels = len(channels)
+    r.start = int(start)
+    r.epoch_len = int(epoch_len)
+    r.n_epochs = int(n_epochs)
+    r.out = out_ptr
+    r._ch_keepalive = arr
+    return r
+
+
+def gnss_track(samples: np.ndarray, fmt: int, fs: float, channels, start: int, epoch_len: int,
+               n_epochs: int, n: int | None = None) -> np.ndarray:
+    """Synchronous early/prompt/late correlators on a host record: int64
+    [n_channels][n_epochs][3][2] (early, prompt, late; re, im)."""
+    s = np.ascontiguousarray(samples)
+    n_samp = int(n if n is not None else _n_samples(s, fmt))
+    out = np.zeros((len(channels), max(int(n_epochs), 0), 3, 2), np.int64)
+    r = make_track_request(s.ctypes.data, fmt, n_samp, fs, channels, start, epoch_len, n_epochs,
+                           out.ctypes.data)
+    _check(_lib.gnss_track(ctypes.byref(r)))
+    return out
+
+
 def gnss_workspace_bytes(req: gnss_request) -> int:
     out = ctypes.c_size_t(0)
     _check(_lib.gnss_workspace_bytes(ctypes.byref(req), ctypes.byref(out)))
@@ -268,6 +322,13 @@ class Context:
         cnt = (ctypes.c_int64 * GNSS_N_STAGES)()
         _check(_lib.gnss_stage_times(self.handle, ms, cnt, GNSS_N_STAGES, 1 if reset else 0))
         return {STAGE_NAMES[i]: (ms[i], cnt[i]) for i in range(GNSS_N_STAGES)}
+
+    def track_device(self, reqs, stream=None):
+        """Tracking correlators of gnss_track_request(s) on device buffers."""
+        if isinstance(reqs, gnss_track_request):
+            reqs = [reqs]
+        arr = (gnss_track_request * len(reqs))(*reqs)
+        _check(_lib.gnss_track_device(self.handle, arr, len(reqs), _stream_ptr(stream)))
 
     # -- batches, graphs, autotuning ----------------------------------------
     def acquire_batch_device(self, reqs, stream=None):

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgnss_acq.so")
-SOURCES = ["gnss_kernels.hip", "gnss_api.hip", "gnss_serve.hip"]
+SOURCES = ["gnss_kernels.hip", "gnss_api.hip", "gnss_serve.hip", "gnss_track.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

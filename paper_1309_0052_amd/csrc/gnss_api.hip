@@ -92,7 +92,7 @@ void release(gnss_ctx *c, DevBuf &b)
 void release_ws(gnss_ctx *c, Workspace &w)
 {
     if (w.stage_ev) (void)hipEventSynchronize(w.stage_ev);
-    for (DevBuf *b : {&w.F, &w.G, &w.Q, &w.K, &w.part, &w.grid, &w.meta, &w.samples, &w.peaks})
+    for (DevBuf *b : {&w.F, &w.G, &w.Q, &w.K, &w.part, &w.grid, &w.meta, &w.samples, &w.peaks, &w.tmeta, &w.tout})
         release(c, *b);
     if (w.h_stage) (void)hipHostFree(w.h_stage);
     if (w.stage_ev) (void)hipEventDestroy(w.stage_ev);
@@ -193,7 +193,6 @@ void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int c
         d.Tc = p.Tc;
         d.Nnc = p.Nnc;
         d.n_prn = p.n_prn;
-        d.n_chunks_box = (int)cdiv(p.N, gnss::kBoxChunk);
         d.n_items = p.n_dopp * p.spc;
         d.n_ptiles = (int)cdiv(p.n_prn, corr_pt);
         d.n_tau_blk = (int)cdiv(p.N, gnss::kPeakThreads);
@@ -204,7 +203,7 @@ void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int c
             grid_int += p.grid_elems();
         }
         const long long cnt[gnss::kNumStages] = {
-            (long long)p.n_dopp * p.Nnc * d.n_chunks_box, p.n_vec(),
+            (long long)p.n_dopp * p.Nnc, p.n_vec(),
             (long long)d.n_ptiles * cdiv(d.n_items, corr_w), (long long)p.n_prn * d.n_tau_blk, (long long)p.n_prn};
         for (int st = 0; st < gnss::kNumStages; ++st) {
             B.pre[(size_t)st * (n + 1) + r] = tot[st];
@@ -441,6 +440,17 @@ DeviceGuard::~DeviceGuard()
 
 static std::mutex g_default_mu;
 static gnss_ctx *g_default = nullptr;
+
+int default_ctx(gnss_ctx **out)
+{
+    std::lock_guard<std::mutex> dlk(g_default_mu);
+    if (!g_default) {
+        int rc = gnss_ctx_create(&g_default, 0, 0, GNSS_FP32);
+        if (rc) return rc;
+    }
+    *out = g_default;
+    return GNSS_OK;
+}
 
 }  // namespace gnss_rt
 

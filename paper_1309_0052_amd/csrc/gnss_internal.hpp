@@ -82,7 +82,6 @@ struct ReqDesc {
     long long part_off;   // offset in the partial sums (n_prn * n_tau_blk)
     double fs, f_if, lo, step;
     int fmt, N, spc, n_dopp, Tc, Nnc, n_prn;
-    int n_chunks_box;     // 2048-sample chunks per (Doppler, block)
     int n_items;          // (Doppler, phase) items = n_dopp * spc
     int n_ptiles;         // PRN tiles of the correlation kernel
     int n_tau_blk;        // 256-lag blocks of the detection kernels
@@ -131,6 +130,27 @@ hipError_t launch_wipe_fold(const void *d_samples, const Plan &p, const uint32_t
                             int32_t *d_out /*[n_dopp][Nnc][N][2]*/, hipStream_t s);
 // detection on a caller's grid (stage entry point)
 size_t peak_scratch_part_elems(const Plan &p);
+
+// ---------------------------------------------------------------------------
+// tracking correlators (early / prompt / late)
+// ---------------------------------------------------------------------------
+// Fixed-point NCO words of one channel.
+struct TrackCh {
+    uint32_t D, phi0;     // carrier step and initial phase, cycles * 2^32
+    long long q0, R, dl;  // code phase at sample 0, code step, early-late offset, chips * 2^32
+    int prn, pad;
+};
+// One tracking request as the kernel sees it.
+struct TrackDesc {
+    const void *samples;
+    long long *out;       // [n_ch][n_epochs][3][2]
+    long long start;      // first sample of epoch 0
+    int fmt, epoch_len, n_epochs, n_ch, ch_off;
+};
+constexpr int kTrackThreads = 256;
+constexpr int kTrackCG = 4;  // channels per pass over an epoch
+hipError_t launch_track(const TrackDesc *d_reqs, const long long *d_pre, int n_req, long long total,
+                        const TrackCh *d_ch, const uint8_t *d_codes, const uint32_t *d_lut, hipStream_t s);
 
 // test entry: natural-order batched 2048-point transforms
 hipError_t launch_fft_test(const float2 *d_in, float2 *d_out, int batch, int inverse,

@@ -377,9 +377,9 @@ __device__ __forceinline__ long long next_item(BatchHdr *h, int stage, long long
 // ===========================================================================
 // stage A1: wipe + fold, then the one-chip boxcar
 // F[n] = sum_{t<spc} f[(n+t) mod N], written split by phase:
-// F[vec(k, b, s)][m] = F[spc m + s] (m < 1023), [..][1023] = 0.  Each work item
-// covers kBoxChunk outputs of one (request, Doppler, block) and wipes the
-// spc - 1 samples past it as a halo.  All integer, exact.
+// F[vec(k, b, s)][m] = F[spc m + s] (m < 1023), [..][1023] = 0.  A work item is
+// one (request, Doppler, block), done in chunks of kBoxChunk outputs, each
+// wiping the spc - 1 samples past it as a halo.  All integer, exact.
 // ===========================================================================
 constexpr int kBoxRun = 8;
 __device__ __forceinline__ int bpad(int i) { return i + (i >> 3); }  // bank-conflict padding
@@ -400,50 +400,50 @@ __global__ __launch_bounds__(256) void k_box(const ReqDesc *__restrict__ R, Batc
         if (it < 0) break;
         const int r = find_req(pst, n_req, it);
         const ReqDesc &d = R[r];
-        const long long local = it - pst[r];
-        const int chunk = (int)(local % d.n_chunks_box);
-        const int kb = (int)(local / d.n_chunks_box);
-        const int k = kb / d.Nnc, b = kb % d.Nnc;
+        const int kb = (int)(it - pst[r]);  // (Doppler, block); < 2^31 by the plan checks
+        const int k = kb / d.Nnc, b = kb - (kb / d.Nnc) * d.Nnc;
         const int N = d.N, spc = d.spc;
         const uint32_t D = nco_step(d.fs, d.f_if, d.lo, d.step, k);
-        const int n0 = chunk * kBoxChunk;
-        const int cnt = min(kBoxChunk, N - n0);
-        const int len = cnt + spc - 1;
-        for (int i = threadIdx.x; i < len; i += 256) {
-            int n = n0 + i;
-            if (n >= N) n -= N;
-            s_f[bpad(i)] = wipe_fold_one(d.samples, d.fmt, N, d.Tc, s_lut, D, b, n);
-        }
-        __syncthreads();
         int2 *dst = F + (d.vec_off + (long long)kb * spc) * kPolyLen;
-        const int n_runs = (cnt + kBoxRun - 1) / kBoxRun;
-        for (int rr = threadIdx.x; rr < n_runs; rr += 256) {
-            const int i0 = rr * kBoxRun;
-            int sx = 0, sy = 0;
-            for (int t = 0; t < spc; ++t) {
-                int2 v = s_f[bpad(i0 + t)];
-                sx += v.x;
-                sy += v.y;
+        for (int n0 = 0; n0 < N; n0 += kBoxChunk) {
+            const int cnt = min(kBoxChunk, N - n0);
+            const int len = cnt + spc - 1;
+            __syncthreads();  // LUT staged / previous chunk's boxcar done
+            for (int i = threadIdx.x; i < len; i += 256) {
+                int n = n0 + i;
+                if (n >= N) n -= N;
+                s_f[bpad(i)] = wipe_fold_one(d.samples, d.fmt, N, d.Tc, s_lut, D, b, n);
             }
-            const int n = n0 + i0;
-            int m = n / spc, s = n - m * spc;
-#pragma unroll
-            for (int j = 0; j < kBoxRun; ++j) {
-                const int i = i0 + j;
-                if (i >= cnt) break;
-                dst[s * kPolyLen + m] = make_int2(sx, sy);
-                if (i + 1 < cnt) {
-                    int2 vi = s_f[bpad(i + spc)], vo = s_f[bpad(i)];
-                    sx += vi.x - vo.x;
-                    sy += vi.y - vo.y;
+            __syncthreads();
+            const int n_runs = (cnt + kBoxRun - 1) / kBoxRun;
+            for (int rr = threadIdx.x; rr < n_runs; rr += 256) {
+                const int i0 = rr * kBoxRun;
+                int sx = 0, sy = 0;
+                for (int t = 0; t < spc; ++t) {
+                    int2 v = s_f[bpad(i0 + t)];
+                    sx += v.x;
+                    sy += v.y;
                 }
-                if (++s == spc) {
-                    s = 0;
-                    ++m;
+                const int n = n0 + i0;
+                int m = n / spc, s = n - m * spc;
+#pragma unroll
+                for (int j = 0; j < kBoxRun; ++j) {
+                    const int i = i0 + j;
+                    if (i >= cnt) break;
+                    dst[s * kPolyLen + m] = make_int2(sx, sy);
+                    if (i + 1 < cnt) {
+                        int2 vi = s_f[bpad(i + spc)], vo = s_f[bpad(i)];
+                        sx += vi.x - vo.x;
+                        sy += vi.y - vo.y;
+                    }
+                    if (++s == spc) {
+                        s = 0;
+                        ++m;
+                    }
                 }
             }
         }
-        if (chunk == 0 && threadIdx.x < spc) dst[threadIdx.x * kPolyLen + (kPolyLen - 1)] = make_int2(0, 0);
+        if (threadIdx.x < spc) dst[threadIdx.x * kPolyLen + (kPolyLen - 1)] = make_int2(0, 0);
     }
 }
 
@@ -1166,6 +1166,168 @@ hipError_t launch_batch(const Launch &L, const Tables &T, int2 *d_F, void *d_G, 
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return mark(4);
+}
+
+// ===========================================================================
+// tracking correlators (the tracking channel's carrier and code NCOs, first
+// mixing stage and time-domain correlation, Fig. 3): early / prompt / late
+// sums per (request, channel, epoch), exact in integers.
+// ===========================================================================
+constexpr long long kCodeFix = 1023LL << 32;  // one code period, chips * 2^32
+
+// 64-bit sum over the workgroup; the result is valid in thread 0.
+__device__ __forceinline__ long long block_sum64(long long v, long long *s_red)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) s_red[w] = v;
+    __syncthreads();
+    long long t = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kTrackThreads / 64; ++i) t += s_red[i];
+    return t;
+}
+
+// Code replicas of a pass as +-1 bytes with one chip of wrap-around on each
+// side: s_sign[c][i] = 1 - 2 code[(i - 1) mod 1023], i in [0, 1024], so the
+// early (chip in [0, 1023]) and late (chip in [-1, 1022]) lookups need no wrap.
+constexpr int kSignRow = 1028;
+
+// Correlates the epoch's samples of one thread with kTrackCG channels:
+// FMT-specialised so the sample decode leaves the loop.  All products fit in
+// 24 bits (|x| <= 127, |LUT| <= 4096, |y| < 2^20), so 24-bit multiplies are exact.
+template <int FMT>
+__device__ __forceinline__ void track_pass(const void *samples, long long n_first, int n_mine,
+                                           const uint32_t *s_lut, const int8_t (*s_sign)[kSignRow],
+                                           uint32_t (&ph)[kTrackCG], const uint32_t (&dph)[kTrackCG],
+                                           unsigned long long (&q)[kTrackCG],
+                                           const unsigned long long (&dq)[kTrackCG],
+                                           const unsigned long long (&dl)[kTrackCG],
+                                           const unsigned long long (&ndl)[kTrackCG], long long (&tot)[kTrackCG][6])
+{
+    // int32 partial sums over at most 1024 samples: |x y| < 2^20
+    for (int j0 = 0; j0 < n_mine; j0 += 1024) {
+        int acc[kTrackCG][6];
+#pragma unroll
+        for (int cc = 0; cc < kTrackCG; ++cc)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) acc[cc][k] = 0;
+        const int j1 = min(n_mine, j0 + 1024);
+        for (int j = j0; j < j1; ++j) {
+            int xr, xi;
+            load_sample(samples, FMT, n_first + (long long)j * kTrackThreads, xr, xi);
+#pragma unroll
+            for (int cc = 0; cc < kTrackCG; ++cc) {
+                const uint32_t lv = s_lut[ph[cc] >> 22];
+                const int cs = (int)(int16_t)(lv & 0xFFFFu), sn = (int)(int16_t)(lv >> 16);
+                int yr, yi;
+                if (FMT == GNSS_CPLX_I8) {
+                    yr = __mul24(xr, cs) + __mul24(xi, sn);
+                    yi = __mul24(xi, cs) - __mul24(xr, sn);
+                } else {
+                    yr = __mul24(xr, cs);
+                    yi = __mul24(-xr, sn);
+                }
+                // keeps the compiler from distributing the +-1 factors below into these
+                // products (which it then evaluates with 64-bit multiply-adds)
+                asm volatile("" : "+v"(yr), "+v"(yi));
+                const int chp = (int)(uint32_t)(q[cc] >> 32);
+                const int che = (int)(uint32_t)((q[cc] + dl[cc]) >> 32);
+                const int chl = (int)(uint32_t)((q[cc] + ndl[cc]) >> 32);  // high word of q - dl: >= -1
+                const int se = s_sign[cc][che + 1], sp = s_sign[cc][chp + 1], sl = s_sign[cc][chl + 1];
+                acc[cc][0] += __mul24(se, yr);
+                acc[cc][1] += __mul24(se, yi);
+                acc[cc][2] += __mul24(sp, yr);
+                acc[cc][3] += __mul24(sp, yi);
+                acc[cc][4] += __mul24(sl, yr);
+                acc[cc][5] += __mul24(sl, yi);
+                ph[cc] += dph[cc];
+                q[cc] += dq[cc];
+                q[cc] -= q[cc] >= (unsigned long long)kCodeFix ? (unsigned long long)kCodeFix : 0ull;
+            }
+        }
+#pragma unroll
+        for (int cc = 0; cc < kTrackCG; ++cc)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) tot[cc][k] += acc[cc][k];
+    }
+}
+
+// One workgroup per (request, epoch); the request's channels in passes of
+// kTrackCG.  Thread t handles samples t, t + 256, ... of the epoch with the
+// NCO words advanced by 256 steps between them; the code phase is kept in
+// [0, 1023 * 2^32), which leaves every chip index mod 1023 unchanged.
+__global__ __launch_bounds__(kTrackThreads) void k_track(const TrackDesc *__restrict__ R, const long long *pre,
+                                                         int n_req, long long total, const TrackCh *__restrict__ CH,
+                                                         const uint8_t *codes, const uint32_t *lut)
+{
+    __shared__ uint32_t s_lut[1024];
+    __shared__ int8_t s_sign[kTrackCG][kSignRow];
+    __shared__ long long s_red[kTrackThreads / 64];
+    for (int i = threadIdx.x; i < 1024; i += kTrackThreads) s_lut[i] = lut[i];
+    for (long long it = blockIdx.x; it < total; it += gridDim.x) {
+        const int r = find_req(pre, n_req, it);
+        const TrackDesc &d = R[r];
+        const int e = (int)(it - pre[r]);
+        const long long n_first = d.start + (long long)e * d.epoch_len + threadIdx.x;
+        for (int c0 = 0; c0 < d.n_ch; c0 += kTrackCG) {
+            __syncthreads();  // LUT staged; previous pass done with s_sign and s_red
+            for (int i = threadIdx.x; i < kTrackCG * (kCodeLen + 2); i += kTrackThreads) {
+                const int cc = i / (kCodeLen + 2), k = i - cc * (kCodeLen + 2);
+                const int prn = CH[d.ch_off + min(c0 + cc, d.n_ch - 1)].prn;
+                const int chip = k == 0 ? kCodeLen - 1 : (k == kCodeLen + 1 ? 0 : k - 1);
+                s_sign[cc][k] = (int8_t)(1 - 2 * (int)(codes[prn * kCodeLen + chip] & 1u));
+            }
+            __syncthreads();
+            uint32_t ph[kTrackCG], dph[kTrackCG];
+            unsigned long long q[kTrackCG], dq[kTrackCG], dl[kTrackCG], ndl[kTrackCG];
+            bool on[kTrackCG];
+#pragma unroll
+            for (int cc = 0; cc < kTrackCG; ++cc) {
+                on[cc] = c0 + cc < d.n_ch;
+                const TrackCh c = CH[d.ch_off + min(c0 + cc, d.n_ch - 1)];
+                ph[cc] = c.phi0 + (uint32_t)((unsigned long long)n_first * c.D);
+                dph[cc] = (uint32_t)kTrackThreads * c.D;
+                q[cc] = (unsigned long long)(c.q0 + n_first * c.R) % (unsigned long long)kCodeFix;
+                dq[cc] = (unsigned long long)((long long)kTrackThreads * c.R) % (unsigned long long)kCodeFix;
+                dl[cc] = (unsigned long long)c.dl;
+                ndl[cc] = (unsigned long long)(-c.dl);
+            }
+            long long tot[kTrackCG][6];
+#pragma unroll
+            for (int cc = 0; cc < kTrackCG; ++cc)
+#pragma unroll
+                for (int k = 0; k < 6; ++k) tot[cc][k] = 0;
+            const int n_mine = d.epoch_len > (int)threadIdx.x ? (d.epoch_len - 1 - (int)threadIdx.x) / kTrackThreads + 1 : 0;
+            if (d.fmt == GNSS_CPLX_I8)
+                track_pass<GNSS_CPLX_I8>(d.samples, n_first, n_mine, s_lut, s_sign, ph, dph, q, dq, dl, ndl, tot);
+            else if (d.fmt == GNSS_REAL_I8)
+                track_pass<GNSS_REAL_I8>(d.samples, n_first, n_mine, s_lut, s_sign, ph, dph, q, dq, dl, ndl, tot);
+            else
+                track_pass<GNSS_REAL_2BIT_PACKED>(d.samples, n_first, n_mine, s_lut, s_sign, ph, dph, q, dq, dl, ndl,
+                                                  tot);
+#pragma unroll
+            for (int cc = 0; cc < kTrackCG; ++cc) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    const long long v = block_sum64(tot[cc][k], s_red);
+                    if (threadIdx.x == 0 && on[cc])
+                        gmem(d.out)[((long long)(c0 + cc) * d.n_epochs + e) * 6 + k] = v;
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_track(const TrackDesc *d_reqs, const long long *d_pre, int n_req, long long total,
+                        const TrackCh *d_ch, const uint8_t *d_codes, const uint32_t *d_lut, hipStream_t s)
+{
+    const long long g = total < 0x7fffffffLL ? total : 0x7fffffffLL;
+    hipLaunchKernelGGL(k_track, dim3((unsigned)(g > 0 ? g : 1)), dim3(kTrackThreads), 0, s, d_reqs, d_pre, n_req,
+                       total, d_ch, d_codes, d_lut);
+    return hipGetLastError();
 }
 
 size_t peak_scratch_part_elems(const Plan &p)

@@ -39,6 +39,7 @@ struct DevBuf {
 // metadata.
 struct Workspace {
     DevBuf F, G, Q, K, part, grid, meta, samples, peaks;
+    DevBuf tmeta, tout;  // tracking: request table and host-call outputs
     void *h_stage = nullptr;
     size_t h_stage_cap = 0;
     hipEvent_t stage_ev = nullptr;
@@ -131,5 +132,8 @@ std::string rate_signature(const gnss::Plan *plans, int n);
 
 // serving loop
 void server_stop(gnss_ctx *c);
+
+// the internally locked default context of the synchronous host-buffer calls
+int default_ctx(gnss_ctx **out);
 
 }  // namespace gnss_rt

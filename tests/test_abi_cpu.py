@@ -117,3 +117,39 @@ def test_doppler_bin_count():
     assert G.n_doppler(-5000, 5000, 500) == 21
     assert G.n_doppler(-7500, 7500, 125) == 121
     assert G.n_doppler(0, 0, 1) == 1
+
+
+def _chan(**kw):
+    c = dict(prn=5, carrier_hz=1000.0, carrier_phase=0.25, code_phase=100.5, code_rate=1023000.0,
+             spacing=0.5)
+    c.update(kw)
+    return (c["prn"], c["carrier_hz"], c["carrier_phase"], c["code_phase"], c["code_rate"], c["spacing"])
+
+
+@pytest.mark.parametrize("ch,kw", [
+    (_chan(prn=0), {}), (_chan(prn=38), {}), (_chan(carrier_phase=1.0), {}),
+    (_chan(carrier_phase=-0.1), {}), (_chan(code_phase=1023.0), {}), (_chan(code_phase=-1.0), {}),
+    (_chan(code_rate=0.0), {}), (_chan(code_rate=float("nan")), {}), (_chan(spacing=0.0), {}),
+    (_chan(spacing=1.5), {}), (_chan(carrier_hz=float("inf")), {}),
+    (_chan(), {"fmt": 7}), (_chan(), {"epoch_len": 0}), (_chan(), {"n_epochs": 0}),
+    (_chan(), {"start": -1}), (_chan(), {"n_epochs": 3}),  # 3 x 2046 > 4092 samples
+    (_chan(), {"fs": 0.0}),
+])
+def test_track_argument_validation(ch, kw):
+    x = np.zeros(2 * 4092, np.int8)
+    args = dict(fmt=G.GNSS_CPLX_I8, fs=2046000.0, start=0, epoch_len=2046, n_epochs=2)
+    args.update(kw)
+    with pytest.raises(G.GnssError) as ei:
+        G.gnss_track(x, args["fmt"], args["fs"], [ch], args["start"], args["epoch_len"],
+                     args["n_epochs"], n=4092)
+    assert ei.value.code == G.GNSS_EINVAL
+
+
+def test_track_null_and_count_checks():
+    r = G.make_track_request(None, G.GNSS_CPLX_I8, 10, 1023000.0, [_chan()], 0, 5, 1, None)
+    assert G.library().gnss_track(ctypes.byref(r)) == G.GNSS_EINVAL
+    x = np.zeros(20, np.int8)
+    r = G.make_track_request(x.ctypes.data, G.GNSS_CPLX_I8, 10, 1023000.0, [_chan()], 0, 5, 1, None)
+    assert G.library().gnss_track(ctypes.byref(r)) == G.GNSS_EINVAL  # out is null
+    assert G.library().gnss_track(None) == G.GNSS_EINVAL
+    assert G.library().gnss_track_device(None, None, 0, None) == G.GNSS_EINVAL
