@@ -527,7 +527,7 @@ def run_track(args, G, torch, ctx, code_fn):
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "wall_s": wall_s, "generate_s": t_gen,
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_INT_TOPS, "unit": "Tops/s",
-                     "frac": round(achieved / PEAK_INT_TOPS, 4), "traffic": read_traffic("track", "track"),
+                     "frac": round(achieved / PEAK_INT_TOPS, 4), "traffic": read_traffic("track", "correlators"),
                      "kernel": "k_track", "avg_launch_ms": round(ms_step, 4)},
         "planted_prompt_over_early_late": float(np.min(pw[:8, 1] / np.maximum(pw[:8, 0], pw[:8, 2]))),
         "source_hash": kernel_source_hash(),
@@ -537,7 +537,7 @@ def run_track(args, G, torch, ctx, code_fn):
         import oracle as O
         threads = O.n_threads()
         done, t1 = 0, time.perf_counter()
-        while done == 0 or (time.perf_counter() - t1 < args.cpu_seconds and done < 4 * n_rec):
+        while done == 0 or (time.perf_counter() - t1 < args.cpu_seconds and done < 200 * n_rec):
             snap, chans = recs[done % n_rec]
             O.track(snap.samples, snap.fmt, fs, [O.Channel(*c) for c in chans], 0, epoch, n_ep, threads=threads)
             done += 1
