@@ -110,8 +110,12 @@ int gnss_acquire(const void *samples, int32_t fmt, size_t n, double fs, double f
 
 /* Context: one device, one HIP stream, the device-resident tables (carrier
  * LUT, C/A codes, code spectra, twiddles) and a workspace that grows on
- * demand up to hbm_budget_bytes (0 = no limit).  precision must be GNSS_FP32.
- * Errors: GNSS_EINVAL, GNSS_ENOMEM, GNSS_EDEVICE. */
+ * demand up to hbm_budget_bytes (0 = no limit).  precision: GNSS_FP32, or
+ * GNSS_FP16 for packed FP16 transforms (Fig. 2's FFT, spectrum product and
+ * IFFT) with per-vector power-of-two scaling that keeps every intermediate
+ * inside the FP16 range, |.|^2 and block sums in FP32; every search on the
+ * context uses it.  Errors: GNSS_EINVAL (unknown precision or device),
+ * GNSS_ENOMEM, GNSS_EDEVICE. */
 int gnss_ctx_create(gnss_ctx **out, int device, size_t hbm_budget_bytes, int precision);
 void gnss_ctx_destroy(gnss_ctx *ctx);
 
@@ -127,8 +131,9 @@ void gnss_ctx_destroy(gnss_ctx *ctx);
  * Errors: GNSS_EINVAL. */
 int gnss_ctx_set(gnss_ctx *ctx, const char *key, double value);
 
-/* Device bytes the context's workspace needs for a request (does not
- * allocate).  Errors: as gnss_acquire's argument checks. */
+/* Device bytes the context's workspace needs for a request in FP32 (an
+ * upper bound for FP16, whose spectra take half the space); does not
+ * allocate.  Errors: as gnss_acquire's argument checks. */
 int gnss_workspace_bytes(const gnss_request *req, size_t *bytes);
 
 /* Acquisition on device buffers (Sec. 3, Fig. 2; the whole coherent

@@ -379,6 +379,101 @@ __device__ __forceinline__ void transpose_b_fwd(T (&v)[32], T *xb, int l)
     for (int i = 0; i < 32; ++i) v[i] = nv[i];
 }
 
+// Quarter-buffer variants of the four exchanges: the same permutations done
+// in four rounds through a buffer half the size (kXbufElemsQ elements per
+// wave), for kernels that trade the extra LDS round trips for occupancy.
+// Exchange A splits by h (columns 64h .. 64h + 63 of the half) with row stride
+// kStrideAQ = 72 (= 8 mod 32 elements: a half-wave's 4 rows x 8 columns hit 32
+// distinct 8-byte banks); exchange B splits by the rows kl of one uu with the
+// stride and swizzle of the full buffer.
+constexpr int kStrideAQ = 72;
+constexpr int kXbufElemsQ = 8 * kStrideAQ;
+static_assert(4 * kStrideB <= kXbufElemsQ, "quarter transpose buffer");
+
+template <typename T>
+__device__ __forceinline__ void transpose_a_inv_q(T (&v)[32], T *xb, int l)
+{
+    T nv[32];
+#pragma unroll
+    for (int half = 0; half < 2; ++half)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) xb[kk * kStrideAQ + l] = v[16 * h + 8 * half + kk];
+            lds_fence();
+            const T *src = xb + (l >> 3) * kStrideAQ + (l & 7);
+#pragma unroll
+            for (int m = 0; m < 8; ++m) nv[16 * half + 8 * h + m] = src[8 * m];
+            lds_fence();
+        }
+#pragma unroll
+    for (int i = 0; i < 32; ++i) v[i] = nv[i];
+}
+
+template <typename T>
+__device__ __forceinline__ void transpose_a_fwd_q(T (&v)[32], T *xb, int l)
+{
+    T nv[32];
+#pragma unroll
+    for (int half = 0; half < 2; ++half)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            T *dst = xb + (l >> 3) * kStrideAQ + (l & 7);
+#pragma unroll
+            for (int m = 0; m < 8; ++m) dst[8 * m] = v[16 * half + 8 * h + m];
+            lds_fence();
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) nv[16 * h + 8 * half + kk] = xb[kk * kStrideAQ + l];
+            lds_fence();
+        }
+#pragma unroll
+    for (int i = 0; i < 32; ++i) v[i] = nv[i];
+}
+
+template <typename T>
+__device__ __forceinline__ void transpose_b_inv_q(T (&v)[32], T *xb, int l)
+{
+    T nv[32];
+#pragma unroll
+    for (int hb = 0; hb < 2; ++hb)
+#pragma unroll
+        for (int uu = 0; uu < 2; ++uu) {
+#pragma unroll
+            for (int hp = 0; hp < 2; ++hp)
+#pragma unroll
+                for (int kq = 0; kq < 4; ++kq)
+                    xb[xb_b(kq, (l >> 3) + 8 * hp, l & 7)] = v[16 * hp + 8 * hb + 4 * uu + kq];
+            lds_fence();
+#pragma unroll
+            for (int m2 = 0; m2 < 8; ++m2) nv[8 * (2 * hb + uu) + m2] = xb[xb_b(l >> 4, l & 15, m2)];
+            lds_fence();
+        }
+#pragma unroll
+    for (int i = 0; i < 32; ++i) v[i] = nv[i];
+}
+
+template <typename T>
+__device__ __forceinline__ void transpose_b_fwd_q(T (&v)[32], T *xb, int l)
+{
+    T nv[32];
+#pragma unroll
+    for (int hb = 0; hb < 2; ++hb)
+#pragma unroll
+        for (int uu = 0; uu < 2; ++uu) {
+#pragma unroll
+            for (int m2 = 0; m2 < 8; ++m2) xb[xb_b(l >> 4, l & 15, m2)] = v[8 * (2 * hb + uu) + m2];
+            lds_fence();
+#pragma unroll
+            for (int hp = 0; hp < 2; ++hp)
+#pragma unroll
+                for (int kq = 0; kq < 4; ++kq)
+                    nv[16 * hp + 8 * hb + 4 * uu + kq] = xb[xb_b(kq, (l >> 3) + 8 * hp, l & 7)];
+            lds_fence();
+        }
+#pragma unroll
+    for (int i = 0; i < 32; ++i) v[i] = nv[i];
+}
+
 // ---------------------------------------------------------------------------
 // twiddle tables (built once per context, staged in LDS by each workgroup)
 //   T1[(16 h + k1) * 64 + l] = exp(+2 pi i (l + 64 h) k1 / 2048)
@@ -393,7 +488,7 @@ constexpr int kTwElems = kT1Elems + kT2Elems;
 // ---------------------------------------------------------------------------
 // Inverse: storage order in, natural order out (unnormalised).
 // PRUNE_OUT: only natural indices with k2b < 4 (i.e. < 1024) are produced.
-template <bool PRUNE_OUT, typename T>
+template <bool PRUNE_OUT, bool QUARTER = false, typename T>
 __device__ __forceinline__ void ifft2048(T (&v)[32], T *xb, const T *t1, const T *t2, int l)
 {
     dft16<true, 0>(v);
@@ -405,7 +500,10 @@ __device__ __forceinline__ void ifft2048(T (&v)[32], T *xb, const T *t1, const T
         for (int k1 = 1; k1 < 16; ++k1) v[16 * h + k1] = c_mul(v[16 * h + k1], t1[(16 * h + k1) * 64 + l]);
     }
     phase_barrier();
-    transpose_a_inv(v, xb, l);
+    if constexpr (QUARTER)
+        transpose_a_inv_q(v, xb, l);
+    else
+        transpose_a_inv(v, xb, l);
     phase_barrier();
     dft16<true, 0>(v);
     dft16<true, 16>(v);
@@ -417,7 +515,10 @@ __device__ __forceinline__ void ifft2048(T (&v)[32], T *xb, const T *t1, const T
         v[16 + k2a] = c_mul(v[16 + k2a], w);
     }
     phase_barrier();
-    transpose_b_inv(v, xb, l);
+    if constexpr (QUARTER)
+        transpose_b_inv_q(v, xb, l);
+    else
+        transpose_b_inv(v, xb, l);
     phase_barrier();
     dft8<true, false, PRUNE_OUT, 0>(v);
     dft8<true, false, PRUNE_OUT, 8>(v);
@@ -427,7 +528,7 @@ __device__ __forceinline__ void ifft2048(T (&v)[32], T *xb, const T *t1, const T
 
 // Forward: natural order in, storage order out.
 // PRUNE_IN: natural indices >= 1024 (k2b >= 4) are zero on input.
-template <bool PRUNE_IN, typename T>
+template <bool PRUNE_IN, bool QUARTER = false, typename T>
 __device__ __forceinline__ void fft2048(T (&v)[32], T *xb, const T *t1, const T *t2, int l)
 {
     dft8<false, PRUNE_IN, false, 0>(v);
@@ -435,7 +536,10 @@ __device__ __forceinline__ void fft2048(T (&v)[32], T *xb, const T *t1, const T 
     dft8<false, PRUNE_IN, false, 16>(v);
     dft8<false, PRUNE_IN, false, 24>(v);
     phase_barrier();
-    transpose_b_fwd(v, xb, l);
+    if constexpr (QUARTER)
+        transpose_b_fwd_q(v, xb, l);
+    else
+        transpose_b_fwd(v, xb, l);
     phase_barrier();
 #pragma unroll
     for (int k2a = 1; k2a < 16; ++k2a) {
@@ -447,7 +551,10 @@ __device__ __forceinline__ void fft2048(T (&v)[32], T *xb, const T *t1, const T 
     dft16<false, 0>(v);
     dft16<false, 16>(v);
     phase_barrier();
-    transpose_a_fwd(v, xb, l);
+    if constexpr (QUARTER)
+        transpose_a_fwd_q(v, xb, l);
+    else
+        transpose_a_fwd(v, xb, l);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         phase_barrier();

@@ -81,6 +81,10 @@ int ensure(gnss_ctx *c, DevBuf &b, size_t bytes)
 
 void release(gnss_ctx *c, DevBuf &b)
 {
+    if (!b.owned) {
+        b = DevBuf{};
+        return;
+    }
     if (!b.p) return;
     (void)hipFree(b.p);
     std::lock_guard<std::mutex> lk(c->mem_mu);

@@ -384,6 +384,41 @@ __device__ __forceinline__ long long next_item(BatchHdr *h, int stage, long long
 constexpr int kBoxRun = 8;
 __device__ __forceinline__ int bpad(int i) { return i + (i >> 3); }  // bank-conflict padding
 
+// Wipe + fold of samples n0 .. n0 + len - 1 (mod N) of block b into s_f,
+// FMT-specialised; the phase of the folded milliseconds advances by N D (mod
+// 2^32) from one to the next, and |x| <= 127, |LUT| <= 4096 make the 24-bit
+// multiplies exact.  Same values as wipe_fold_one.
+template <int FMT>
+__device__ __forceinline__ void box_wipe(const void *samples, int N, int Tc, const uint32_t *s_lut, uint32_t D,
+                                         int b, int n0, int len, int2 *s_f)
+{
+    const uint32_t dN = (uint32_t)N * D;
+    const long long base = (long long)b * Tc * N;
+    for (int i = threadIdx.x; i < len; i += 256) {
+        int n = n0 + i;
+        if (n >= N) n -= N;
+        long long ng = base + n;
+        uint32_t ph = (uint32_t)ng * D;
+        int yr = 0, yi = 0;
+        for (int c = 0; c < Tc; ++c) {
+            int xr, xi;
+            load_sample(samples, FMT, ng, xr, xi);
+            const uint32_t e = s_lut[ph >> 22];
+            const int cs = (int)(int16_t)(e & 0xFFFFu), sn = (int)(int16_t)(e >> 16);
+            if (FMT == GNSS_CPLX_I8) {
+                yr += __mul24(xr, cs) + __mul24(xi, sn);
+                yi += __mul24(xi, cs) - __mul24(xr, sn);
+            } else {
+                yr += __mul24(xr, cs);
+                yi -= __mul24(xr, sn);
+            }
+            ng += N;
+            ph += dN;
+        }
+        s_f[bpad(i)] = make_int2(yr, yi);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_box(const ReqDesc *__restrict__ R, BatchHdr *H, const long long *pre,
                                              const uint32_t *lut, int2 *F)
 {
@@ -409,11 +444,12 @@ __global__ __launch_bounds__(256) void k_box(const ReqDesc *__restrict__ R, Batc
             const int cnt = min(kBoxChunk, N - n0);
             const int len = cnt + spc - 1;
             __syncthreads();  // LUT staged / previous chunk's boxcar done
-            for (int i = threadIdx.x; i < len; i += 256) {
-                int n = n0 + i;
-                if (n >= N) n -= N;
-                s_f[bpad(i)] = wipe_fold_one(d.samples, d.fmt, N, d.Tc, s_lut, D, b, n);
-            }
+            if (d.fmt == GNSS_CPLX_I8)
+                box_wipe<GNSS_CPLX_I8>(d.samples, N, d.Tc, s_lut, D, b, n0, len, s_f);
+            else if (d.fmt == GNSS_REAL_I8)
+                box_wipe<GNSS_REAL_I8>(d.samples, N, d.Tc, s_lut, D, b, n0, len, s_f);
+            else
+                box_wipe<GNSS_REAL_2BIT_PACKED>(d.samples, N, d.Tc, s_lut, D, b, n0, len, s_f);
             __syncthreads();
             const int n_runs = (cnt + kBoxRun - 1) / kBoxRun;
             for (int rr = threadIdx.x; rr < n_runs; rr += 256) {
@@ -730,7 +766,7 @@ __global__ __launch_bounds__(256) void k_fft_poly_h(const int2 *F, const hc2 *tw
                                                     const BatchHdr *H)
 {
     __shared__ hc2 s_tw[kTwElems];
-    __shared__ hc2 s_xb[4][kXbufElems];
+    __shared__ hc2 s_xb[4][kXbufElemsQ];
     stage_twiddles_h(s_tw, tw, threadIdx.x, 256);
     __syncthreads();
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -768,7 +804,7 @@ __global__ __launch_bounds__(256) void k_fft_poly_h(const int2 *F, const hc2 *tw
                     v[8 * u + k2b] = make_hc2(zero, zero);
                 }
             }
-        fft2048<true>(v, s_xb[w], s_tw, s_tw + kT1Elems, l);
+        fft2048<true, true>(v, s_xb[w], s_tw, s_tw + kT1Elems, l);
         uint4 *ga = Gh + va * 512, *gb = Gh + vb * 512;
 #pragma unroll
         for (int jj = 0; jj < 8; ++jj) {
@@ -797,7 +833,7 @@ __device__ __forceinline__ hc2 c_mul_bcast(__half2 g, hc2 c)
 // inverse transform per pair and block.  Work item = (request, PRN tile,
 // chunk of kCorrWavesH (Doppler, phase) items).
 template <int PT>
-__global__ __launch_bounds__(64 * kCorrWavesH) void k_corr_h(const ReqDesc *__restrict__ R, BatchHdr *H,
+__global__ __launch_bounds__(64 * kCorrWavesH) __attribute__((amdgpu_waves_per_eu(PT == 2 ? 3 : 1))) void k_corr_h(const ReqDesc *__restrict__ R, BatchHdr *H,
                                                              const long long *pre, const uint4 *Gh,
                                                              const int *E, const uint4 *__restrict__ CSh,
                                                              const hc2 *__restrict__ tw, float out_scale)
@@ -807,7 +843,7 @@ __global__ __launch_bounds__(64 * kCorrWavesH) void k_corr_h(const ReqDesc *__re
     constexpr int W = kCorrWavesH;
     constexpr int kCcBytes = NP * 1024 * (int)sizeof(uint4);
     constexpr int kTwBytes = kTwElems * (int)sizeof(hc2);
-    constexpr int kXbBytes = W * kXbufElems * (int)sizeof(hc2);
+    constexpr int kXbBytes = W * kXbufElemsQ * (int)sizeof(hc2);
     constexpr int kStageBytes = PT * 1024 * (W + 1) * (int)sizeof(float);
     constexpr int kSmem = (kCcBytes + kTwBytes + kXbBytes) > kStageBytes ? (kCcBytes + kTwBytes + kXbBytes)
                                                                           : kStageBytes;
@@ -858,7 +894,7 @@ __global__ __launch_bounds__(64 * kCorrWavesH) void k_corr_h(const ReqDesc *__re
 
         if (active) {
             const long long v0 = d.vec_off + (long long)k * d.Nnc * spc + s;
-            hc2 *xb = s_xb + w * kXbufElems;
+            hc2 *xb = s_xb + w * kXbufElemsQ;
             for (int b = 0; b < d.Nnc; ++b) {
                 const long long vec = v0 + (long long)b * spc;
                 const float sc = ldexpf(1.f, 2 * E[vec]);
@@ -879,7 +915,7 @@ __global__ __launch_bounds__(64 * kCorrWavesH) void k_corr_h(const ReqDesc *__re
                         z[4 * jj + 3] = c_mul_bcast(bits_h2(g.w), make_hc2(bits_h2(c1.z), bits_h2(c1.w)));
                     }
                     phase_barrier();
-                    ifft2048<true>(z, xb, s_tw, s_tw + kT1Elems, l);
+                    ifft2048<true, true>(z, xb, s_tw, s_tw + kT1Elems, l);
                     phase_barrier();
 #pragma unroll
                     for (int u = 0; u < 4; ++u)

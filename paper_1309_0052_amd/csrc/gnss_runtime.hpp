@@ -33,6 +33,7 @@ extern thread_local std::string t_err;
 struct DevBuf {
     void *p = nullptr;
     size_t cap = 0;
+    bool owned = true;  // false: a view into another allocation (never freed on its own)
 };
 
 // Device buffers of one in-flight batch and the pinned staging of its

@@ -49,9 +49,12 @@ struct Ticket {
     Clock::time_point t_submit, t_start, t_done;
 };
 
+// A batch slot.  All its device buffers are views into one arena that grows
+// geometrically, up to the slot's share of the budget, and is never resized
+// for a batch that fits: the per-batch layout changes, the allocation does not.
 struct Slot {
-    Workspace ws;
-    DevBuf samples, peaks, grids;
+    Workspace ws;                  // device fields: views into the arena
+    DevBuf arena, samples, peaks, grids;
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     bool busy = false;
@@ -129,6 +132,14 @@ static size_t slot_budget(gnss_ctx *c)
     return free_b / 3;  // two slots and headroom
 }
 
+// What admission lets into one batch: the slot's share less a reserve for the
+// 256-byte alignment of the buffers laid out in the slot's arena.
+static size_t admit_budget(gnss_ctx *c)
+{
+    const size_t share = slot_budget(c), reserve = (size_t)4 << 20;
+    return share > reserve ? share - reserve : 0;
+}
+
 static int ensure_pinned(void **p, size_t *cap, size_t bytes)
 {
     if (*cap >= bytes) return GNSS_OK;
@@ -164,21 +175,24 @@ static void release_slot_buffers(gnss_ctx *c, Slot &sl)
     release(c, sl.samples);
     release(c, sl.peaks);
     release(c, sl.grids);
+    release(c, sl.arena);
+}
+
+static DevBuf view(const DevBuf &arena, size_t off, size_t bytes)
+{
+    DevBuf v;
+    v.p = (char *)arena.p + off;
+    v.cap = bytes;
+    v.owned = false;
+    return v;
 }
 
 static int run_slot_once(gnss_ctx *c, Slot &sl);
 
-// Uploads, launches and enqueues the result copies of a formed batch.  A
-// slot's buffers keep the largest size each has needed; if together they no
-// longer fit the budget for this batch, they are released and allocated anew.
+// Uploads, launches and enqueues the result copies of a formed batch.
 static int run_slot(gnss_ctx *c, Slot &sl)
 {
-    int rc = run_slot_once(c, sl);
-    if (rc == GNSS_ENOMEM) {
-        release_slot_buffers(c, sl);
-        rc = run_slot_once(c, sl);
-    }
-    return rc;
+    return run_slot_once(c, sl);
 }
 
 static int run_slot_once(gnss_ctx *c, Slot &sl)
@@ -198,8 +212,36 @@ static int run_slot_once(gnss_ctx *c, Slot &sl)
         if (t->req.out_grid) gb += (size_t)t->plan.grid_elems() * sizeof(float);
     }
     int rc;
-    if ((rc = ensure(c, sl.samples, sb)) || (rc = ensure(c, sl.peaks, pb)) || (rc = ensure(c, sl.grids, std::max<size_t>(gb, 1))))
-        return rc;
+    {
+        // the batch's layout in the slot's arena: workspace buffers, then the
+        // samples, peaks and grids of its requests
+        std::vector<gnss_request> rq(n);
+        std::vector<gnss::Plan> pl(n);
+        for (int i = 0; i < n; ++i) {
+            rq[i] = sl.members[i]->req;
+            pl[i] = sl.members[i]->plan;
+        }
+        BatchHost P;
+        build_batch(pl.data(), rq.data(), n, 2, c->threshold, c->precision, P);
+        const size_t sizes[10] = {P.F_bytes, P.G_bytes, P.Q_bytes, P.K_bytes, P.part_bytes, P.grid_bytes,
+                                  meta_bytes(n), sb, pb, gb};
+        size_t off[10], need = 0;
+        for (int k = 0; k < 10; ++k) {
+            off[k] = need;
+            need += (std::max<size_t>(sizes[k], 1) + 255) & ~(size_t)255;
+        }
+        if (need > sl.arena.cap) {
+            // grow geometrically, within the slot's share (of the budget, or of the
+            // free device memory without one)
+            const size_t want = std::max(need, std::min(2 * sl.arena.cap, slot_budget(c)));
+            (void)hipStreamSynchronize(sl.stream);
+            release_slot_buffers(c, sl);
+            if ((rc = ensure(c, sl.arena, want))) return rc;
+        }
+        DevBuf *bufs[10] = {&sl.ws.F, &sl.ws.G, &sl.ws.Q, &sl.ws.K, &sl.ws.part, &sl.ws.grid, &sl.ws.meta,
+                            &sl.samples, &sl.peaks, &sl.grids};
+        for (int k = 0; k < 10; ++k) *bufs[k] = view(sl.arena, off[k], std::max<size_t>(sizes[k], 1));
+    }
     if ((rc = ensure_pinned(&sl.h_peaks, &sl.h_peaks_cap, pb))) return rc;
     std::vector<gnss_request> reqs(n);
     std::vector<gnss::Plan> plans(n);
@@ -276,7 +318,7 @@ static void server_loop(gnss_ctx *c)
             std::vector<Ticket *> take;
             {
                 std::unique_lock<std::mutex> lk(S.mu);
-                const size_t cap = slot_budget(c);
+                const size_t cap = admit_budget(c);
                 size_t used = 0;
                 while (!S.queue.empty() && (int)take.size() < c->max_slots) {
                     Ticket *t = S.queue.front();
@@ -438,9 +480,9 @@ int gnss_submit(gnss_ctx *ctx, const gnss_request *req, uint64_t *ticket)
     build_batch(&p, &r1, 1, corr_ptile_for(ctx, &p, 1), ctx->threshold, ctx->precision, B);
     t->need_bytes = batch_device_bytes(B) + t->sample_bytes + (size_t)p.n_prn * sizeof(gnss_peak) +
                     (req->out_grid ? (size_t)p.grid_elems() * sizeof(float) : 0);
-    if (t->need_bytes > slot_budget(ctx))
+    if (t->need_bytes > admit_budget(ctx))
         return set_err(GNSS_ENOMEM, "request needs %zu device bytes, more than a batch slot's %zu", t->need_bytes,
-                       slot_budget(ctx));
+                       admit_budget(ctx));
     Server &S = *ctx->server;
     t->h_samples = S.pinned.take(std::max<size_t>(t->sample_bytes, 1), &t->h_samples_cap);
     if (!t->h_samples) return set_err(GNSS_ENOMEM, "pinned allocation of %zu bytes failed", t->sample_bytes);

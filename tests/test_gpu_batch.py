@@ -267,3 +267,42 @@ def test_medium_batch_matches_oracle(ctx):
         ctx.acquire_device(reqs[i].req)
         g2, p2 = reqs[i].result()
         assert np.array_equal(g, g2) and np.array_equal(p, p2)
+
+
+def test_serving_budget_holds_across_alternating_shapes():
+    # Two request shapes whose largest buffers differ (A: a large grid; B: long
+    # records, large forward spectra).  A slot's share of the budget fits either one
+    # but not the per-buffer maxima of both; with both slots busy every ticket must
+    # still succeed (each slot resizes within its share) and match the result alone.
+    a_snap, a_srch = synth.weak_complex_int8(O.ca_code, seed=21)
+    a_srch = synth.Search(a_srch.prns, a_srch.lo, a_srch.hi, a_srch.step, 1, 4)
+    b_snap = synth.make_snapshot(22, O.REAL_I8, 4092000, 1023000.0, 200.0,
+                                 [synth.Planted(prn=3, code_phase=1000, doppler_hz=1500.0, cn0_dbhz=45.0)],
+                                 O.ca_code)
+    b_srch = synth.Search([3, 4, 5, 6, 7, 8, 9, 10], -5000.0, 5000.0, 500.0, 1, 200)
+    shapes = [(a_snap, a_srch, True), (b_snap, b_srch, False)]
+    needs = []
+    for snap, srch, grid in shapes:
+        req, x, g, pk = _host_request(snap, srch, want_grid=grid)
+        needs.append(G.gnss_workspace_bytes(req) + (g.nbytes if grid else 0))
+    share = int(1.15 * max(needs))
+    alone = []
+    with G.Context(0) as c1:
+        for snap, srch, grid in shapes:
+            req, x, g, pk = _host_request(snap, srch, want_grid=grid)
+            t = c1.submit(req)
+            assert c1.wait(t, 120.0).status == 0
+            alone.append((g.copy() if grid else None, pk.copy()))
+    log("alternating shapes: needs %s, slot share %d" % (needs, share))
+    with G.Context(0, hbm_budget_bytes=2 * share + (8 << 20)) as sctx:
+        subs = []
+        for i in range(8):
+            snap, srch, grid = shapes[i % 2]
+            req, x, g, pk = _host_request(snap, srch, want_grid=grid)
+            subs.append((i % 2, sctx.submit(req), g, pk, x, req))
+        for k, t, g, pk, x, req in subs:
+            info = sctx.wait(t, 120.0)
+            assert info.status == 0, G.last_error()
+            assert np.array_equal(pk, alone[k][1])
+            if g is not None:
+                assert np.array_equal(g, alone[k][0])
