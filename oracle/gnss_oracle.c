@@ -104,6 +104,18 @@ uint32_t orc_nco_step(double f_if, double f_bin, double fs)
     return (uint32_t)(int64_t)llround(f * 4294967296.0 / fs);
 }
 
+/* Code-Doppler compensation of the non-coherent sum (an option).  The code
+ * rate scales with the carrier Doppler (f_L1 = 1540 x the chip rate), so a
+ * satellite's correlation peak at Doppler f moves by f / f_L1 samples per
+ * sample.  Block b starts b*Tc*N samples into the record; its peak sits
+ * delta_b = llround(b*Tc*N * f / 1575.42e6) samples earlier than block 0's,
+ * and the compensated power is P[tau] = sum_b |R_b[(tau - delta_b) mod N]|^2. */
+int64_t orc_code_shift(int64_t b, int Tc, int64_t N, double f_bin)
+{
+    double x = (double)(b * (int64_t)Tc * N) * f_bin / 1575420000.0;
+    return (int64_t)llround(x);
+}
+
 /* Read sample n of the record as (re, im) integers. */
 static void orc_sample(const void *samples, int fmt, int64_t n, int64_t *re, int64_t *im)
 {
@@ -219,7 +231,7 @@ static void orc_corr_block(const int64_t *y, int64_t blk, int64_t n_first, const
  * worker threads, as the paper's Listing 2 does for its channel tasks. */
 int orc_grid_direct(const void *samples, int fmt, int64_t n_samples, int64_t fs_hz,
                     double f_if, const int32_t *prn_list, int n_prn, double lo, double step,
-                    int n_dopp, int Tc, int Nnc, double *P, int nthreads)
+                    int n_dopp, int Tc, int Nnc, double *P, int nthreads, int code_doppler)
 {
     int64_t N;
     int rc = orc_check_common(samples, fmt, n_samples, fs_hz, n_dopp, Tc, Nnc, &N);
@@ -254,7 +266,12 @@ int orc_grid_direct(const void *samples, int fmt, int64_t n_samples, int64_t fs_
                 double acc = 0.0;
                 for (int b = 0; b < Nnc; b++) {
                     int64_t Rre, Rim;
-                    orc_corr_block(y + 2 * (int64_t)b * blk, blk, (int64_t)b * blk, c, N, tau,
+                    int64_t t = tau;
+                    if (code_doppler) {
+                        t = (tau - orc_code_shift(b, Tc, N, orc_bin_freq(lo, step, k))) % N;
+                        if (t < 0) t += N;
+                    }
+                    orc_corr_block(y + 2 * (int64_t)b * blk, blk, (int64_t)b * blk, c, N, t,
                                    &Rre, &Rim);
                     acc += ((double)Rre * (double)Rre + (double)Rim * (double)Rim) * 0x1p-24;
                 }
@@ -272,7 +289,7 @@ int orc_grid_direct(const void *samples, int fmt, int64_t n_samples, int64_t fs_
 int orc_cells_direct(const void *samples, int fmt, int64_t n_samples, int64_t fs_hz,
                      double f_if, const int32_t *prn_list, int n_prn, double lo, double step,
                      int n_dopp, int Tc, int Nnc, const int32_t *cells, int64_t n_cells,
-                     double *out, int nthreads)
+                     double *out, int nthreads, int code_doppler)
 {
     int64_t N;
     int rc = orc_check_common(samples, fmt, n_samples, fs_hz, n_dopp, Tc, Nnc, &N);
@@ -306,8 +323,13 @@ int orc_cells_direct(const void *samples, int fmt, int64_t n_samples, int64_t fs
             double acc = 0.0;
             for (int b = 0; b < Nnc; b++) {
                 int64_t Rre, Rim;
+                int64_t t = cl[2];
+                if (code_doppler) {
+                    t = (t - orc_code_shift(b, Tc, N, orc_bin_freq(lo, step, cl[1]))) % N;
+                    if (t < 0) t += N;
+                }
                 orc_wipe_lut(samples, fmt, D, (int64_t)b * blk, blk, cosL, sinL, y);
-                orc_corr_block(y, blk, (int64_t)b * blk, c, N, cl[2], &Rre, &Rim);
+                orc_corr_block(y, blk, (int64_t)b * blk, c, N, t, &Rre, &Rim);
                 acc += ((double)Rre * (double)Rre + (double)Rim * (double)Rim) * 0x1p-24;
             }
             out[i] = acc;

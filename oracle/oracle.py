@@ -63,10 +63,12 @@ def _load():
                                       ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
         lib.orc_grid_direct.argtypes = [vp, ctypes.c_int, i64, i64, dbl, vp, ctypes.c_int,
                                         dbl, dbl, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                        vp, ctypes.c_int]
+                                        vp, ctypes.c_int, ctypes.c_int]
         lib.orc_cells_direct.argtypes = [vp, ctypes.c_int, i64, i64, dbl, vp, ctypes.c_int,
                                          dbl, dbl, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                         vp, i64, vp, ctypes.c_int]
+                                         vp, i64, vp, ctypes.c_int, ctypes.c_int]
+        lib.orc_code_shift.argtypes = [i64, ctypes.c_int, i64, dbl]
+        lib.orc_code_shift.restype = i64
         lib.orc_track.argtypes = [vp, ctypes.c_int, i64, ctypes.c_int, vp, vp, vp, vp, vp, vp, i64,
                                   i64, ctypes.c_int, vp, ctypes.c_int]
         for f in (lib.orc_ca_code, lib.orc_code_replica, lib.orc_wipe, lib.orc_wipe_fold,
@@ -170,8 +172,9 @@ def wipe_fold(samples, fmt, fs_hz, f_if, lo, step, n_dopp, T_coh, N_noncoh) -> n
 # ---------------------------------------------------------------------------
 
 def grid_direct(samples, fmt, fs_hz, f_if, prns, lo, step, n_dopp, T_coh, N_noncoh,
-                threads: int | None = None) -> np.ndarray:
-    """P[p][k][tau] by direct time-domain circular correlation (FP64 float64 array)."""
+                threads: int | None = None, code_doppler: bool = False) -> np.ndarray:
+    """P[p][k][tau] by direct time-domain circular correlation (FP64 float64 array);
+    code_doppler: each block's lag shifted by code_shift (the compensated sum)."""
     s = np.ascontiguousarray(samples)
     prn_arr = np.ascontiguousarray(np.asarray(prns, np.int32))
     N = samples_per_ms(fs_hz)
@@ -179,12 +182,13 @@ def grid_direct(samples, fmt, fs_hz, f_if, prns, lo, step, n_dopp, T_coh, N_nonc
     _check(_load().orc_grid_direct(_ptr(s), int(fmt), n_samples_of(s, fmt), int(fs_hz),
                                    float(f_if), _ptr(prn_arr), prn_arr.size, float(lo),
                                    float(step), int(n_dopp), int(T_coh), int(N_noncoh),
-                                   _ptr(P), int(threads or n_threads())), "grid_direct")
+                                   _ptr(P), int(threads or n_threads()), int(bool(code_doppler))),
+           "grid_direct")
     return P
 
 
 def cells_direct(samples, fmt, fs_hz, f_if, prns, lo, step, n_dopp, T_coh, N_noncoh, cells,
-                 threads: int | None = None) -> np.ndarray:
+                 threads: int | None = None, code_doppler: bool = False) -> np.ndarray:
     """P at selected cells (rows of (prn index, k, tau)) by direct correlation."""
     s = np.ascontiguousarray(samples)
     prn_arr = np.ascontiguousarray(np.asarray(prns, np.int32))
@@ -194,15 +198,22 @@ def cells_direct(samples, fmt, fs_hz, f_if, prns, lo, step, n_dopp, T_coh, N_non
                                     float(f_if), _ptr(prn_arr), prn_arr.size, float(lo),
                                     float(step), int(n_dopp), int(T_coh), int(N_noncoh),
                                     _ptr(cl), cl.shape[0], _ptr(out),
-                                    int(threads or n_threads())), "cells_direct")
+                                    int(threads or n_threads()), int(bool(code_doppler))), "cells_direct")
     return out
 
 
+def code_shift(b: int, T_coh: int, N: int, f_bin: float) -> int:
+    """Samples by which block b's correlation peak at Doppler f_bin sits
+    earlier than block 0's (code-Doppler compensation reading)."""
+    return int(_load().orc_code_shift(int(b), int(T_coh), int(N), float(f_bin)))
+
+
 def grid_fft(samples, fmt, fs_hz, f_if, prns, lo, step, n_dopp, T_coh, N_noncoh,
-             folded: np.ndarray | None = None) -> np.ndarray:
+             folded: np.ndarray | None = None, code_doppler: bool = False) -> np.ndarray:
     """P[p][k][tau] through the correlation theorem in FP64:
     R_b = IDFT_N( DFT_N(f_b) * conj(DFT_N(c)) ), P = sum_b |R_b|^2 2^-24.
-    The folded blocks are exact integers, so the only error is FP64 FFT rounding."""
+    The folded blocks are exact integers, so the only error is FP64 FFT rounding.
+    code_doppler: P[tau] = sum_b |R_b[(tau - delta_b(k)) mod N]|^2 2^-24."""
     import scipy.fft as sfft
 
     N = samples_per_ms(fs_hz)
@@ -218,7 +229,11 @@ def grid_fft(samples, fmt, fs_hz, f_if, prns, lo, step, n_dopp, T_coh, N_noncoh,
         pw = (R.real * R.real + R.imag * R.imag) * POWER_SCALE
         acc = np.zeros((n_dopp, N), np.float64)
         for b in range(N_noncoh):  # blocks summed in ascending order
-            acc += pw[:, b, :]
+            if code_doppler:
+                for k in range(n_dopp):
+                    acc[k] += np.roll(pw[k, b, :], code_shift(b, T_coh, N, bin_freq(lo, step, k)))
+            else:
+                acc += pw[:, b, :]
         P[pi] = acc
         del R, pw
     return P

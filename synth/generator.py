@@ -54,11 +54,20 @@ class Snapshot:
     seed: int = 0
 
 
-def _code_wave(chips: np.ndarray, fs_hz: int, n: np.ndarray, code_phase: int) -> np.ndarray:
+L1_HZ = 1575420000.0
+
+
+def _code_wave(chips: np.ndarray, fs_hz: int, n: np.ndarray, code_phase: int,
+               doppler_hz: float = 0.0, code_doppler: bool = False) -> np.ndarray:
     """+-1 code waveform at sample indices n for a code whose chip 0 starts at
-    sample code_phase (code rate fixed at 1.023 MHz)."""
+    sample code_phase.  Code rate 1.023 MHz, or with code_doppler the received
+    rate 1.023 MHz * (1 + doppler / f_L1) (chip 0 still at code_phase)."""
     rel = n.astype(np.int64) - int(code_phase)
-    chip = np.floor_divide(rel * CHIP_RATE, int(fs_hz)) % 1023
+    if code_doppler and doppler_hz != 0.0:
+        rate = CHIP_RATE * (1.0 + doppler_hz / L1_HZ)
+        chip = np.floor(rel.astype(np.float64) * (rate / float(fs_hz))).astype(np.int64) % 1023
+    else:
+        chip = np.floor_divide(rel * CHIP_RATE, int(fs_hz)) % 1023
     return 1.0 - 2.0 * chips[chip].astype(np.float64)
 
 
@@ -101,9 +110,10 @@ def unpack_2bit(b: np.ndarray, n: int) -> np.ndarray:
 
 def make_snapshot(seed: int, fmt: int, fs_hz: int, f_if_hz: float, duration_ms: float,
                   planted: list, code_fn, noise_sigma: float = 1.0, noise: bool = True,
-                  chunk: int = 1 << 20) -> Snapshot:
+                  chunk: int = 1 << 20, code_doppler: bool = False) -> Snapshot:
     """Generate one snapshot.  ``planted`` is a list of ``Planted``; their
-    amplitudes are set from C/N0 and written back."""
+    amplitudes are set from C/N0 and written back.  code_doppler: the code
+    rate of each planted satellite follows its Doppler (off by default)."""
     rng = np.random.default_rng(seed)
     n_total = int(round(fs_hz * duration_ms / 1000.0))
     cplx = fmt == CPLX_I8
@@ -123,7 +133,7 @@ def make_snapshot(seed: int, fmt: int, fs_hz: int, f_if_hz: float, duration_ms: 
         re = np.zeros(n.size)
         im = np.zeros(n.size) if cplx else None
         for i, p in enumerate(planted):
-            w = p.amplitude * _code_wave(chips[p.prn], fs_hz, n, p.code_phase)
+            w = p.amplitude * _code_wave(chips[p.prn], fs_hz, n, p.code_phase, p.doppler_hz, code_doppler)
             if navs[i] is not None:
                 w = w * navs[i][n]
             theta = 2.0 * np.pi * (f_if_hz + p.doppler_hz) * (n / fs_hz) + p.carrier_phase
