@@ -126,8 +126,12 @@ void gnss_ctx_destroy(gnss_ctx *ctx);
  * "persistent" (grid of the correlation kernel, the dominant one: 1, the
  * default, an occupancy-sized grid whose workgroups take items from per-XCD
  * work counters and then from the other XCDs' ranges; 0 one workgroup per
- * item; the other stages always run one workgroup per item), "max_slots"
- * (requests per served batch, 1..4096).
+ * item; the other stages always run one workgroup per item),
+ * "code_doppler" (1: code-Doppler compensation of the non-coherent sum: the
+ * code rate follows the carrier Doppler (f_L1 = 1540 chip rates), so block
+ * b's correlation at bin f_k is taken at lag tau - llround(b T_coh N f_k /
+ * 1575.42e6) (circular); 0, the default: plain sum), "max_slots" (requests per
+ * served batch, 1..4096).
  * Errors: GNSS_EINVAL. */
 int gnss_ctx_set(gnss_ctx *ctx, const char *key, double value);
 

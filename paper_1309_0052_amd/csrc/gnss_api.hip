@@ -257,8 +257,10 @@ int stage_batch(gnss_ctx *c, Workspace &w, BatchHost &B, hipStream_t s, gnss::La
         (rc = ensure(c, w.part, std::max<size_t>(B.part_bytes, 1))) ||
         (rc = ensure(c, w.grid, std::max<size_t>(B.grid_bytes, 1))) || (rc = ensure(c, w.meta, mb)))
         return rc;
-    for (int r = 0; r < B.n; ++r)
+    for (int r = 0; r < B.n; ++r) {
         if (B.grid_off[r] >= 0) B.d[r].grid = (float *)w.grid.p + B.grid_off[r];
+        B.d[r].code_doppler = c->code_doppler;
+    }
     // pinned staging: wait until the previous copy out of it has finished
     if (w.stage_ev) HIP_TRY(hipEventSynchronize(w.stage_ev));
     if (w.h_stage_cap < mb) {
@@ -550,6 +552,11 @@ int gnss_ctx_set(gnss_ctx *ctx, const char *key, double value)
     if (!strcmp(key, "persistent")) {
         if (value != 0.0 && value != 1.0) return set_err(GNSS_EINVAL, "persistent must be 0 or 1");
         ctx->persistent = (int)value;
+        return GNSS_OK;
+    }
+    if (!strcmp(key, "code_doppler")) {
+        if (value != 0.0 && value != 1.0) return set_err(GNSS_EINVAL, "code_doppler must be 0 or 1");
+        ctx->code_doppler = (int)value;
         return GNSS_OK;
     }
     if (!strcmp(key, "max_slots")) {

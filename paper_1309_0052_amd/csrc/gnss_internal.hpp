@@ -86,6 +86,7 @@ struct ReqDesc {
     int n_ptiles;         // PRN tiles of the correlation kernel
     int n_tau_blk;        // 256-lag blocks of the detection kernels
     float threshold;
+    int code_doppler;     // 1: shift each block's lags by its code-Doppler drift
     int prns[kMaxList];
 };
 

@@ -384,18 +384,31 @@ __device__ __forceinline__ long long next_item(BatchHdr *h, int stage, long long
 constexpr int kBoxRun = 8;
 __device__ __forceinline__ int bpad(int i) { return i + (i >> 3); }  // bank-conflict padding
 
+// Code-Doppler drift of block b at Doppler bin k in samples, reduced to
+// [0, N): llround(b Tc N f_k / f_L1) with f_L1 = 1575.42 MHz (1540 chip rates),
+// in IEEE double as written.  Delaying the folded block by it circularly
+// shifts the block's correlation by the same number of lags.
+__device__ __forceinline__ int code_shift(const ReqDesc &d, int k, int b)
+{
+    const double fk = __dadd_rn(d.lo, __dmul_rn((double)k, d.step));
+    const double x = __ddiv_rn(__dmul_rn((double)((long long)b * d.Tc * d.N), fk), 1575420000.0);
+    long long s = (long long)llround(x) % d.N;
+    return (int)(s < 0 ? s + d.N : s);
+}
+
 // Wipe + fold of samples n0 .. n0 + len - 1 (mod N) of block b into s_f,
 // FMT-specialised; the phase of the folded milliseconds advances by N D (mod
 // 2^32) from one to the next, and |x| <= 127, |LUT| <= 4096 make the 24-bit
 // multiplies exact.  Same values as wipe_fold_one.
 template <int FMT>
 __device__ __forceinline__ void box_wipe(const void *samples, int N, int Tc, const uint32_t *s_lut, uint32_t D,
-                                         int b, int n0, int len, int2 *s_f)
+                                         int b, int n0, int len, int shift, int2 *s_f)
 {
     const uint32_t dN = (uint32_t)N * D;
     const long long base = (long long)b * Tc * N;
     for (int i = threadIdx.x; i < len; i += 256) {
-        int n = n0 + i;
+        int n = n0 + i - shift;  // shift in [0, N): the block read circularly delayed
+        if (n < 0) n += N;
         if (n >= N) n -= N;
         long long ng = base + n;
         uint32_t ph = (uint32_t)ng * D;
@@ -439,17 +452,18 @@ __global__ __launch_bounds__(256) void k_box(const ReqDesc *__restrict__ R, Batc
         const int k = kb / d.Nnc, b = kb - (kb / d.Nnc) * d.Nnc;
         const int N = d.N, spc = d.spc;
         const uint32_t D = nco_step(d.fs, d.f_if, d.lo, d.step, k);
+        const int shift = d.code_doppler ? code_shift(d, k, b) : 0;
         int2 *dst = F + (d.vec_off + (long long)kb * spc) * kPolyLen;
         for (int n0 = 0; n0 < N; n0 += kBoxChunk) {
             const int cnt = min(kBoxChunk, N - n0);
             const int len = cnt + spc - 1;
             __syncthreads();  // LUT staged / previous chunk's boxcar done
             if (d.fmt == GNSS_CPLX_I8)
-                box_wipe<GNSS_CPLX_I8>(d.samples, N, d.Tc, s_lut, D, b, n0, len, s_f);
+                box_wipe<GNSS_CPLX_I8>(d.samples, N, d.Tc, s_lut, D, b, n0, len, shift, s_f);
             else if (d.fmt == GNSS_REAL_I8)
-                box_wipe<GNSS_REAL_I8>(d.samples, N, d.Tc, s_lut, D, b, n0, len, s_f);
+                box_wipe<GNSS_REAL_I8>(d.samples, N, d.Tc, s_lut, D, b, n0, len, shift, s_f);
             else
-                box_wipe<GNSS_REAL_2BIT_PACKED>(d.samples, N, d.Tc, s_lut, D, b, n0, len, s_f);
+                box_wipe<GNSS_REAL_2BIT_PACKED>(d.samples, N, d.Tc, s_lut, D, b, n0, len, shift, s_f);
             __syncthreads();
             const int n_runs = (cnt + kBoxRun - 1) / kBoxRun;
             for (int rr = threadIdx.x; rr < n_runs; rr += 256) {

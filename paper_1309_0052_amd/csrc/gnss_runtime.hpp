@@ -73,6 +73,7 @@ struct gnss_ctx {
     float threshold = 2.5f;
     int corr_pt_forced = 0; // 0: tuned / default
     int persistent = 1;     // correlation grid: 1 occupancy-sized with work counters, 0 one workgroup per item
+    int code_doppler = 0;   // 1: code-Doppler compensation of the non-coherent sum
     int max_slots = 64;     // requests per served batch
     hipStream_t stream = nullptr;
     // tables

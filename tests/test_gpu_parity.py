@@ -334,3 +334,51 @@ def test_threshold_option(ctx):
         ctx.set("threshold", -1.0)
     with pytest.raises(G.GnssError):
         ctx.set("no_such_option", 1.0)
+
+
+# ---------------------------------------------------------------------------
+# code-Doppler compensation (context option)
+# ---------------------------------------------------------------------------
+
+def test_code_doppler_compensation_matches_oracle(ctx):
+    # bins far out so that the blocks shift by several samples; every format
+    for fmt, fs, f_if in ((O.CPLX_I8, 1023000, 0.0), (O.REAL_2BIT_PACKED, 2046000, 511500.0)):
+        Tc, Nnc = 16, 5
+        lo, step, nd = -40000.0, 20000.0, 5
+        snap = _planted_snapshot(60 + fmt, fmt, fs, f_if, Tc * Nnc + 0.3, [6], 48.0, [-40000.0 + 20000.0 * 3])
+        prns = [6, 20]
+        ctx.set("code_doppler", 1)
+        try:
+            grid, peaks = _run_device(ctx, snap, synth.Search(prns, lo, lo + step * (nd - 1), step, Tc, Nnc))
+        finally:
+            ctx.set("code_doppler", 0)
+        P = O.grid_direct(snap.samples, fmt, fs, f_if, prns, lo, step, nd, Tc, Nnc, code_doppler=True)
+        worst = assert_grid_close(grid, P)
+        ref = O.peaks(P, prns, fs // 1023000, 2.5, lo, step)
+        compare_detections(peaks, ref, P)
+        plain, _ = _run_device(ctx, snap, synth.Search(prns, lo, lo + step * (nd - 1), step, Tc, Nnc))
+        assert not np.array_equal(plain[:, 0], grid[:, 0])  # bin -40 kHz: shifts applied
+        log("  code-Doppler fmt %d: max err %.2e" % (fmt, worst))
+
+
+def test_code_doppler_compensation_realigns_planted_signal(ctx):
+    # a satellite whose code rate follows its 10 kHz Doppler over 200 ms: its peak
+    # moves 2.5 samples; the compensated search finds the planted code phase
+    fs, Tc, Nnc = 2046000, 10, 20
+    D = O.nco_step(0.0, 10000.0, fs)
+    f_q = D * fs / 2.0 ** 32
+    pl = [synth.Planted(prn=9, code_phase=700, doppler_hz=f_q, cn0_dbhz=44.0)]
+    snap = synth.make_snapshot(5, O.CPLX_I8, fs, 0.0, Tc * Nnc, pl, O.ca_code, code_doppler=True)
+    srch = synth.Search([9, 10], 9000.0, 11000.0, 500.0, Tc, Nnc)
+    ctx.set("code_doppler", 1)
+    try:
+        grid, pk = _run_device(ctx, snap, srch)
+    finally:
+        ctx.set("code_doppler", 0)
+    P = O.grid_fft(snap.samples, O.CPLX_I8, fs, 0.0, srch.prns, srch.lo, srch.step, 5, Tc, Nnc,
+                   code_doppler=True)
+    assert_grid_close(grid, P)
+    assert pk[0]["detected"] and pk[0]["code_phase"] == 700 and pk[0]["doppler_bin"] == 2
+    plain, _ = _run_device(ctx, snap, srch)
+    log("  planted 10 kHz: compensated peak %.4g, plain max %.4g" % (grid[0].max(), plain[0].max()))
+    assert grid[0].max() > plain[0].max()
