@@ -127,7 +127,7 @@ def main():
                          "per item, -1 the library default")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16"],
                     help="fp16: packed FP16 transforms, FP32 power and block sums")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (counter calibration)")
@@ -183,7 +183,10 @@ def main():
     req = G.make_request(d_x.data_ptr(), snap.fmt, snap.n, snap.fs_hz, snap.f_if_hz, srch.prns,
                          srch.lo, srch.hi, srch.step, srch.T_coh, srch.N_noncoh,
                          d_grid.data_ptr(), d_pk.data_ptr())
-    pt = args.corr_ptile or ctx.autotune([req], os.path.join("/tmp", "gnss_autotune.txt"))
+    pt, sched = args.corr_ptile, args.persistent
+    if not pt or sched < 0:  # explicit tile and schedule options skip the autotuner
+        t_pt, t_sched = ctx.autotune([req], os.path.join("/tmp", "gnss_autotune.txt"))
+        pt, sched = pt or t_pt, sched if sched >= 0 else t_sched
     ctx.set("profile", 1)
     for _ in range(args.warmup):
         ctx.acquire_device(req, stream)
@@ -225,6 +228,17 @@ def main():
                 "traffic": traffic, "kernel": kern, "avg_launch_ms": round(corr_ms, 4),
                 "flops_per_launch": units * flops_unit}
 
+    # the FFT pipeline (forward FFT + correlation stages) against the HBM roofline:
+    # staged-model bytes, each stage buffer crossing HBM once (F in, G out, G in,
+    # grid out), over the two stages' measured time
+    n_vec = nd * srch.N_noncoh * (N // 1023)
+    g_vec = 8192 if args.precision == "fp16" else 16384
+    staged = n_vec * (8192 + 2 * g_vec) + n_prn * nd * N * 4
+    pipe_ms = stages["fft"][0] / max(1, stages["fft"][1]) + corr_ms
+    fft_hbm = {"staged_bytes": staged, "time_ms": round(pipe_ms, 4),
+               "achieved_GBs": round(staged / (pipe_ms / 1e3) / 1e9, 1), "peak_GBs": PEAK_HBM_GBS,
+               "frac": round(staged / (pipe_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
+
     out = {
         "metric": "search cells/s (PRNxDopplerxphasexms) + p50/p99 latency/snapshot",
         "value": value,
@@ -240,12 +254,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "n_prn": n_prn, "n_doppler": nd, "code_phases": N,
                    "T_coh_ms": srch.T_coh, "N_noncoh": srch.N_noncoh,
-                   "cells_per_snapshot": cells, "corr_ptile": pt, "precision": args.precision},
+                   "cells_per_snapshot": cells, "corr_ptile": pt, "persistent": sched,
+                   "precision": args.precision},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "min": float(lat.min()), "max": float(lat.max())},
         "wall_s": wall_s,
         "stages_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in stages.items()},
         "roofline": roofline,
+        "fft_pipeline_hbm": fft_hbm,
         "detections": {"planted": sorted(planted), "detected": sorted(detected),
                        "planted_found": sorted(planted & detected)},
         "source_hash": kernel_source_hash(),
@@ -286,7 +302,10 @@ def run_batch(args, G, torch, ctx, code_fn):
                                    srch.N_noncoh, g.data_ptr(), pk.data_ptr()))
         cells += _cells(srch, snap.fs_hz)
     torch.cuda.synchronize()
-    pt = args.corr_ptile or ctx.autotune(reqs, os.path.join("/tmp", "gnss_autotune.txt"))
+    pt, sched = args.corr_ptile, args.persistent
+    if not pt or sched < 0:  # explicit tile and schedule options skip the autotuner
+        t_pt, t_sched = ctx.autotune(reqs, os.path.join("/tmp", "gnss_autotune.txt"))
+        pt, sched = pt or t_pt, sched if sched >= 0 else t_sched
     graph = ctx.graph(reqs)
     for _ in range(args.warmup):
         graph.launch(stream)
@@ -331,7 +350,7 @@ def run_batch(args, G, torch, ctx, code_fn):
                                "16.368} MHz, 8-32 PRNs, +-2-10 kHz windows, 1 ms coh; one hipGraph "
                                "launch per step" % len(items),
                    "snapshots": len(items), "cells_per_step": cells, "corr_ptile": pt,
-                   "precision": args.precision},
+                   "persistent": sched, "precision": args.precision},
         "snapshots_per_s": len(items) / (ms_step / 1e3),
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "wall_s": wall_s, "generate_s": t_gen,

@@ -123,10 +123,11 @@ void gnss_ctx_destroy(gnss_ctx *ctx);
  * 0 = unlimited; device memory of tables and workspaces), "profile" (1:
  * record per-stage HIP events, see gnss_stage_times; 0: off), "corr_ptile"
  * (PRNs per correlation workgroup: 2 or 4; 0 = autotuned, default 2),
- * "persistent" (grid of the correlation kernel, the dominant one: 1, the
- * default, an occupancy-sized grid whose workgroups take items from per-XCD
- * work counters and then from the other XCDs' ranges; 0 one workgroup per
- * item; the other stages always run one workgroup per item),
+ * "persistent" (grid of the correlation kernel, the dominant one: 1 an
+ * occupancy-sized grid whose workgroups take items from per-XCD work counters
+ * and then from the other XCDs' ranges; 0 one workgroup per item; -1, the
+ * default, the autotuned choice or 1; the other stages always run one
+ * workgroup per item),
  * "code_doppler" (1: code-Doppler compensation of the non-coherent sum: the
  * code rate follows the carrier Doppler (f_L1 = 1540 chip rates), so block
  * b's correlation at bin f_k is taken at lag tau - llround(b T_coh N f_k /
@@ -169,13 +170,16 @@ int gnss_graph_create(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, gn
 int gnss_graph_launch(gnss_graph *graph, void *stream);
 void gnss_graph_destroy(gnss_graph *graph);
 
-/* Picks the correlation PRN tile (2 or 4) for batches with the sample rates
- * of `reqs` by timing both on the device (reqs are device-buffer requests,
- * their outputs are overwritten), or takes it from the text cache file
- * `cache_path` (nullable) keyed by device and rate signature; writes the
- * cache and sets the context to use the choice.  *chosen (nullable) gets it. */
+/* Picks the correlation kernel's PRN tile (2 or 4) and schedule (1:
+ * persistent with work counters, 0: one workgroup per item) for batches with
+ * the sample rates of `reqs` by timing the four pairs on the device (reqs are
+ * device-buffer requests, their outputs are overwritten), or takes them from
+ * the text cache file `cache_path` (nullable) keyed by device, precision and
+ * rate signature; writes the cache and sets the context to use the choice
+ * (options "corr_ptile" 2/4 and "persistent" 0/1 override it).
+ * *chosen_tile and *chosen_persistent (nullable) get it. */
 int gnss_autotune(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, const char *cache_path,
-                  int32_t *chosen);
+                  int32_t *chosen_tile, int32_t *chosen_persistent);
 
 /* ---- serving: continuous batching of submitted requests --------------- */
 /* Outcome of a finished ticket: status (GNSS_OK or the request's error),

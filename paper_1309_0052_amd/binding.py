@@ -124,7 +124,7 @@ def _load() -> ctypes.CDLL:
         "gnss_graph_launch": [vp, vp],
         "gnss_graph_destroy": [vp],
         "gnss_autotune": [vp, ctypes.POINTER(gnss_request), i32, ctypes.c_char_p,
-                          ctypes.POINTER(i32)],
+                          ctypes.POINTER(i32), ctypes.POINTER(i32)],
         "gnss_submit": [vp, ctypes.POINTER(gnss_request), ctypes.POINTER(ctypes.c_uint64)],
         "gnss_poll": [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int),
                       ctypes.POINTER(gnss_ticket_info)],
@@ -339,12 +339,14 @@ class Context:
         """Captures the batch `reqs` (device-buffer requests) into a HIP graph."""
         return Graph(self, reqs)
 
-    def autotune(self, reqs, cache_path: str | None = None) -> int:
+    def autotune(self, reqs, cache_path: str | None = None):
+        """Returns the chosen (PRN tile, persistent schedule)."""
         arr = _req_array(reqs)
-        out = ctypes.c_int32(0)
+        tile, pers = ctypes.c_int32(0), ctypes.c_int32(0)
         _check(_lib.gnss_autotune(self.handle, arr, len(reqs),
-                                  cache_path.encode() if cache_path else None, ctypes.byref(out)))
-        return out.value
+                                  cache_path.encode() if cache_path else None, ctypes.byref(tile),
+                                  ctypes.byref(pers)))
+        return tile.value, pers.value
 
     # -- serving --------------------------------------------------------------
     def submit(self, req: gnss_request) -> int:

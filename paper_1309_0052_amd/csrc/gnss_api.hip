@@ -290,7 +290,7 @@ int stage_batch(gnss_ctx *c, Workspace &w, BatchHost &B, hipStream_t s, gnss::La
     L.reqs = (const gnss::ReqDesc *)(dm + off_desc);
     L.n_req = B.n;
     L.corr_pt = B.corr_pt;
-    L.persistent = c->persistent;
+    L.persistent = persistent_for(c, B);
     L.precision = B.precision;
     for (int st = 0; st < gnss::kNumStages; ++st) L.total[st] = B.total[st];
     return GNSS_OK;
@@ -550,8 +550,9 @@ int gnss_ctx_set(gnss_ctx *ctx, const char *key, double value)
         return GNSS_OK;
     }
     if (!strcmp(key, "persistent")) {
-        if (value != 0.0 && value != 1.0) return set_err(GNSS_EINVAL, "persistent must be 0 or 1");
-        ctx->persistent = (int)value;
+        if (value != -1.0 && value != 0.0 && value != 1.0)
+            return set_err(GNSS_EINVAL, "persistent must be 0, 1 or -1 (tuned)");
+        ctx->persistent_forced = (int)value;
         return GNSS_OK;
     }
     if (!strcmp(key, "code_doppler")) {

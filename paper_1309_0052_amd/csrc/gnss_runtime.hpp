@@ -72,7 +72,8 @@ struct gnss_ctx {
     int precision = GNSS_FP32;
     float threshold = 2.5f;
     int corr_pt_forced = 0; // 0: tuned / default
-    int persistent = 1;     // correlation grid: 1 occupancy-sized with work counters, 0 one workgroup per item
+    int persistent_forced = -1;  // correlation grid: 1 occupancy-sized with work counters, 0 one
+                                 // workgroup per item, -1 tuned / default (1)
     int code_doppler = 0;   // 1: code-Doppler compensation of the non-coherent sum
     int max_slots = 64;     // requests per served batch
     hipStream_t stream = nullptr;
@@ -85,8 +86,8 @@ struct gnss_ctx {
     void *d_cs_h = nullptr;     //   code spectra * 2^-cs_exp, packed storage order
     int cs_exp = 0;
     gnss_rt::Workspace ws;      // synchronous and device-buffer calls
-    // autotuned PRN tile per sample-rate signature
-    std::map<std::string, int> tuned_pt;
+    // autotuned (PRN tile, correlation schedule) per sample-rate signature
+    std::map<std::string, std::pair<int, int>> tuned;
     // per-stage timing
     bool profile = false;
     std::vector<hipEvent_t> event_pool;
@@ -130,6 +131,7 @@ int launch(gnss_ctx *c, Workspace &w, const gnss::Launch &L, hipStream_t s, bool
 
 // autotuner lookup: the PRN tile for a batch of these plans
 int corr_ptile_for(gnss_ctx *c, const gnss::Plan *plans, int n);
+int persistent_for(gnss_ctx *c, const BatchHost &B);
 std::string rate_signature(const gnss::Plan *plans, int n);
 
 // serving loop

@@ -421,8 +421,17 @@ std::string rate_signature(const gnss::Plan *plans, int n)
 int corr_ptile_for(gnss_ctx *c, const gnss::Plan *plans, int n)
 {
     if (c->corr_pt_forced) return c->corr_pt_forced;
-    auto it = c->tuned_pt.find(rate_signature(plans, n));
-    return it != c->tuned_pt.end() ? it->second : 2;
+    auto it = c->tuned.find(rate_signature(plans, n));
+    return it != c->tuned.end() ? it->second.first : 2;
+}
+
+int persistent_for(gnss_ctx *c, const BatchHost &B)
+{
+    if (c->persistent_forced >= 0) return c->persistent_forced;
+    std::vector<gnss::Plan> spc(B.n);
+    for (int i = 0; i < B.n; ++i) spc[i].spc = B.d[i].spc;
+    auto it = c->tuned.find(rate_signature(spc.data(), B.n));
+    return it != c->tuned.end() ? it->second.second : 1;
 }
 
 static std::string device_key(int dev)
@@ -433,20 +442,28 @@ static std::string device_key(int dev)
 }
 
 // Cache file: one "key value" pair per line (key = device + rate signature).
-static void cache_read(const char *path, std::map<std::string, int> &m)
+// Cache file: one "key tile schedule" line per tuned configuration (key =
+// device, precision and rate signature).
+static void cache_read(const char *path, std::map<std::string, std::pair<int, int>> &m)
 {
     std::ifstream f(path);
-    std::string k;
-    int v;
-    while (f >> k >> v) m[k] = v;
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        std::string k;
+        int pt = 0, pers = 1;
+        if (!(is >> k >> pt)) continue;
+        if (!(is >> pers)) pers = 1;
+        m[k] = {pt, pers};
+    }
 }
 
-static void cache_write(const char *path, const std::map<std::string, int> &m)
+static void cache_write(const char *path, const std::map<std::string, std::pair<int, int>> &m)
 {
     std::string tmp = std::string(path) + ".tmp";
     {
         std::ofstream f(tmp);
-        for (auto &kv : m) f << kv.first << " " << kv.second << "\n";
+        for (auto &kv : m) f << kv.first << " " << kv.second.first << " " << kv.second.second << "\n";
     }
     (void)rename(tmp.c_str(), path);
 }
@@ -550,7 +567,8 @@ int gnss_wait(gnss_ctx *ctx, uint64_t ticket, double timeout_s, gnss_ticket_info
     return GNSS_OK;
 }
 
-int gnss_autotune(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, const char *cache_path, int32_t *chosen)
+int gnss_autotune(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, const char *cache_path,
+                  int32_t *chosen_tile, int32_t *chosen_persistent)
 {
     if (!ctx) return set_err(GNSS_EINVAL, "ctx is null");
     std::vector<gnss::Plan> plans;
@@ -561,38 +579,46 @@ int gnss_autotune(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, const 
     const std::string sig = rate_signature(plans.data(), n_req);
     const std::string key =
         device_key(ctx->device) + (ctx->precision == GNSS_FP16 ? "/fp16/" : "/fp32/") + sig;
-    std::map<std::string, int> cache;
+    std::map<std::string, std::pair<int, int>> cache;
     if (cache_path) cache_read(cache_path, cache);
     auto hit = cache.find(key);
-    int best = 0;
-    if (hit != cache.end() && gnss::corr_ptile_valid(hit->second)) {
+    std::pair<int, int> best{0, 1};
+    if (hit != cache.end() && gnss::corr_ptile_valid(hit->second.first) &&
+        (hit->second.second == 0 || hit->second.second == 1)) {
         best = hit->second;
     } else {
+        // every (PRN tile, correlation schedule) pair, fastest of 3 runs each
         double best_ms = 1e30;
-        hipEvent_t e0, e1;
-        HIP_TRY(hipEventCreate(&e0));
-        HIP_TRY(hipEventCreate(&e1));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            if (e0) (void)hipEventDestroy(e0);
+            return set_err(GNSS_EDEVICE, "hipEventCreate failed");
+        }
         for (int pt : {2, 4}) {
-            std::lock_guard<std::mutex> lk(ctx->mu);
-            BatchHost B;
-            build_batch(plans.data(), reqs, n_req, pt, ctx->threshold, ctx->precision, B);
-            gnss::Launch L;
-            if ((rc = stage_batch(ctx, ctx->ws, B, ctx->stream, L))) break;
-            double ms_min = 1e30;
-            for (int rep = 0; rep < 3; ++rep) {  // first run warms caches; keep the fastest
-                HIP_TRY(hipEventRecord(e0, ctx->stream));
-                if ((rc = launch(ctx, ctx->ws, L, ctx->stream, false))) break;
-                HIP_TRY(hipEventRecord(e1, ctx->stream));
-                HIP_TRY(hipEventSynchronize(e1));
-                float ms = 0.f;
-                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-                ms_min = std::min(ms_min, (double)ms);
+            for (int pers : {1, 0}) {
+                std::lock_guard<std::mutex> lk(ctx->mu);
+                BatchHost B;
+                build_batch(plans.data(), reqs, n_req, pt, ctx->threshold, ctx->precision, B);
+                gnss::Launch L;
+                if ((rc = stage_batch(ctx, ctx->ws, B, ctx->stream, L))) break;
+                L.persistent = pers;
+                double ms_min = 1e30;
+                for (int rep = 0; rep < 3 && !rc; ++rep) {
+                    float ms = 0.f;
+                    if (hipEventRecord(e0, ctx->stream) != hipSuccess) rc = set_err(GNSS_EDEVICE, "hipEventRecord");
+                    if (!rc) rc = launch(ctx, ctx->ws, L, ctx->stream, false);
+                    if (!rc && (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                        rc = set_err(GNSS_EDEVICE, "timing events failed");
+                    if (!rc) ms_min = std::min(ms_min, (double)ms);
+                }
+                if (rc) break;
+                if (ms_min < best_ms) {
+                    best_ms = ms_min;
+                    best = {pt, pers};
+                }
             }
             if (rc) break;
-            if (ms_min < best_ms) {
-                best_ms = ms_min;
-                best = pt;
-            }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -602,9 +628,10 @@ int gnss_autotune(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, const 
     }
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
-        ctx->tuned_pt[sig] = best;
+        ctx->tuned[sig] = best;
     }
-    if (chosen) *chosen = best;
+    if (chosen_tile) *chosen_tile = best.first;
+    if (chosen_persistent) *chosen_persistent = best.second;
     return GNSS_OK;
 }
 

@@ -95,19 +95,22 @@ def test_batch_equals_alone_and_oracle(ctx, small):
         compare_detections(alone[i][1], ref, P)
 
 
-def test_prn_tile_does_not_change_results(ctx, small):
+def test_tile_and_schedule_do_not_change_results(ctx, small):
     items, reqs, alone = small
     try:
         for pt in (2, 4):
-            ctx.set("corr_ptile", pt)
-            for r in reqs:
-                r.clear()
-            ctx.acquire_batch_device([r.req for r in reqs])
-            for i, r in enumerate(reqs):
-                g, p = r.result()
-                assert np.array_equal(g, alone[i][0]) and np.array_equal(p, alone[i][1]), (pt, i)
+            for sched in (0, 1):
+                ctx.set("corr_ptile", pt)
+                ctx.set("persistent", sched)
+                for r in reqs:
+                    r.clear()
+                ctx.acquire_batch_device([r.req for r in reqs])
+                for i, r in enumerate(reqs):
+                    g, p = r.result()
+                    assert np.array_equal(g, alone[i][0]) and np.array_equal(p, alone[i][1]), (pt, sched, i)
     finally:
         ctx.set("corr_ptile", 0)
+        ctx.set("persistent", -1)
 
 
 def test_graph_replays_match_eager(ctx, small):
@@ -133,10 +136,10 @@ def test_graph_replays_match_eager(ctx, small):
 def test_autotune_and_cache(ctx, small, tmp_path):
     items, reqs, alone = small
     path = str(tmp_path / "tune.txt")
-    pt = ctx.autotune([r.req for r in reqs], path)
-    assert pt in (2, 4)
-    assert os.path.exists(path) and open(path).read().split()[-1] == str(pt)
-    assert ctx.autotune([r.req for r in reqs], path) == pt
+    pt, sched = ctx.autotune([r.req for r in reqs], path)
+    assert pt in (2, 4) and sched in (0, 1)
+    assert os.path.exists(path) and open(path).read().split()[-2:] == [str(pt), str(sched)]
+    assert ctx.autotune([r.req for r in reqs], path) == (pt, sched)  # from the cache
     for r in reqs:
         r.clear()
     ctx.acquire_batch_device([r.req for r in reqs])
