@@ -124,7 +124,8 @@ hipError_t launch_batch(const Launch &L, const Tables &T, int2 *d_F, void *d_G, 
                         double *d_part, int n_cu, hipStream_t s, hipEvent_t *marks);
 int corr_ptile_valid(int pt);
 constexpr int kBoxChunk = 2048;
-constexpr int kPeakThreads = 256;
+constexpr int kPeakThreads = 256;   // threads of the column-max kernel (256-lag blocks)
+constexpr int kArgThreads = 1024;   // threads of the per-PRN argmax kernel
 
 // standalone wipe + fold (stage entry point)
 hipError_t launch_wipe_fold(const void *d_samples, const Plan &p, const uint32_t *d_lut,

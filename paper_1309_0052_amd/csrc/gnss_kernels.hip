@@ -413,6 +413,7 @@ __device__ __forceinline__ void box_wipe(const void *samples, int N, int Tc, con
         long long ng = base + n;
         uint32_t ph = (uint32_t)ng * D;
         int yr = 0, yi = 0;
+#pragma unroll 4
         for (int c = 0; c < Tc; ++c) {
             int xr, xi;
             load_sample(samples, FMT, ng, xr, xi);
@@ -976,7 +977,22 @@ __global__ __launch_bounds__(kPeakThreads) void k_colmax(const ReqDesc *__restri
             float best = col[0];
             int kb = 0;
             colsum = (double)best;
-            for (int k = 1; k < d.n_dopp; ++k) {
+            int k = 1;
+            // eight rows' loads in flight at a time; max and sum in row order
+            for (; k + 8 <= d.n_dopp; k += 8) {
+                float v[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[j] = col[(long long)(k + j) * N];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    colsum += (double)v[j];
+                    if (v[j] > best) {
+                        best = v[j];
+                        kb = k + j;
+                    }
+                }
+            }
+            for (; k < d.n_dopp; ++k) {
                 float v = col[(long long)k * N];
                 colsum += (double)v;
                 if (v > best) {
@@ -1000,12 +1016,12 @@ __global__ __launch_bounds__(kPeakThreads) void k_colmax(const ReqDesc *__restri
 
 // Work item = (request, PRN): argmax (lowest tau on ties), second peak outside
 // +-spc (circular), mean, ratio test.
-__global__ __launch_bounds__(kPeakThreads) void k_peak(const ReqDesc *__restrict__ R, BatchHdr *H,
+__global__ __launch_bounds__(kArgThreads) void k_peak(const ReqDesc *__restrict__ R, BatchHdr *H,
                                                        const long long *pre, const float *Q,
                                                        const int32_t *K, const double *part)
 {
-    __shared__ float sv[kPeakThreads];
-    __shared__ int st[kPeakThreads];
+    __shared__ float sv[kArgThreads];
+    __shared__ int st[kArgThreads];
     const int tid = threadIdx.x;
     const int n_req = H->n_req;
     const long long total = H->total[kStPeak];
@@ -1018,7 +1034,7 @@ __global__ __launch_bounds__(kPeakThreads) void k_peak(const ReqDesc *__restrict
         const float *q = Q + d.qk_off + (long long)p * N;
         float bv = -INFINITY;
         int bt = 0x7fffffff;
-        for (int tau = tid; tau < N; tau += kPeakThreads) {
+        for (int tau = tid; tau < N; tau += kArgThreads) {
             float v = q[tau];
             if (v > bv) {
                 bv = v;
@@ -1029,7 +1045,7 @@ __global__ __launch_bounds__(kPeakThreads) void k_peak(const ReqDesc *__restrict
         sv[tid] = bv;
         st[tid] = bt;
         __syncthreads();
-        for (int s = kPeakThreads / 2; s > 0; s >>= 1) {
+        for (int s = kArgThreads / 2; s > 0; s >>= 1) {
             if (tid < s) {
                 float v2 = sv[tid + s];
                 int t2 = st[tid + s];
@@ -1045,14 +1061,14 @@ __global__ __launch_bounds__(kPeakThreads) void k_peak(const ReqDesc *__restrict
         const int tstar = (st[0] >= 0 && st[0] < N) ? st[0] : 0;
         __syncthreads();
         float m2 = -INFINITY;
-        for (int tau = tid; tau < N; tau += kPeakThreads) {
+        for (int tau = tid; tau < N; tau += kArgThreads) {
             int dd = abs(tau - tstar);
             dd = min(dd, N - dd);
             if (dd > d.spc) m2 = fmaxf(m2, q[tau]);
         }
         sv[tid] = m2;
         __syncthreads();
-        for (int s = kPeakThreads / 2; s > 0; s >>= 1) {
+        for (int s = kArgThreads / 2; s > 0; s >>= 1) {
             if (tid < s) sv[tid] = fmaxf(sv[tid], sv[tid + s]);
             __syncthreads();
         }
@@ -1207,7 +1223,7 @@ hipError_t launch_batch(const Launch &L, const Tables &T, int2 *d_F, void *d_G, 
         hipLaunchKernelGGL(k_colmax, dim3(grid_for(L.total[kStColmax], cap, false)), dim3(kPeakThreads), 0, s,
                            L.reqs, L.hdr, L.pre, d_Q, d_K, d_part);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_peak, dim3(grid_for(L.total[kStPeak], 4LL * n_cu, false)), dim3(kPeakThreads), 0,
+        hipLaunchKernelGGL(k_peak, dim3(grid_for(L.total[kStPeak], 4LL * n_cu, false)), dim3(kArgThreads), 0,
                            s, L.reqs, L.hdr, L.pre, d_Q, d_K, d_part);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const long long ni = (L.total[kStPeak] + 63) / 64;
