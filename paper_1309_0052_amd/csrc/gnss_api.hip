@@ -10,7 +10,7 @@
 //
 // Every search runs as a batch: the host writes a table of request
 // descriptors and per-stage work-item prefix sums into pinned memory, one
-// copy moves it to the device, and the persistent stage kernels walk it.  A
+// copy moves it to the device, and the stage kernels walk it.  A
 // single request is a batch of one; a batch can be captured once into a
 // HIP graph and replayed (gnss_graph_*).
 #include "fft2048.hpp"

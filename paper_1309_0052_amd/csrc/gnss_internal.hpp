@@ -66,8 +66,9 @@ inline size_t g_bytes(long long n_vec, int precision)
 }
 
 // ---------------------------------------------------------------------------
-// batched hot path: every stage kernel is persistent and walks a device-
-// resident table of requests (a single request is a batch of one)
+// batched hot path: every stage kernel walks a device-resident table of
+// requests (a single request is a batch of one); the correlation kernel can
+// run persistent, the others run one workgroup per work item
 // ---------------------------------------------------------------------------
 enum Stage { kStBox = 0, kStVec, kStCorr, kStColmax, kStPeak, kNumStages };
 constexpr int kXcds = 8;

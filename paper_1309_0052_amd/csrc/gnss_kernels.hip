@@ -18,14 +18,20 @@
 // per PRN serves every sample rate, and each transform lives in one
 // wavefront's registers.
 //
-// Kernel sequence per request:
-//   k_wipe_fold_box  NCO wipe-off + coherent fold + boxcar + polyphase split
+// Kernel sequence of a batch (every kernel walks a device table of the batch's
+// requests; a single request is a batch of one):
+//   k_reset          clears the work counters (a kernel, so the sequence can be
+//                    captured in a graph)
+//   k_box            NCO wipe-off + coherent fold + boxcar + polyphase split
 //                    (exact int32)                     -> F[k][b][s][1024]
 //   k_fft_poly       forward 2048-point FFT of every g_s -> G (storage order)
 //   k_corr           per (PRN tile, Doppler, phase): G * conj(code spectrum),
 //                    IFFT, |.|^2, sum over blocks in registers -> grid
 //   k_colmax/k_peak  column max over Doppler, argmax, second peak, mean
 //   k_interp         FP64 parabolic refinement
+// FP16 contexts use k_fft_poly_h and k_corr_h (packed half precision with
+// per-vector power-of-two scaling).  k_track computes the tracking channel's
+// early / prompt / late correlators (Fig. 3).
 #include "fft2048.hpp"
 #include "gnss_internal.hpp"
 
