@@ -32,11 +32,40 @@ if ROOT not in sys.path:
 # MI355X vector peaks (256 CU x 2.4 GHz): FP32 with packed FP32 instructions,
 # and FP16 with packed FP16 instructions, both 256 flop/clock/CU
 PEAK_VALU_TFLOPS = {"fp32": 157.3, "fp16": 157.3}
+# dense FP16 matrix-core peak (FP32 accumulation), MI355X
+PEAK_MFMA_F16_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 # integer VALU: 256 CU x 64 lanes x 2.4 GHz, a multiply-add counted as 2 ops
 PEAK_INT_TOPS = 78.6
-DTYPE = {"fp32": "f32", "fp16": "f16"}
-CORR_KERNEL = {"fp32": "k_corr", "fp16": "k_corr_h"}
+PRECISIONS = ["fp32", "fp16", "fp16pfa"]
+DTYPE = {"fp32": "f32", "fp16": "f16", "fp16pfa": "f16"}
+CORR_KERNEL = {"fp32": "k_corr", "fp16": "k_corr_h", "fp16pfa": "k_corr_x"}
+# what bounds each mode's correlation kernel, and that unit's peak
+ROOF = {"fp32": ("alu", 157.3), "fp16": ("alu", 157.3), "fp16pfa": ("mfma", PEAK_MFMA_F16_TFLOPS)}
+# bytes of one stored block spectrum (one polyphase vector)
+G_VEC_BYTES = {"fp32": 16384, "fp16": 8192, "fp16pfa": 4224}
+# matrix-core flops of one 1023-point inverse transform in the exact-length
+# mode: 54 16x16x32 FP16 products of 16384 flops each
+PFA_MFMA_FLOPS = 54 * 16384
+
+
+def precision_const(G, name: str) -> int:
+    return {"fp32": G.GNSS_FP32, "fp16": G.GNSS_FP16, "fp16pfa": G.GNSS_FP16_PFA}[name]
+
+
+def corr_roofline(prec: str, flops: float, corr_ms: float, traffic, transforms: int) -> dict:
+    """Roofline object of the correlation kernel: algorithmic flops (exact
+    length-N FFT correlation) per launch over its average launch time."""
+    bound, peak = ROOF[prec]
+    achieved = flops / (corr_ms / 1e3) / 1e12
+    r = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+         "frac": round(achieved / peak, 4), "traffic": traffic, "kernel": CORR_KERNEL[prec],
+         "avg_launch_ms": round(corr_ms, 4), "flops_per_launch": flops}
+    if prec == "fp16pfa":
+        issued = transforms * PFA_MFMA_FLOPS
+        r["mfma_flops_issued_per_launch"] = issued
+        r["mfma_issued_frac"] = round(issued / (corr_ms / 1e3) / 1e12 / peak, 4)
+    return r
 
 
 def kernel_source_hash() -> str:
@@ -128,8 +157,9 @@ def main():
     ap.add_argument("--persistent", type=int, default=-1, choices=[-1, 0, 1],
                     help="correlation grid: 1 occupancy-sized with work counters, 0 one workgroup "
                          "per item, -1 the library default")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16"],
-                    help="fp16: packed FP16 transforms, FP32 power and block sums")
+    ap.add_argument("--precision", default="fp32", choices=PRECISIONS,
+                    help="fp16: packed FP16 transforms, FP32 power and block sums; fp16pfa: exact-length "
+                         "1023-point transforms on the matrix cores (FP16 operands, FP32 accumulation)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -148,7 +178,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    prec = G.GNSS_FP16 if args.precision == "fp16" else G.GNSS_FP32
+    prec = precision_const(G, args.precision)
     ctx = G.Context(0, precision=prec)
     if args.corr_ptile:
         ctx.set("corr_ptile", args.corr_ptile)
@@ -223,21 +253,16 @@ def main():
     corr_ms = stages["corr"][0] / max(1, stages["corr"][1])
     units = n_prn * nd * srch.N_noncoh  # (PRN, Doppler, block) correlations per launch
     flops_unit = 5.0 * N * math.log2(N) + 10.0 * N
-    achieved = units * flops_unit / (corr_ms / 1e3) / 1e12
     wl = args.workload
     kern = CORR_KERNEL[args.precision]
     traffic = read_traffic(kern[2:], wl)
-    peak = PEAK_VALU_TFLOPS[args.precision]
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                "traffic": traffic, "kernel": kern, "avg_launch_ms": round(corr_ms, 4),
-                "flops_per_launch": units * flops_unit}
+    roofline = corr_roofline(args.precision, units * flops_unit, corr_ms, traffic, units * (N // 1023))
 
     # the FFT pipeline (forward FFT + correlation stages) against the HBM roofline:
     # staged-model bytes, each stage buffer crossing HBM once (F in, G out, G in,
     # grid out), over the two stages' measured time
     n_vec = nd * srch.N_noncoh * (N // 1023)
-    g_vec = 8192 if args.precision == "fp16" else 16384
+    g_vec = G_VEC_BYTES[args.precision]
     staged = n_vec * (8192 + 2 * g_vec) + n_prn * nd * N * 4
     pipe_ms = stages["fft"][0] / max(1, stages["fft"][1]) + corr_ms
     fft_hbm = {"staged_bytes": staged, "time_ms": round(pipe_ms, 4),
@@ -341,11 +366,12 @@ def run_batch(args, G, torch, ctx, code_fn):
             found += int(det.get(pl.prn, -1) == pl.code_phase)
     corr_ms = stages["corr"][0] / max(1, stages["corr"][1])
     units_flops = 0.0
+    transforms = 0
     for snap, srch in items:
         N = snap.fs_hz // 1000
         nd = G.n_doppler(srch.lo, srch.hi, srch.step)
         units_flops += len(srch.prns) * nd * srch.N_noncoh * (5.0 * N * math.log2(N) + 10.0 * N)
-    achieved = units_flops / (corr_ms / 1e3) / 1e12
+        transforms += len(srch.prns) * nd * srch.N_noncoh * (N // 1023)
     out = {
         "metric": "search cells/s (PRNxDopplerxphasexms) + p50/p99 latency/snapshot",
         "value": cells / (ms_step / 1e3), "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
@@ -360,10 +386,8 @@ def run_batch(args, G, torch, ctx, code_fn):
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "wall_s": wall_s, "generate_s": t_gen,
         "stages_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in stages.items()},
-        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_VALU_TFLOPS[args.precision],
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_VALU_TFLOPS[args.precision], 4),
-                     "traffic": read_traffic(CORR_KERNEL[args.precision][2:], "batch"),
-                     "kernel": CORR_KERNEL[args.precision], "avg_launch_ms": round(corr_ms, 4)},
+        "roofline": corr_roofline(args.precision, units_flops, corr_ms,
+                                  read_traffic(CORR_KERNEL[args.precision][2:], "batch"), transforms),
         "planted_recovered": [found, total],
         "source_hash": kernel_source_hash(),
     }
@@ -395,7 +419,7 @@ def run_serve(args, G, torch, ctx, code_fn):
     rng = np.random.default_rng(5)
     for rate in rates:
         sctx = G.Context(0, hbm_budget_bytes=int(args.budget_gb * (1 << 30)),
-                         precision=G.GNSS_FP16 if args.precision == "fp16" else G.GNSS_FP32)
+                         precision=precision_const(G, args.precision))
         n_total = args.serve_warmup + args.serve_n
         gaps = rng.exponential(1.0 / rate, n_total)
         sched = np.cumsum(gaps)
@@ -575,9 +599,10 @@ def run_track(args, G, torch, ctx, code_fn):
 
 
 def run_precision(args, G, torch, ctx, code_fn):
-    """The strong-signal snapshot on FP32 and FP16 contexts of the same GPU:
-    device time of each, and the FP16 grid and detections against the FP32
-    ones (the error against the FP64 oracle is in the FP16 tests)."""
+    """The strong-signal snapshot on FP32, FP16 and exact-length FP16
+    contexts of the same GPU: device time of each, and each FP16 mode's grid
+    and detections against the FP32 ones (the error against the FP64 oracle
+    is in the FP16 tests)."""
     import numpy as np
     import synth
 
@@ -589,8 +614,8 @@ def run_precision(args, G, torch, ctx, code_fn):
     x = torch.from_numpy(np.ascontiguousarray(snap.samples)).cuda()
     res = {}
     ctx.close()
-    for name, prec in (("fp32", G.GNSS_FP32), ("fp16", G.GNSS_FP16)):
-        c = G.Context(0, precision=prec)
+    for name in PRECISIONS:
+        c = G.Context(0, precision=precision_const(G, name))
         g = torch.empty(n_prn * nd * N, dtype=torch.float32, device="cuda")
         pk = torch.zeros(n_prn * 48, dtype=torch.uint8, device="cuda")
         req = G.make_request(x.data_ptr(), snap.fmt, snap.n, snap.fs_hz, snap.f_if_hz, srch.prns, srch.lo,
@@ -608,26 +633,32 @@ def run_precision(args, G, torch, ctx, code_fn):
         res[name] = (ms, g.cpu().numpy().reshape(n_prn, nd, N).astype(np.float64),
                      pk.cpu().numpy().view(G.PEAK_DTYPE).copy())
         c.close()
-    (t32, P32, k32), (t16, P16, k16) = res["fp32"], res["fp16"]
-    mixed = max(float(np.max(np.abs(P16[i] - P32[i]) / (P32[i] + P32[i].mean()))) for i in range(n_prn))
-    same = int(sum(int(a["detected"]) == int(b["detected"]) and int(a["code_phase"]) == int(b["code_phase"])
-                   and int(a["doppler_bin"]) == int(b["doppler_bin"]) for a, b in zip(k16, k32)))
-    peak_rel = []
-    for pl in snap.planted:
-        i = srch.prns.index(pl.prn)
-        kb, tau = int(k32[i]["doppler_bin"]), int(k32[i]["code_phase"])
-        peak_rel.append(abs(P16[i, kb, tau] - P32[i, kb, tau]) / P32[i, kb, tau])
+    t32, P32, k32 = res["fp32"]
+    modes = {"fp32": {"ms": t32}}
+    for name in ("fp16", "fp16pfa"):
+        t, P, k = res[name]
+        mixed = max(float(np.max(np.abs(P[i] - P32[i]) / (P32[i] + P32[i].mean()))) for i in range(n_prn))
+        same = int(sum(int(a["detected"]) == int(b["detected"]) and int(a["code_phase"]) == int(b["code_phase"])
+                       and int(a["doppler_bin"]) == int(b["doppler_bin"]) for a, b in zip(k, k32)))
+        peak_rel = []
+        for pl in snap.planted:
+            i = srch.prns.index(pl.prn)
+            kb, tau = int(k32[i]["doppler_bin"]), int(k32[i]["code_phase"])
+            peak_rel.append(abs(P[i, kb, tau] - P32[i, kb, tau]) / P32[i, kb, tau])
+        modes[name] = {"ms": t, "speedup_vs_fp32": t32 / t, "max_mixed_rel_power_diff_vs_fp32": mixed,
+                       "planted_peak_cell_rel_diff_max": max(peak_rel), "detections_identical": same,
+                       "prns": n_prn}
+    head = args.precision if args.precision != "fp32" else "fp16"
     cells = n_prn * nd * N * srch.T_coh * srch.N_noncoh
     out = {
         "metric": "search cells/s (PRNxDopplerxphasexms) + p50/p99 latency/snapshot",
-        "value": cells / (t16 / 1e3), "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": t16, "higher_is_better": True, "scaling": "weak",
+        "value": cells / (res[head][0] / 1e3), "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res[head][0], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f16", "data": "synthetic",
-        "config": {"workload": "FP16 path on the strong-signal snapshot (real 2-bit IF, 4.092 MHz, 10 ms; "
-                               "32 PRN x 21 bins x 10 ms), against the FP32 path on the same GPU"},
-        "fp32_ms": t32, "fp16_ms": t16, "speedup": t32 / t16,
-        "fp16_vs_fp32": {"max_mixed_rel_power_diff": mixed, "planted_peak_cell_rel_diff_max": max(peak_rel),
-                         "detections_identical": same, "prns": n_prn},
+        "config": {"workload": "%s path on the strong-signal snapshot (real 2-bit IF, 4.092 MHz, 10 ms; "
+                               "32 PRN x 21 bins x 10 ms), against the FP32 path on the same GPU" % head,
+                   "precision": head},
+        "modes": modes,
         "source_hash": kernel_source_hash(),
     }
     print(json.dumps(out), flush=True)

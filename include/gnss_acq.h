@@ -63,6 +63,10 @@ extern "C" {
 #define GNSS_FP32 0  /* FP32 transforms and power                             */
 #define GNSS_FP16 1  /* packed FP16 transforms with per-vector power-of-two
                         scaling; FP32 |.|^2 and block sums                    */
+#define GNSS_FP16_PFA 2 /* exact-length 1023-point transforms (Good-Thomas
+                        31 x 33, no zero padding) as FP16 x FP16 -> FP32
+                        matrix-core products, the same per-vector scaling;
+                        FP32 |.|^2 and block sums                            */
 
 /* One detection result per requested PRN (Sec. 3: coarse Doppler and code
  * phase; refined values come from the FP64 parabolas). */
@@ -113,8 +117,10 @@ int gnss_acquire(const void *samples, int32_t fmt, size_t n, double fs, double f
  * demand up to hbm_budget_bytes (0 = no limit).  precision: GNSS_FP32, or
  * GNSS_FP16 for packed FP16 transforms (Fig. 2's FFT, spectrum product and
  * IFFT) with per-vector power-of-two scaling that keeps every intermediate
- * inside the FP16 range, |.|^2 and block sums in FP32; every search on the
- * context uses it.  Errors: GNSS_EINVAL (unknown precision or device),
+ * inside the FP16 range, |.|^2 and block sums in FP32, or GNSS_FP16_PFA for
+ * the same correlation with exact-length 1023-point transforms whose passes
+ * run on the matrix cores (FP16 operands, FP32 accumulation); every search on
+ * the context uses it.  Errors: GNSS_EINVAL (unknown precision or device),
  * GNSS_ENOMEM, GNSS_EDEVICE. */
 int gnss_ctx_create(gnss_ctx **out, int device, size_t hbm_budget_bytes, int precision);
 void gnss_ctx_destroy(gnss_ctx *ctx);
@@ -239,6 +245,17 @@ int gnss_wipe_fold(gnss_ctx *ctx, const gnss_request *req, int32_t *d_out, void 
  * (inverse != 0) unnormalised exp(+2 pi i nk/2048).  d_in and d_out hold
  * batch*2048 complex values and may not overlap. */
 int gnss_fft2048(gnss_ctx *ctx, const float *d_in, float *d_out, int32_t batch,
+                 int32_t inverse, void *stream);
+
+/* Batched exact-length 1023-point DFT in the GNSS_FP16_PFA arithmetic (the
+ * Good-Thomas 31 x 33 transform of that mode: per-vector power-of-two scaling
+ * from the l1 norm, FP16 operands, FP32 accumulation), natural order in and
+ * out, interleaved float re/im, forward exp(-2 pi i nk/1023) or (inverse != 0)
+ * unnormalised exp(+2 pi i nk/1023).  d_in and d_out (device memory, owned by
+ * the caller) hold batch*1023 complex values, batch <= 2^28, and may not
+ * overlap.  Errors: GNSS_EINVAL (arguments), GNSS_ENOTSUP (context not
+ * created with GNSS_FP16_PFA), GNSS_EDEVICE. */
+int gnss_dft1023(gnss_ctx *ctx, const float *d_in, float *d_out, int32_t batch,
                  int32_t inverse, void *stream);
 
 /* Detection and refinement on a device grid [n_prn][n_dopp][N] (rule in the

@@ -30,6 +30,7 @@ GNSS_CPLX_I8 = 1
 GNSS_REAL_2BIT_PACKED = 2
 GNSS_FP32 = 0
 GNSS_FP16 = 1
+GNSS_FP16_PFA = 2
 
 EXPORTED = [
     "gnss_acquire", "gnss_ctx_create", "gnss_ctx_destroy", "gnss_ctx_set",
@@ -37,7 +38,7 @@ EXPORTED = [
     "gnss_nco_lut", "gnss_wipe_fold", "gnss_fft2048", "gnss_peaks", "gnss_stage_times",
     "gnss_strerror", "gnss_last_error", "gnss_acquire_batch_device", "gnss_graph_create",
     "gnss_graph_launch", "gnss_graph_destroy", "gnss_autotune", "gnss_submit", "gnss_poll",
-    "gnss_wait", "gnss_track", "gnss_track_device",
+    "gnss_wait", "gnss_track", "gnss_track_device", "gnss_dft1023",
 ]
 
 GNSS_STAGE_WIPE_FOLD = 0
@@ -117,6 +118,7 @@ def _load() -> ctypes.CDLL:
         "gnss_nco_lut": [vp, vp, vp, vp],
         "gnss_wipe_fold": [vp, ctypes.POINTER(gnss_request), vp, vp],
         "gnss_fft2048": [vp, vp, vp, i32, i32, vp],
+        "gnss_dft1023": [vp, vp, vp, i32, i32, vp],
         "gnss_peaks": [vp, vp, pi32, i32, i32, i32, i32, dbl, dbl, vp, vp],
         "gnss_stage_times": [vp, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64), i32, i32],
         "gnss_acquire_batch_device": [vp, ctypes.POINTER(gnss_request), i32, vp],
@@ -388,6 +390,10 @@ class Context:
 
     def fft2048(self, d_in: int, d_out: int, batch: int, inverse: bool, stream=None):
         _check(_lib.gnss_fft2048(self.handle, d_in, d_out, int(batch), 1 if inverse else 0,
+                                 _stream_ptr(stream)))
+
+    def dft1023(self, d_in: int, d_out: int, batch: int, inverse: bool, stream=None):
+        _check(_lib.gnss_dft1023(self.handle, d_in, d_out, int(batch), 1 if inverse else 0,
                                  _stream_ptr(stream)))
 
     def peaks(self, d_grid: int, prns, n_dopp: int, N: int, spc: int, doppler_lo: float,

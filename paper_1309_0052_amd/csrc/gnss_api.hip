@@ -171,7 +171,9 @@ static long long cdiv(long long a, long long b) { return (a + b - 1) / b; }
 void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int corr_pt,
                  float threshold, int precision, BatchHost &B)
 {
-    const int corr_w = precision == GNSS_FP16 ? gnss::kCorrWavesH : gnss::kCorrWaves;
+    const int corr_w = precision == GNSS_FP16       ? gnss::kCorrWavesH
+                       : precision == GNSS_FP16_PFA ? gnss::kCorrWavesX
+                                                    : gnss::kCorrWaves;
     B.d.assign(n, gnss::ReqDesc{});
     B.pre.assign((size_t)gnss::kNumStages * (n + 1), 0);
     B.grid_off.assign(n, -1);
@@ -335,7 +337,7 @@ int launch(gnss_ctx *c, Workspace &w, const gnss::Launch &L, hipStream_t s, bool
         for (auto &e : ev)
             if ((rc = take_event(c, &e))) return rc;
     }
-    const gnss::Tables T{c->d_lut, c->d_tw, c->d_cs, c->d_tw_h, c->d_cs_h, c->cs_exp};
+    const gnss::Tables T{c->d_lut, c->d_tw, c->d_cs, c->d_tw_h, c->d_cs_h, c->d_frags_x, c->d_cs_x, c->cs_exp};
     HIP_TRY(gnss::launch_batch(L, T, (int2 *)w.F.p, w.G.p, (float *)w.Q.p, (int32_t *)w.K.p, (double *)w.part.p,
                                c->n_cu, s, prof ? ev.data() : nullptr));
     if (prof) c->pending.push_back(ev);
@@ -365,8 +367,9 @@ int ctx_init_tables(gnss_ctx *c)
     const size_t codes_b = (gnss::kMaxPrn + 1) * gnss::kCodeLen;
     const size_t tw_b = gnss::kTwElems * sizeof(float2);
     const size_t cs_b = (size_t)(gnss::kMaxPrn + 1) * gnss::kVec * sizeof(float4);
-    const bool h = c->precision == GNSS_FP16;
-    const size_t table_bytes = lut_b + codes_b + tw_b + cs_b + (h ? gnss::kTwHBytes + gnss::kCsHBytes : 0);
+    const bool h = c->precision == GNSS_FP16, x = c->precision == GNSS_FP16_PFA;
+    const size_t table_bytes = lut_b + codes_b + tw_b + cs_b + (h ? gnss::kTwHBytes + gnss::kCsHBytes : 0) +
+                               (x ? gnss::kFragXBytes + gnss::kCsXBytes : 0);
     if (c->budget && table_bytes > c->budget)
         return set_err(GNSS_ENOMEM, "HBM budget %zu below the %zu bytes of tables", c->budget, table_bytes);
     HIP_TRY(hipMalloc(&c->d_lut, lut_b));
@@ -395,6 +398,31 @@ int ctx_init_tables(gnss_ctx *c)
         HIP_TRY(gnss::launch_tables_h(c->d_cs, c->d_tw_h, c->d_cs_h, c->cs_exp, c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));
     }
+    if (x) {
+        // exact 1023-point code spectra in FP64, their common exponent
+        // (max |C| * 2^-cs_exp <= 1), then the FP16 fragment tables
+        HIP_TRY(hipMalloc(&c->d_frags_x, gnss::kFragXBytes));
+        HIP_TRY(hipMalloc(&c->d_cs_x, gnss::kCsXBytes));
+        double2 *d_stage = nullptr;
+        HIP_TRY(hipMalloc(&d_stage, gnss::kCsXStageBytes));
+        std::vector<double2> cs(gnss::kCsXStageBytes / sizeof(double2));
+        hipError_t err = gnss::launch_tables_x_frags(c->d_frags_x, c->stream);
+        if (err == hipSuccess) err = gnss::launch_code_spectra_x(c->d_codes, d_stage, c->stream);
+        if (err == hipSuccess) err = hipMemcpyAsync(cs.data(), d_stage, gnss::kCsXStageBytes, hipMemcpyDeviceToHost,
+                                                    c->stream);
+        if (err == hipSuccess) err = hipStreamSynchronize(c->stream);
+        if (err == hipSuccess) {
+            double m = 0.0;
+            for (const double2 &v : cs) m = std::max(m, std::hypot(v.x, v.y));
+            int e = 0;
+            while (std::ldexp(1.0, e) < m * (1.0 + 0x1p-10)) ++e;
+            c->cs_exp = e;
+            err = gnss::launch_code_spectra_x_pack(d_stage, c->d_cs_x, c->cs_exp, c->stream);
+        }
+        if (err == hipSuccess) err = hipStreamSynchronize(c->stream);
+        (void)hipFree(d_stage);
+        HIP_TRY(err);
+    }
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, c->device));
     c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
@@ -418,6 +446,8 @@ void ctx_free(gnss_ctx *c)
     if (c->d_cs) (void)hipFree(c->d_cs);
     if (c->d_tw_h) (void)hipFree(c->d_tw_h);
     if (c->d_cs_h) (void)hipFree(c->d_cs_h);
+    if (c->d_frags_x) (void)hipFree(c->d_frags_x);
+    if (c->d_cs_x) (void)hipFree(c->d_cs_x);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     if (switched) (void)hipSetDevice(cur);
     delete c;
@@ -483,8 +513,8 @@ int gnss_ctx_create(gnss_ctx **out, int device, size_t hbm_budget_bytes, int pre
 {
     if (!out) return set_err(GNSS_EINVAL, "out is null");
     *out = nullptr;
-    if (precision != GNSS_FP32 && precision != GNSS_FP16)
-        return set_err(GNSS_EINVAL, "precision %d is not GNSS_FP32 or GNSS_FP16", precision);
+    if (precision != GNSS_FP32 && precision != GNSS_FP16 && precision != GNSS_FP16_PFA)
+        return set_err(GNSS_EINVAL, "precision %d is not GNSS_FP32, GNSS_FP16 or GNSS_FP16_PFA", precision);
     int count = 0;
     hipError_t e = hipGetDeviceCount(&count);
     if (e != hipSuccess || count < 1) {
@@ -828,6 +858,20 @@ int gnss_fft2048(gnss_ctx *ctx, const float *d_in, float *d_out, int32_t batch, 
     if (g.rc) return g.rc;
     HIP_TRY(gnss::launch_fft_test((const float2 *)d_in, (float2 *)d_out, batch, inverse ? 1 : 0, ctx->d_tw,
                                   (hipStream_t)stream));
+    return GNSS_OK;
+}
+
+int gnss_dft1023(gnss_ctx *ctx, const float *d_in, float *d_out, int32_t batch, int32_t inverse, void *stream)
+{
+    if (!ctx || !d_in || !d_out) return set_err(GNSS_EINVAL, "null argument");
+    if (batch < 0 || batch > (1 << 28)) return set_err(GNSS_EINVAL, "batch outside [0, 2^28]");
+    if (ctx->precision != GNSS_FP16_PFA) return set_err(GNSS_ENOTSUP, "gnss_dft1023 needs a GNSS_FP16_PFA context");
+    if (batch == 0) return GNSS_OK;
+    if (d_in == d_out) return set_err(GNSS_EINVAL, "in-place transform is not supported");
+    DeviceGuard g(ctx->device);
+    if (g.rc) return g.rc;
+    HIP_TRY(gnss::launch_dft1023_test((const float2 *)d_in, (float2 *)d_out, batch, inverse ? 1 : 0,
+                                      ctx->d_frags_x, (hipStream_t)stream));
     return GNSS_OK;
 }
 

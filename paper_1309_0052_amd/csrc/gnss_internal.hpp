@@ -18,6 +18,7 @@ constexpr int kVec = 1024;             // float4 per storage-order spectrum (204
 constexpr int kPolyLen = 1024;         // int2 per polyphase component (1023 + 1 zero)
 constexpr int kCorrWaves = 8;          // waves per FP32 correlation workgroup
 constexpr int kCorrWavesH = 4;         // waves per FP16 correlation workgroup
+constexpr int kCorrWavesX = 4;         // waves per exact-length correlation workgroup
 
 struct PrnList {
     int32_t v[kMaxList];
@@ -51,18 +52,29 @@ hipError_t launch_code_spectra(const uint8_t *d_codes, const float2 *d_tw, float
 hipError_t launch_tables_h(const float4 *d_cs, void *d_tw_h, void *d_cs_h, int cs_exp, hipStream_t s);
 constexpr size_t kTwHBytes = 2176 * 8;                      // hc2 twiddles
 constexpr size_t kCsHBytes = (size_t)(kMaxPrn + 1) * 8192;  // [38][2048] half2
+// Exact-length mode tables: FP16 weight fragments of the 31- and 33-point
+// passes, and the code spectra (FP64 staging, then FP16 fragments)
+constexpr size_t kPfaVecBytes = 264 * 16;  // one stored 1023-point spectrum
+constexpr size_t kFragXBytes = 49 * 64 * 16;
+constexpr size_t kCsXBytes = (size_t)(kMaxPrn + 1) * kPfaVecBytes;
+constexpr size_t kCsXStageBytes = (size_t)(kMaxPrn + 1) * 31 * 33 * 16;
+hipError_t launch_tables_x_frags(void *d_frags, hipStream_t s);
+hipError_t launch_code_spectra_x(const uint8_t *d_codes, double2 *d_stage, hipStream_t s);
+hipError_t launch_code_spectra_x_pack(const double2 *d_stage, void *d_cs_x, int cs_exp, hipStream_t s);
 
 // Bytes of the block spectra of n_vec polyphase vectors: FP32 float4
 // storage order; FP16 packed half2 (re, im), followed by one int exponent per
 // vector.
 inline size_t g_spectra_bytes(long long n_vec, int precision)
 {
-    return precision == GNSS_FP16 ? (size_t)n_vec * 8192 : (size_t)n_vec * kVec * 16;
+    return precision == GNSS_FP16 ? (size_t)n_vec * 8192
+           : precision == GNSS_FP16_PFA ? (size_t)n_vec * kPfaVecBytes
+                                        : (size_t)n_vec * kVec * 16;
 }
 inline size_t g_bytes(long long n_vec, int precision)
 {
-    return precision == GNSS_FP16 ? g_spectra_bytes(n_vec, precision) + (((size_t)n_vec * 4 + 255) & ~(size_t)255)
-                                  : g_spectra_bytes(n_vec, precision);
+    return precision == GNSS_FP32 ? g_spectra_bytes(n_vec, precision)
+                                  : g_spectra_bytes(n_vec, precision) + (((size_t)n_vec * 4 + 255) & ~(size_t)255);
 }
 
 // ---------------------------------------------------------------------------
@@ -118,6 +130,8 @@ struct Tables {
     const float4 *cs;
     const void *tw_h;  // FP16 path only
     const void *cs_h;
+    const void *frags_x;  // exact-length path only
+    const void *cs_x;
     int cs_exp;
 };
 
@@ -158,5 +172,8 @@ hipError_t launch_track(const TrackDesc *d_reqs, const long long *d_pre, int n_r
 // test entry: natural-order batched 2048-point transforms
 hipError_t launch_fft_test(const float2 *d_in, float2 *d_out, int batch, int inverse,
                            const float2 *d_tw, hipStream_t s);
+// test entry: natural-order batched 1023-point transforms (exact-length mode)
+hipError_t launch_dft1023_test(const float2 *d_in, float2 *d_out, int batch, int inverse, const void *d_frags,
+                               hipStream_t s);
 
 }  // namespace gnss

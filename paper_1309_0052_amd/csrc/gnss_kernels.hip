@@ -34,6 +34,7 @@
 // early / prompt / late correlators (Fig. 3).
 #include "fft2048.hpp"
 #include "gnss_internal.hpp"
+#include "pfa1023.hpp"
 
 #include <math.h>
 
@@ -544,12 +545,36 @@ __global__ __launch_bounds__(256) void k_fft_poly(const int2 *F, const float2 *t
 // ===========================================================================
 constexpr int kStagePad = kCorrWaves + 1;
 
-// Grid write of a correlation work item.  P = |IFFT|^2 * scale (2^-22 for the
+// Grid write of a correlation work item.  Lag tau = spc*q + s interleaves the
+// waves' phases, so the sums are staged in LDS ([1024 q][W + 1] floats per
+// PRN: both the per-wave writes and the per-row reads are free of bank
+// conflicts) and written as contiguous runs of consecutive tau.
+// write_rows writes one PRN's staged sums (column w = wave w's (Doppler,
+// phase) item; consecutive items of a bin are consecutive lags).
+template <int W>
+__device__ __forceinline__ void write_rows(const float *st, const ReqDesc &d, int pi, int chunk, int tid)
+{
+    constexpr int kPad = W + 1;
+    const int spc = d.spc;
+    const int first = chunk * W;
+    const int n_items_here = min(W, d.n_items - first);
+    int wa = 0;
+    while (wa < n_items_here) {
+        const int ka = (first + wa) / spc, sa = (first + wa) - ka * spc;
+        const int ns = min(spc - sa, n_items_here - wa);  // consecutive phases of bin ka
+        const int cnt = kCodeLen * ns;
+        GNSS_GLOBAL float *row = gmem(d.grid) + ((long long)pi * d.n_dopp + ka) * d.N + sa;
+        for (int idx = tid; idx < cnt; idx += 64 * W) {
+            const int q = idx / ns, j = idx - q * ns;
+            row[(long long)spc * q + j] = st[q * kPad + wa + j];
+        }
+        wa += ns;
+    }
+}
+
+// Stages and writes a tile's sums, P = |IFFT|^2 * scale (2^-22 for the
 // unnormalised 2048-point IFFT and 2^-24 for the LUT scale, times the FP16
-// path's code-spectrum scaling).  Lag tau = spc*q + s interleaves the waves'
-// phases, so the sums are staged in LDS ([PT][1024 q][W + 1] floats: both the
-// per-wave writes and the per-row reads are free of bank conflicts) and
-// written as contiguous runs of consecutive tau.
+// path's code-spectrum scaling).
 template <int PT, int W>
 __device__ __forceinline__ void store_tile(const float (&acc)[PT][16], float *s_stage, const ReqDesc &d,
                                            int ptile, int chunk, int w, int l, int tid, float scale)
@@ -566,25 +591,10 @@ __device__ __forceinline__ void store_tile(const float (&acc)[PT][16], float *s_
                 s_stage[(p * 1024 + q) * kPad + w] = acc[p][4 * u + k2b] * scale;
             }
     __syncthreads();
-    const int spc = d.spc;
-    const int first = chunk * W;
-    const int n_items_here = min(W, d.n_items - first);
-    int wa = 0;
-    while (wa < n_items_here) {
-        const int ka = (first + wa) / spc, sa = (first + wa) - ka * spc;
-        const int ns = min(spc - sa, n_items_here - wa);  // consecutive phases of bin ka
-        const int cnt = kCodeLen * ns;
-        for (int p = 0; p < PT; ++p) {
-            const int pi = ptile * PT + p;
-            if (pi >= d.n_prn) break;
-            GNSS_GLOBAL float *row = gmem(d.grid) + ((long long)pi * d.n_dopp + ka) * d.N + sa;
-            const float *st = s_stage + p * 1024 * kPad + wa;
-            for (int idx = tid; idx < cnt; idx += 64 * W) {
-                const int q = idx / ns, j = idx - q * ns;
-                row[(long long)spc * q + j] = st[q * kPad + j];
-            }
-        }
-        wa += ns;
+    for (int p = 0; p < PT; ++p) {
+        const int pi = ptile * PT + p;
+        if (pi >= d.n_prn) break;
+        write_rows<W>(s_stage + p * 1024 * kPad, d, pi, chunk, tid);
     }
 }
 
@@ -958,6 +968,345 @@ __global__ __launch_bounds__(64 * kCorrWavesH) __attribute__((amdgpu_waves_per_e
 }
 
 // ===========================================================================
+// Exact-length mode (GNSS_FP16_PFA): the length-1023 correlations of the
+// polyphase form with 1023-point transforms (Good-Thomas 31 x 33, no zero
+// padding, pfa1023.hpp) whose two passes are FP16 x FP16 -> FP32 products on
+// the matrix cores.  Scaling as in the FP16 mode: each polyphase vector is
+// scaled by 2^-e so that its l1 norm is <= 32, and the code spectra by
+// 2^-ecs so that max |C| <= 1.  Every pass output is bounded by the l1 norm
+// of its input: the forward transform's values by 32, the spectrum product's
+// by 32, the inverse 31-pass by 31 * 32 (rounded to FP16 for the second
+// pass) and the 33-pass output (FP32) by 33 * 31 * 32.  |.|^2 is formed in
+// FP32, times 2^(2e), summed over blocks; the grid gets 2^(2 ecs - 24) / 1023^2.
+// ===========================================================================
+
+// Real-form weight of an L-point DFT (L = 31 or 33): input (i_in, part p_in)
+// to output (i_out, part p_out), parts 0 = re, 1 = im; zero outside [0, L).
+// The complex weight is e^(-+ 2 pi i i_in i_out / L) (forward: minus).
+__device__ double pfa_weight(int L, bool inv, int i_in, int p_in, int i_out, int p_out)
+{
+    if (i_in < 0 || i_out < 0 || i_in >= L || i_out >= L) return 0.0;
+    const int e = (i_in * i_out) % L;
+    double sn, cs;
+    sincospi(2.0 * (double)e / (double)L, &sn, &cs);
+    const double sg = inv ? 1.0 : -1.0;  // weight = cs + i sg sn
+    // (xr + i xi)(cs + i sg sn) = (xr cs - xi sg sn) + i (xr sg sn + xi cs)
+    if (p_out == 0) return p_in == 0 ? cs : -sg * sn;
+    return p_in == 0 ? sg * sn : cs;
+}
+
+// two doubles to FP16 (one rounding, to nearest even)
+__device__ __forceinline__ uint32_t pack2d(double x, double y)
+{
+    pfa::h2v v = {(_Float16)x, (_Float16)y};
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+// Output column of an x32 weight fragment: (index, part); index -1 = unused.
+__device__ __forceinline__ void pfa_column(int L, bool inv, int tile, int c, int &i_out, int &p_out)
+{
+    if (L == pfa::kN1) {
+        i_out = 16 * (tile & 1) + c;
+        p_out = tile >> 1;
+    } else if (tile < 4 || !inv) {
+        i_out = 16 * (tile >> 1) + c;
+        p_out = tile & 1;
+    } else {  // inverse tile 4: column 32, re in lane c = 0, im in lane c = 1
+        i_out = c < 2 ? 32 : -1;
+        p_out = c & 1;
+    }
+}
+
+// B fragments of the four passes (forward / inverse, 31 / 33), FP16.  K
+// slot 8 g + j of step `step` is input index 16 step + 4 g + (j & 3), part
+// j >> 2.
+__global__ void k_pfa_frags(pfa::u4 *fr)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= pfa::kFrags * 64) return;
+    const int f = i >> 6, l = i & 63, g = l >> 4, c = l & 15;
+    int L, step, tile;
+    bool inv;
+    if (f < pfa::kFragInv33) {
+        L = pfa::kN1, inv = true, step = f / 4, tile = f % 4;
+    } else if (f < pfa::kFragFwd31) {
+        L = pfa::kN2, inv = true, step = (f - pfa::kFragInv33) / 5, tile = (f - pfa::kFragInv33) % 5;
+    } else if (f < pfa::kFragFwd33) {
+        L = pfa::kN1, inv = false, step = (f - pfa::kFragFwd31) / 4, tile = (f - pfa::kFragFwd31) % 4;
+    } else {
+        L = pfa::kN2, inv = false, step = (f - pfa::kFragFwd33) / 6, tile = (f - pfa::kFragFwd33) % 6;
+    }
+    int i_out, p_out;
+    pfa_column(L, inv, tile, c, i_out, p_out);
+    double wv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) wv[j] = pfa_weight(L, inv, 16 * step + 4 * g + (j & 3), j >> 2, i_out, p_out);
+    fr[i] = pfa::u4{pack2d(wv[0], wv[1]), pack2d(wv[2], wv[3]), pack2d(wv[4], wv[5]), pack2d(wv[6], wv[7])};
+}
+
+// Exact 1023-point spectra of the +-1 codes in FP64, [prn][a][b] at
+// k = k(a, b) (PRN 0: zero).  Grid (31, 38), one thread per b.
+__global__ __launch_bounds__(64) void k_code_spectra_x(const uint8_t *codes, double2 *out)
+{
+    __shared__ double2 s_w[kCodeLen];  // e^(-2 pi i j / 1023)
+    for (int j = threadIdx.x; j < kCodeLen; j += 64) {
+        double sn, cs;
+        sincospi(2.0 * (double)j / (double)kCodeLen, &sn, &cs);
+        s_w[j] = make_double2(cs, -sn);
+    }
+    __syncthreads();
+    const int a = blockIdx.x, prn = blockIdx.y, b = threadIdx.x;
+    if (b >= pfa::kN2) return;
+    const int k = pfa::freq_index(a, b);
+    double re = 0.0, im = 0.0;
+    if (prn != 0) {
+        const uint8_t *code = codes + prn * kCodeLen;
+        int idx = 0;
+        for (int m = 0; m < kCodeLen; ++m) {
+            const double chip = code[m] ? -1.0 : 1.0;
+            re += chip * s_w[idx].x;
+            im += chip * s_w[idx].y;
+            idx += k;
+            if (idx >= kCodeLen) idx -= kCodeLen;
+        }
+    }
+    out[((long long)prn * pfa::kN1 + a) * pfa::kN2 + b] = make_double2(re, im);
+}
+
+// Coordinates of stored unit `unit` of a spectrum (see pfa::kUnits).
+__device__ __forceinline__ void pfa_unit(int unit, int &t, int &s, int &g, int &c)
+{
+    if (unit < pfa::kTailUnit) {
+        const int ff = unit >> 6, l = unit & 63;
+        t = ff >> 1, s = ff & 1, g = l >> 4, c = l & 15;
+    } else {
+        t = 2, s = (unit - pfa::kTailUnit) >> 2, g = (unit - pfa::kTailUnit) & 3, c = 0;
+    }
+}
+
+// FP16 code spectra C * 2^-ecs in the stored fragment layout.
+__global__ void k_code_spectra_x_pack(const double2 *cs, pfa::u4 *out, int ecs)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (kMaxPrn + 1) * pfa::kUnits) return;
+    const int prn = i / pfa::kUnits, unit = i % pfa::kUnits;
+    int t, s, g, c;
+    pfa_unit(unit, t, s, g, c);
+    double re[4], im[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int a = 16 * s + 4 * g + j, b = 16 * t + c;
+        double2 v = make_double2(0.0, 0.0);
+        if (a < pfa::kN1 && b < pfa::kN2) v = cs[((long long)prn * pfa::kN1 + a) * pfa::kN2 + b];
+        re[j] = ldexp(v.x, -ecs);
+        im[j] = ldexp(v.y, -ecs);
+    }
+    out[i] = pfa::u4{pack2d(re[0], re[1]), pack2d(re[2], re[3]), pack2d(im[0], im[1]), pack2d(im[2], im[3])};
+}
+
+hipError_t launch_tables_x_frags(void *d_frags, hipStream_t s)
+{
+    constexpr int n = pfa::kFrags * 64;
+    hipLaunchKernelGGL(k_pfa_frags, dim3((n + 255) / 256), dim3(256), 0, s, (pfa::u4 *)d_frags);
+    return hipGetLastError();
+}
+
+hipError_t launch_code_spectra_x(const uint8_t *d_codes, double2 *d_tmp, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_code_spectra_x, dim3(pfa::kN1, kMaxPrn + 1), dim3(64), 0, s, d_codes, d_tmp);
+    return hipGetLastError();
+}
+
+hipError_t launch_code_spectra_x_pack(const double2 *d_tmp, void *d_cs_x, int cs_exp, hipStream_t s)
+{
+    constexpr int n = (kMaxPrn + 1) * pfa::kUnits;
+    hipLaunchKernelGGL(k_code_spectra_x_pack, dim3((n + 255) / 256), dim3(256), 0, s, d_tmp, (pfa::u4 *)d_cs_x,
+                       cs_exp);
+    return hipGetLastError();
+}
+
+// Forward transforms, one polyphase vector per wave: the vector in LDS, its
+// exponent from the exact l1 norm, the Good-Thomas gather into fragments,
+// two passes, and the spectrum stored as fragments with its exponent.
+__global__ __launch_bounds__(256) void k_fft_x(const int2 *F, const pfa::u4 *__restrict__ fr, pfa::u4 *Gx, int *E,
+                                               const BatchHdr *H)
+{
+    __shared__ int2 s_x[4][kPolyLen];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+    pfa::FwdB B;
+    pfa::load_fwd(B, fr, l);
+    const long long n_vec = H->total[kStVec];
+    int2 *xs = s_x[w];
+    for (long long vec = (long long)blockIdx.x * 4 + w; vec < n_vec; vec += (long long)gridDim.x * 4) {
+        const int2 *src = F + vec * kPolyLen;
+        float nrm = 0.f;
+        lds_fence();  // the previous vector's gathers are complete
+#pragma unroll
+        for (int i = 0; i < kPolyLen / 64; ++i) {
+            const int2 v = src[l + 64 * i];
+            xs[l + 64 * i] = v;
+            nrm += fabsf((float)v.x) + fabsf((float)v.y);
+        }
+        const int e = l1_exponent(wave_sum(nrm));
+        const float f = ldexpf(1.f, -e);
+        lds_fence();
+        pfa::u4 a1[3][2];
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                float re[4], im[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int n1 = 16 * s + 4 * g + j, n2 = 16 * t + c;
+                    int2 v = make_int2(0, 0);
+                    if (n1 < pfa::kN1 && n2 < pfa::kN2) v = xs[pfa::time_index(n1, n2)];
+                    re[j] = (float)v.x * f;
+                    im[j] = (float)v.y * f;
+                }
+                a1[t][s] = pfa::u4{pfa::pack2(re[0], re[1]), pfa::pack2(re[2], re[3]), pfa::pack2(im[0], im[1]),
+                                   pfa::pack2(im[2], im[3])};
+            }
+        pfa::f4 o[2][6];
+        pfa::forward(a1, B, o);
+        pfa::u4 *dst = Gx + vec * pfa::kUnits;
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const pfa::f4 re = o[s][2 * t], im = o[s][2 * t + 1];
+                dst[(2 * t + s) * 64 + l] = pfa::u4{pfa::pack2(re.x, re.y), pfa::pack2(re.z, re.w),
+                                                    pfa::pack2(im.x, im.y), pfa::pack2(im.z, im.w)};
+            }
+        if (c == 0) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const pfa::f4 re = o[s][4], im = o[s][5];
+                dst[pfa::kTailUnit + 4 * s + g] = pfa::u4{pfa::pack2(re.x, re.y), pfa::pack2(re.z, re.w),
+                                                          pfa::pack2(im.x, im.y), pfa::pack2(im.z, im.w)};
+            }
+        }
+        if (l == 0) E[vec] = e;
+    }
+}
+
+// G * conj(C) for the four complex values of a fragment (packed FP16)
+__device__ __forceinline__ pfa::u4 cmul_conj_frag(pfa::u4 g, pfa::u4 c)
+{
+    const __half2 gr0 = bits_h2(g.x), gr1 = bits_h2(g.y), gi0 = bits_h2(g.z), gi1 = bits_h2(g.w);
+    const __half2 cr0 = bits_h2(c.x), cr1 = bits_h2(c.y), ci0 = bits_h2(c.z), ci1 = bits_h2(c.w);
+    const __half2 yr0 = __hfma2(gr0, cr0, __hmul2(gi0, ci0)), yr1 = __hfma2(gr1, cr1, __hmul2(gi1, ci1));
+    const __half2 yi0 = __hfma2(gi0, cr0, __hneg2(__hmul2(gr0, ci0)));
+    const __half2 yi1 = __hfma2(gi1, cr1, __hneg2(__hmul2(gr1, ci1)));
+    return pfa::u4{h2_bits(yr0), h2_bits(yr1), h2_bits(yi0), h2_bits(yi1)};
+}
+
+// Correlation, exact-length mode.  Work item = (request, PRN tile, chunk of
+// kCorrWavesX (Doppler, phase) items); one wave per item; the tile's PRNs in
+// turn, each over all blocks with its sums in registers, then written.
+__global__ __launch_bounds__(64 * kCorrWavesX) void k_corr_x(const ReqDesc *__restrict__ R, BatchHdr *H,
+                                                             const long long *pre, const pfa::u4 *Gx,
+                                                             const int *E, const pfa::u4 *__restrict__ CSx,
+                                                             const pfa::u4 *__restrict__ fr, float out_scale)
+{
+    constexpr int W = kCorrWavesX;
+    constexpr int kPad = W + 1;
+    __shared__ pfa::u4 s_c[pfa::kUnits];
+    __shared__ float s_stage[1024 * kPad];
+    __shared__ long long s_item;
+    const int tid = threadIdx.x;
+    const int w = tid >> 6, l = tid & 63, g = l >> 4, c = l & 15;
+    pfa::InvB B;
+    pfa::load_inv(B, fr, l);
+    const int n_req = H->n_req;
+    const int pt = H->corr_pt;
+    const long long total = H->total[kStCorr];
+    const long long *pst = pre + (long long)kStCorr * (n_req + 1);
+    const pfa::u4 zero4 = {0u, 0u, 0u, 0u};
+    bool first = true;
+    for (;;) {
+        const long long it = next_item(H, kStCorr, total, &s_item, first);
+        if (it < 0) break;
+        const int r = find_req(pst, n_req, it);
+        const ReqDesc &d = R[r];
+        const long long local = it - pst[r];
+        const int ptile = (int)(local % d.n_ptiles), chunk = (int)(local / d.n_ptiles);
+        const int item = chunk * W + w;
+        const bool active = item < d.n_items;
+        const int spc = d.spc;
+        const int k = item / spc, s = item - k * spc;
+        const long long v0 = d.vec_off + (long long)k * d.Nnc * spc + s;
+        for (int pp = 0; pp < pt; ++pp) {
+            const int pi = ptile * pt + pp;
+            if (pi >= d.n_prn) break;
+            __syncthreads();  // the previous PRN's reads of s_c and s_stage are done
+            for (int i = tid; i < pfa::kUnits; i += 64 * W) s_c[i] = CSx[(long long)d.prns[pi] * pfa::kUnits + i];
+            __syncthreads();
+            float acc[2][3][4];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int h = 0; h < 3; ++h)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[u][h][q] = 0.f;
+            if (active) {
+                pfa::u4 cf[3][2];
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int ss = 0; ss < 2; ++ss) cf[t][ss] = s_c[(2 * t + ss) * 64 + l];
+#pragma unroll
+                for (int ss = 0; ss < 2; ++ss) cf[2][ss] = c == 0 ? s_c[pfa::kTailUnit + 4 * ss + g] : zero4;
+                for (int b = 0; b < d.Nnc; ++b) {
+                    const long long vec = v0 + (long long)b * spc;
+                    const pfa::u4 *gq = Gx + vec * pfa::kUnits;
+                    const float sc = ldexpf(1.f, 2 * E[vec]);
+                    pfa::u4 a1[3][2];
+#pragma unroll
+                    for (int t = 0; t < 2; ++t)
+#pragma unroll
+                        for (int ss = 0; ss < 2; ++ss) a1[t][ss] = cmul_conj_frag(gq[(2 * t + ss) * 64 + l], cf[t][ss]);
+#pragma unroll
+                    for (int ss = 0; ss < 2; ++ss)
+                        a1[2][ss] = c == 0 ? cmul_conj_frag(gq[pfa::kTailUnit + 4 * ss + g], cf[2][ss]) : zero4;
+                    pfa::f4 o[2][5];
+                    pfa::inverse(a1, B, o);
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+#pragma unroll
+                        for (int h = 0; h < 2; ++h)
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                const float yr = o[u][2 * h][q], yi = o[u][2 * h + 1][q];
+                                acc[u][h][q] = fmaf(fmaf(yr, yr, yi * yi), sc, acc[u][h][q]);
+                            }
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            // column 32: re in lane c = 0, im in lane c = 1
+                            const float t2 = o[u][4][q] * o[u][4][q];
+                            const float t1 = __shfl_down(t2, 1);
+                            acc[u][2][q] = fmaf(t2 + t1, sc, acc[u][2][q]);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int h = 0; h < 3; ++h)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int n1 = 16 * u + 4 * g + q, n2 = 16 * h + c;
+                            if (n1 < pfa::kN1 && n2 < pfa::kN2)
+                                s_stage[pfa::time_index(n1, n2) * kPad + w] = acc[u][h][q] * out_scale;
+                        }
+            }
+            __syncthreads();
+            write_rows<W>(s_stage, d, pi, chunk, tid);
+        }
+    }
+}
+
+// ===========================================================================
 // detection: column max over Doppler, argmax, second peak, mean; refinement
 // ===========================================================================
 // Work item = (request, PRN, block of 256 lags).  Q[tau] = max_k P (lowest k
@@ -1162,10 +1511,10 @@ hipError_t launch_batch(const Launch &L, const Tables &T, int2 *d_F, void *d_G, 
     const uint32_t *d_lut = T.lut;
     const float2 *d_tw = T.tw;
     const float4 *d_cs = T.cs;
-    const bool h = L.precision == GNSS_FP16;
-    // FP16: packed spectra, then the per-vector exponents
+    const bool h = L.precision == GNSS_FP16, x = L.precision == GNSS_FP16_PFA;
+    // FP16 modes: packed spectra, then the per-vector exponents
     uint4 *d_Gh = (uint4 *)d_G;
-    int *d_E = (int *)((char *)d_G + g_spectra_bytes(L.total[kStVec], GNSS_FP16));
+    int *d_E = (int *)((char *)d_G + g_spectra_bytes(L.total[kStVec], L.precision));
     hipError_t e;
     const bool pers = L.persistent != 0;
     auto mark = [&](int i) -> hipError_t { return marks ? hipEventRecord(marks[i], s) : hipSuccess; };
@@ -1180,7 +1529,13 @@ hipError_t launch_batch(const Launch &L, const Tables &T, int2 *d_F, void *d_G, 
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if ((e = mark(1)) != hipSuccess) return e;
-    if (L.total[kStVec] > 0 && !h) {
+    if (L.total[kStVec] > 0 && x) {
+        static int cap = 0;
+        if (!cap) cap = occupancy(k_fft_x, 256, n_cu);
+        hipLaunchKernelGGL(k_fft_x, dim3(grid_for((L.total[kStVec] + 3) / 4, cap, false)), dim3(256), 0, s, d_F,
+                           (const pfa::u4 *)T.frags_x, (pfa::u4 *)d_G, d_E, L.hdr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else if (L.total[kStVec] > 0 && !h) {
         static int cap = 0;
         if (!cap) cap = occupancy(k_fft_poly, 256, n_cu);
         hipLaunchKernelGGL(k_fft_poly, dim3(grid_for((L.total[kStVec] + 3) / 4, cap, false)), dim3(256), 0,
@@ -1194,7 +1549,15 @@ hipError_t launch_batch(const Launch &L, const Tables &T, int2 *d_F, void *d_G, 
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if ((e = mark(2)) != hipSuccess) return e;
-    if (L.total[kStCorr] > 0 && h) {
+    if (L.total[kStCorr] > 0 && x) {
+        const float osc = ldexpf(1.f, 2 * T.cs_exp - 24) / (float)(kCodeLen * kCodeLen);
+        static int cap = 0;
+        if (!cap) cap = occupancy(k_corr_x, 64 * kCorrWavesX, n_cu);
+        hipLaunchKernelGGL(k_corr_x, dim3(grid_for(L.total[kStCorr], cap, pers)), dim3(64 * kCorrWavesX), 0, s,
+                           L.reqs, L.hdr, L.pre, (const pfa::u4 *)d_G, d_E, (const pfa::u4 *)T.cs_x,
+                           (const pfa::u4 *)T.frags_x, osc);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else if (L.total[kStCorr] > 0 && h) {
         const float osc = ldexpf(1.f, 2 * T.cs_exp - 46);
         if (L.corr_pt == 2) {
             static int cap = 0;
@@ -1451,6 +1814,83 @@ hipError_t launch_fft_test(const float2 *d_in, float2 *d_out, int batch, int inv
 {
     hipLaunchKernelGGL(k_fft_test, dim3((batch + 3) / 4), dim3(256), 0, s, d_in, d_out, batch,
                        inverse, d_tw);
+    return hipGetLastError();
+}
+
+
+// ===========================================================================
+// test entry: batched natural-order 1023-point DFT / unnormalised inverse in
+// the exact-length mode's arithmetic (per-vector exponent from the l1 norm,
+// FP16 operands, FP32 accumulation); one wave per vector
+// ===========================================================================
+__global__ __launch_bounds__(256) void k_dft1023_test(const float2 *in, float2 *out, int batch, int inverse,
+                                                      const pfa::u4 *__restrict__ fr)
+{
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+    const long long vec = (long long)blockIdx.x * 4 + w;
+    if (vec >= batch) return;
+    const float2 *src = in + vec * kCodeLen;
+    float *dst = (float *)(out + vec * kCodeLen);
+    float nrm = 0.f;
+    for (int i = l; i < kCodeLen; i += 64) nrm += fabsf(src[i].x) + fabsf(src[i].y);
+    const int e = l1_exponent(wave_sum(nrm));
+    const float f = ldexpf(1.f, -e), fo = ldexpf(1.f, e);
+    pfa::u4 a1[3][2];
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            float re[4], im[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int i1 = 16 * s + 4 * g + j, i2 = 16 * t + c;
+                float2 v = make_float2(0.f, 0.f);
+                if (i1 < pfa::kN1 && i2 < pfa::kN2)
+                    v = src[inverse ? pfa::freq_index(i1, i2) : pfa::time_index(i1, i2)];
+                re[j] = v.x * f;
+                im[j] = v.y * f;
+            }
+            a1[t][s] = pfa::u4{pfa::pack2(re[0], re[1]), pfa::pack2(re[2], re[3]), pfa::pack2(im[0], im[1]),
+                               pfa::pack2(im[2], im[3])};
+        }
+    if (!inverse) {
+        pfa::FwdB B;
+        pfa::load_fwd(B, fr, l);
+        pfa::f4 o[2][6];
+        pfa::forward(a1, B, o);
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 6; ++v)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int a = 16 * u + 4 * g + r, b = 16 * (v >> 1) + c;
+                    if (a < pfa::kN1 && b < pfa::kN2) dst[2 * pfa::freq_index(a, b) + (v & 1)] = o[u][v][r] * fo;
+                }
+    } else {
+        pfa::InvB B;
+        pfa::load_inv(B, fr, l);
+        pfa::f4 o[2][5];
+        pfa::inverse(a1, B, o);
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 5; ++v)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int n1 = 16 * u + 4 * g + r;
+                    const int n2 = v < 4 ? 16 * (v >> 1) + c : (c < 2 ? 32 : pfa::kN2);
+                    const int part = v < 4 ? (v & 1) : c;
+                    if (n1 < pfa::kN1 && n2 < pfa::kN2) dst[2 * pfa::time_index(n1, n2) + part] = o[u][v][r] * fo;
+                }
+    }
+}
+
+hipError_t launch_dft1023_test(const float2 *d_in, float2 *d_out, int batch, int inverse, const void *d_frags,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dft1023_test, dim3((batch + 3) / 4), dim3(256), 0, s, d_in, d_out, batch, inverse,
+                       (const pfa::u4 *)d_frags);
     return hipGetLastError();
 }
 

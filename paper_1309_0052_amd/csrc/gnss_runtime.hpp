@@ -84,6 +84,8 @@ struct gnss_ctx {
     float4 *d_cs = nullptr;     // [38][1024] code spectra, storage order
     void *d_tw_h = nullptr;     // FP16 contexts: packed twiddles
     void *d_cs_h = nullptr;     //   code spectra * 2^-cs_exp, packed storage order
+    void *d_frags_x = nullptr;  // exact-length contexts: weight fragments of the 31/33-point passes
+    void *d_cs_x = nullptr;     //   1023-point code spectra * 2^-cs_exp, fragment layout
     int cs_exp = 0;
     gnss_rt::Workspace ws;      // synchronous and device-buffer calls
     // autotuned (PRN tile, correlation schedule) per sample-rate signature

@@ -578,7 +578,8 @@ int gnss_autotune(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, const 
     if (g.rc) return g.rc;
     const std::string sig = rate_signature(plans.data(), n_req);
     const std::string key =
-        device_key(ctx->device) + (ctx->precision == GNSS_FP16 ? "/fp16/" : "/fp32/") + sig;
+        device_key(ctx->device) +
+        (ctx->precision == GNSS_FP16 ? "/fp16/" : ctx->precision == GNSS_FP16_PFA ? "/fp16pfa/" : "/fp32/") + sig;
     std::map<std::string, std::pair<int, int>> cache;
     if (cache_path) cache_read(cache_path, cache);
     auto hit = cache.find(key);

@@ -24,6 +24,16 @@ Hence the mixed tolerance |P16 - P64| <= TOL16 (P64 + mean P64) with TOL16 =
 2 * 6 * eta = 3.4e-2 (a factor 2 for the non-Gaussian tail).  Detections must
 equal the oracle's unless its decision is within TIE16 = TOL16 of a tie or of
 the threshold.  The measured errors are logged.
+
+The same tests run on the exact-length mode (GNSS_FP16_PFA: 1023-point
+Good-Thomas transforms, each pass an FP16 x FP16 -> FP32 matrix product).
+Its roundings to FP16 are the input, the forward 31-pass output, the stored
+spectrum, the code spectrum, the two operations of the spectrum product and
+the inverse 31-pass output, plus the FP16 weights of the four passes (each
+weight within u of the exact one, which perturbs a pass output by about u of
+its RMS); sums are FP32.  That is 11 sources of about u each:
+eta ~ sqrt(11) u ~ 3.3 u, and the same argument gives TOLX = 2 * 6 * eta =
+2.0e-2.
 """
 import time
 
@@ -40,13 +50,16 @@ torch = pytest.importorskip("torch")
 G = pytest.importorskip("paper_1309_0052_amd")
 
 TOL16 = 3.4e-2
-TIE16 = TOL16
+TOLX = 2.0e-2
+TOL = {G.GNSS_FP16: TOL16, G.GNSS_FP16_PFA: TOLX}
+NAME = {G.GNSS_FP16: "FP16", G.GNSS_FP16_PFA: "FP16 exact-length"}
 
 
-@pytest.fixture(scope="module")
-def ctx16():
+@pytest.fixture(scope="module", params=[G.GNSS_FP16, G.GNSS_FP16_PFA], ids=["fp16", "pfa"])
+def ctx16(request):
     assert torch.cuda.is_available(), "GPU tests need a GPU"
-    c = G.Context(0, precision=G.GNSS_FP16)
+    c = G.Context(0, precision=request.param)
+    c.prec = request.param
     yield c
     c.close()
 
@@ -70,12 +83,13 @@ def _run(ctx, snap, srch):
     return grid, d_pk.cpu().numpy().view(G.PEAK_DTYPE).copy()
 
 
-def _check(grid, pk, P, srch, spc, planted):
+def _check(grid, pk, P, srch, spc, planted, prec):
+    tol = TOL[prec]
     worst = grid_error(grid, P)
     assert np.all(np.isfinite(grid))
-    assert worst <= TOL16, "FP16 mixed error %.3e > %.1e" % (worst, TOL16)
+    assert worst <= tol, "%s mixed error %.3e > %.1e" % (NAME[prec], worst, tol)
     ref = O.peaks(P, srch.prns, spc, 2.5, srch.lo, srch.step)
-    exempt = compare_detections(pk, ref, P, tie_rel=TIE16, value_rel=TOL16)
+    exempt = compare_detections(pk, ref, P, tie_rel=tol, value_rel=tol)
     peak_err = []
     for p in planted:
         i = srch.prns.index(p.prn)
@@ -84,8 +98,8 @@ def _check(grid, pk, P, srch, spc, planted):
         peak_err.append(abs(float(grid[i, r.doppler_bin, r.code_phase]) - r.peak) / r.peak)
     agree = sum(int(pk[i]["detected"]) == int(r.detected) and int(pk[i]["code_phase"]) == r.code_phase
                 and int(pk[i]["doppler_bin"]) == r.doppler_bin for i, r in enumerate(ref))
-    log("  FP16 vs FP64: max mixed error %.3e, planted peak-cell error max %.2e, detections "
-        "identical %d / %d, near-tie exemptions %d" % (worst, max(peak_err) if peak_err else 0.0,
+    log("  %s vs FP64: max mixed error %.3e, planted peak-cell error max %.2e, detections "
+        "identical %d / %d, near-tie exemptions %d" % (NAME[prec], worst, max(peak_err) if peak_err else 0.0,
                                                         agree, len(ref), exempt))
     return worst
 
@@ -121,7 +135,7 @@ def test_fp16_search_matches_direct_oracle(ctx16, case):
     log("fp16 search %s: fs=%d prns=%s bins=%d Tc=%d Nnc=%d" % (name, fs, prns, nd, Tc, Nnc))
     grid, pk = _run(ctx16, snap, srch)
     P = O.grid_direct(snap.samples, fmt, fs, f_if, prns, lo, step, nd, Tc, Nnc)
-    _check(grid, pk, P, srch, fs // 1023000, snap.planted)
+    _check(grid, pk, P, srch, fs // 1023000, snap.planted, ctx16.prec)
 
 
 def test_fp16_noiseless_closed_form(ctx16):
@@ -138,9 +152,9 @@ def test_fp16_noiseless_closed_form(ctx16):
     assert pk[0]["code_phase"] == d and pk[0]["detected"]
     rel = abs(grid[0, 0, d] / (Nnc * float(Tc * N) ** 2) - 1.0)
     log("  noiseless peak relative error %.2e" % rel)
-    assert rel < TOL16
+    assert rel < TOL[ctx16.prec]
     P = O.grid_direct(x, O.CPLX_I8, fs, 0.0, [prn, 5], 0.0, 1.0, 1, Tc, Nnc)
-    assert grid_error(grid, P) <= TOL16
+    assert grid_error(grid, P) <= TOL[ctx16.prec]
 
 
 def test_fp16_strong_workload(ctx16, strong_case):
@@ -149,7 +163,7 @@ def test_fp16_strong_workload(ctx16, strong_case):
     snap, srch, nd, P = strong_case
     log("fp16 strong workload: real 2-bit 4.092 MHz, 32 PRN x 21 bins x 10 ms")
     grid, pk = _run(ctx16, snap, srch)
-    _check(grid, pk, P, srch, 4, snap.planted)
+    _check(grid, pk, P, srch, 4, snap.planted, ctx16.prec)
     # deterministic
     grid2, pk2 = _run(ctx16, snap, srch)
     assert np.array_equal(grid, grid2) and np.array_equal(pk, pk2)
@@ -161,7 +175,8 @@ def test_fp16_strong_workload(ctx16, strong_case):
             for _ in range(5):
                 _run(c, snap, srch)
             times[name] = (time.perf_counter() - t0) / 5 * 1e3
-    log("  wall per search incl. copies: fp32 %.3f ms, fp16 %.3f ms" % (times["fp32"], times["fp16"]))
+    log("  wall per search incl. copies: fp32 %.3f ms, %s %.3f ms" % (times["fp32"], NAME[ctx16.prec],
+                                                                       times["fp16"]))
 
 
 @pytest.mark.timeout(600)
@@ -169,7 +184,7 @@ def test_fp16_weak_workload_full_size(ctx16, weak_case):
     snap, srch, nd, P = weak_case
     log("fp16 weak workload: complex int8 16.368 MHz, 32 PRN x 121 bins x 25 x 4 ms")
     grid, pk = _run(ctx16, snap, srch)
-    _check(grid, pk, P, srch, 16, snap.planted)
+    _check(grid, pk, P, srch, 16, snap.planted, ctx16.prec)
 
 
 def test_fp16_batch_graph_serving_equal_alone(ctx16):
@@ -206,7 +221,7 @@ def test_fp16_batch_graph_serving_equal_alone(ctx16):
                 assert np.array_equal(g, alone[i][0].ravel()) and np.array_equal(p, alone[i][1]), (rep, i)
     finally:
         graph.close()
-    with G.Context(0, precision=G.GNSS_FP16) as sctx:
+    with G.Context(0, precision=ctx16.prec) as sctx:
         tickets = []
         for i, (snap, srch) in enumerate(items):
             nd = O.n_doppler(srch.lo, srch.hi, srch.step)
