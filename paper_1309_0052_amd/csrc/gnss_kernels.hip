@@ -1190,6 +1190,26 @@ __global__ __launch_bounds__(256) void k_fft_x(const int2 *F, const pfa::u4 *__r
     }
 }
 
+// LDS copy of one stored spectrum: the four full fragments (1 KB each) and
+// the 128-byte tail, staged as 32 dwords (lanes 32..63 repeat them).
+constexpr int kXBuf = pfa::kTailUnit + 16;  // u4 units per LDS spectrum buffer
+__device__ __forceinline__ void stage_spectrum(const pfa::u4 *src, pfa::u4 *dst, int l)
+{
+    typedef __attribute__((address_space(1))) const void gvoid;
+    typedef __attribute__((address_space(3))) void lvoid;
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+        __builtin_amdgcn_global_load_lds((gvoid *)(src + f * 64 + l), (lvoid *)(dst + f * 64), 16, 0, 0);
+    const uint32_t *tail = (const uint32_t *)(src + pfa::kTailUnit);
+    __builtin_amdgcn_global_load_lds((gvoid *)(tail + (l & 31)), (lvoid *)(dst + pfa::kTailUnit), 4, 0, 0);
+}
+
+// Value of lane 4 q + 1 in lane 4 q (DPP quad permutation [1, 1, 3, 3]).
+__device__ __forceinline__ float from_next_lane(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xF5, 0xF, 0xF, false));
+}
+
 // G * conj(C) for the four complex values of a fragment (packed FP16)
 __device__ __forceinline__ pfa::u4 cmul_conj_frag(pfa::u4 g, pfa::u4 c)
 {
@@ -1213,6 +1233,7 @@ __global__ __launch_bounds__(64 * kCorrWavesX) void k_corr_x(const ReqDesc *__re
     constexpr int kPad = W + 1;
     __shared__ pfa::u4 s_c[pfa::kUnits];
     __shared__ float s_stage[1024 * kPad];
+    __shared__ pfa::u4 s_g[W * 2 * kXBuf];  // two block spectra per wave
     __shared__ long long s_item;
     const int tid = threadIdx.x;
     const int w = tid >> 6, l = tid & 63, g = l >> 4, c = l & 15;
@@ -1250,27 +1271,22 @@ __global__ __launch_bounds__(64 * kCorrWavesX) void k_corr_x(const ReqDesc *__re
 #pragma unroll
                     for (int q = 0; q < 4; ++q) acc[u][h][q] = 0.f;
             if (active) {
-                pfa::u4 cf[3][2];
+                // Block b + 1's spectrum is copied from HBM into the wave's other
+                // LDS buffer (direct-to-LDS loads, no registers) while block b's
+                // transform runs.
+                pfa::u4 *bufs = s_g + w * 2 * kXBuf;
+                auto spectrum = [&](int b) { return Gx + (v0 + (long long)b * spc) * pfa::kUnits; };
+                auto product = [&](const pfa::u4 *cur, pfa::u4 (&a1)[3][2]) {
 #pragma unroll
-                for (int t = 0; t < 2; ++t)
+                    for (int t = 0; t < 3; ++t)
 #pragma unroll
-                    for (int ss = 0; ss < 2; ++ss) cf[t][ss] = s_c[(2 * t + ss) * 64 + l];
-#pragma unroll
-                for (int ss = 0; ss < 2; ++ss) cf[2][ss] = c == 0 ? s_c[pfa::kTailUnit + 4 * ss + g] : zero4;
-                for (int b = 0; b < d.Nnc; ++b) {
-                    const long long vec = v0 + (long long)b * spc;
-                    const pfa::u4 *gq = Gx + vec * pfa::kUnits;
-                    const float sc = ldexpf(1.f, 2 * E[vec]);
-                    pfa::u4 a1[3][2];
-#pragma unroll
-                    for (int t = 0; t < 2; ++t)
-#pragma unroll
-                        for (int ss = 0; ss < 2; ++ss) a1[t][ss] = cmul_conj_frag(gq[(2 * t + ss) * 64 + l], cf[t][ss]);
-#pragma unroll
-                    for (int ss = 0; ss < 2; ++ss)
-                        a1[2][ss] = c == 0 ? cmul_conj_frag(gq[pfa::kTailUnit + 4 * ss + g], cf[2][ss]) : zero4;
-                    pfa::f4 o[2][5];
-                    pfa::inverse(a1, B, o);
+                        for (int ss = 0; ss < 2; ++ss) {
+                            const int unit = t < 2 ? (2 * t + ss) * 64 + l : pfa::kTailUnit + 4 * ss + g;
+                            const bool has = t < 2 || c == 0;
+                            a1[t][ss] = has ? cmul_conj_frag(cur[unit], s_c[unit]) : zero4;
+                        }
+                };
+                auto power = [&](const pfa::f4 (&o)[2][5], float sc) {
 #pragma unroll
                     for (int u = 0; u < 2; ++u) {
 #pragma unroll
@@ -1284,10 +1300,30 @@ __global__ __launch_bounds__(64 * kCorrWavesX) void k_corr_x(const ReqDesc *__re
                         for (int q = 0; q < 4; ++q) {
                             // column 32: re in lane c = 0, im in lane c = 1
                             const float t2 = o[u][4][q] * o[u][4][q];
-                            const float t1 = __shfl_down(t2, 1);
-                            acc[u][2][q] = fmaf(t2 + t1, sc, acc[u][2][q]);
+                            acc[u][2][q] = fmaf(t2 + from_next_lane(t2), sc, acc[u][2][q]);
                         }
                     }
+                };
+                stage_spectrum(spectrum(0), bufs, l);
+                int e_next = E[v0];
+                for (int b = 0; b < d.Nnc; ++b) {
+                    const float sc = ldexpf(1.f, 2 * e_next);
+                    pfa::u4 a1[3][2];
+                    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // block b is in LDS
+                    product(bufs + (b & 1) * kXBuf, a1);
+                    if (b + 1 < d.Nnc) {
+                        // the other buffer was last read by block b - 1's product
+                        stage_spectrum(spectrum(b + 1), bufs + ((b + 1) & 1) * kXBuf, l);
+                        e_next = E[v0 + (long long)(b + 1) * spc];
+                    }
+                    // the transform's matrix-core phase at raised wave priority, so
+                    // that the other wave of the SIMD fills it with vector work
+                    // rather than both waves meeting in the same phase
+                    pfa::f4 o[2][5];
+                    __builtin_amdgcn_s_setprio(1);
+                    pfa::inverse(a1, B, o);
+                    __builtin_amdgcn_s_setprio(0);
+                    power(o, sc);
                 }
 #pragma unroll
                 for (int u = 0; u < 2; ++u)
