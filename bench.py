@@ -160,6 +160,9 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=PRECISIONS,
                     help="fp16: packed FP16 transforms, FP32 power and block sums; fp16pfa: exact-length "
                          "1023-point transforms on the matrix cores (FP16 operands, FP32 accumulation)")
+    ap.add_argument("--doppler-fd", action="store_true",
+                    help="with --precision fp16pfa: frequency-domain Doppler (one long DFT per block "
+                         "serves every bin; exact-exponential carrier)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -184,6 +187,8 @@ def main():
         ctx.set("corr_ptile", args.corr_ptile)
     if args.persistent >= 0:
         ctx.set("persistent", args.persistent)
+    if args.doppler_fd:
+        ctx.set("doppler_fd", 1)
     stream = torch.cuda.current_stream()
 
     def code_fn(prn):
@@ -285,7 +290,7 @@ def main():
         "config": {"workload": desc, "n_prn": n_prn, "n_doppler": nd, "code_phases": N,
                    "T_coh_ms": srch.T_coh, "N_noncoh": srch.N_noncoh,
                    "cells_per_snapshot": cells, "corr_ptile": pt, "persistent": sched,
-                   "precision": args.precision},
+                   "precision": args.precision, "doppler_fd": bool(args.doppler_fd)},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "min": float(lat.min()), "max": float(lat.max())},
         "wall_s": wall_s,
@@ -381,7 +386,7 @@ def run_batch(args, G, torch, ctx, code_fn):
                                "16.368} MHz, 8-32 PRNs, +-2-10 kHz windows, 1 ms coh; one hipGraph "
                                "launch per step" % len(items),
                    "snapshots": len(items), "cells_per_step": cells, "corr_ptile": pt,
-                   "persistent": sched, "precision": args.precision},
+                   "persistent": sched, "precision": args.precision, "doppler_fd": bool(args.doppler_fd)},
         "snapshots_per_s": len(items) / (ms_step / 1e3),
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "wall_s": wall_s, "generate_s": t_gen,
@@ -420,6 +425,8 @@ def run_serve(args, G, torch, ctx, code_fn):
     for rate in rates:
         sctx = G.Context(0, hbm_budget_bytes=int(args.budget_gb * (1 << 30)),
                          precision=precision_const(G, args.precision))
+        if args.doppler_fd:
+            sctx.set("doppler_fd", 1)
         n_total = args.serve_warmup + args.serve_n
         gaps = rng.exponential(1.0 / rate, n_total)
         sched = np.cumsum(gaps)

@@ -137,7 +137,17 @@ void gnss_ctx_destroy(gnss_ctx *ctx);
  * "code_doppler" (1: code-Doppler compensation of the non-coherent sum: the
  * code rate follows the carrier Doppler (f_L1 = 1540 chip rates), so block
  * b's correlation at bin f_k is taken at lag tau - llround(b T_coh N f_k /
- * 1575.42e6) (circular); 0, the default: plain sum), "max_slots" (requests per
+ * 1575.42e6) (circular); 0, the default: plain sum), "doppler_fd" (1, only on
+ * GNSS_FP16_PFA contexts: frequency-domain Doppler -- the carrier is removed
+ * once per block at f_if + doppler_lo by an exact exponential, one
+ * zero-padded DFT of length P*T_coh*N per block serves every Doppler bin by a
+ * shift of k*kappa bins, and the polyphase block spectra are synthesised from
+ * it; needs doppler_step*T_coh*P/1000 a whole number kappa for some P in
+ * {1, 2, 4} and P*T_coh*spc a power of two <= 256, else GNSS_ENOTSUP at
+ * search time; not with code_doppler.  The grid is then sum_b |R_b|^2 of the
+ * exactly wiped blocks, on the scale of the NCO path's 2^-24 |R_b|^2 of its
+ * 4096-scaled table; 0, the default: NCO and lookup table as in Fig. 2),
+ * "max_slots" (requests per
  * served batch, 1..4096).
  * Errors: GNSS_EINVAL. */
 int gnss_ctx_set(gnss_ctx *ctx, const char *key, double value);

@@ -167,6 +167,34 @@ def wipe_fold(samples, fmt, fs_hz, f_if, lo, step, n_dopp, T_coh, N_noncoh) -> n
     return out
 
 
+def raw_samples(samples: np.ndarray, fmt: int, n0: int, count: int) -> np.ndarray:
+    """Decoded samples x[n0 .. n0 + count) as complex128 (the mixing stage at
+    carrier step 0: LUT entry 0 is 4096 + 0j)."""
+    y = wipe(samples, fmt, 0, n0, count)
+    return (y[:, 0] + 1j * y[:, 1]) / 4096.0
+
+
+def fold_exact(samples, fmt, fs_hz, f_if, lo, step, n_dopp, T_coh, N_noncoh) -> np.ndarray:
+    """Folded coherent blocks with an exact carrier: y[n] = x[b L + n]
+    exp(-2 pi i (f_if + f_k) n / fs) for n < L = T_coh N (phase zero at the block
+    start, which leaves every |R_b|^2 unchanged), f[k][b][j] = sum_{t<Tc} y[j + t N].
+    complex128 [n_dopp][N_noncoh][N] -- the carrier of the frequency-domain
+    Doppler variant, which removes it by shifting a spectrum instead of by the
+    NCO's lookup table."""
+    N = samples_per_ms(fs_hz)
+    L = T_coh * N
+    n = np.arange(L, dtype=np.float64)
+    out = np.zeros((n_dopp, N_noncoh, N), np.complex128)
+    for b in range(N_noncoh):
+        x = raw_samples(samples, fmt, b * L, L)
+        for k in range(n_dopp):
+            ph = (f_if + bin_freq(lo, step, k)) * n / fs_hz  # cycles
+            ph -= np.floor(ph)
+            y = x * np.exp(-2j * np.pi * ph)
+            out[k, b] = y.reshape(T_coh, N).sum(axis=0)
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Correlation grid
 # ---------------------------------------------------------------------------
@@ -209,24 +237,32 @@ def code_shift(b: int, T_coh: int, N: int, f_bin: float) -> int:
 
 
 def grid_fft(samples, fmt, fs_hz, f_if, prns, lo, step, n_dopp, T_coh, N_noncoh,
-             folded: np.ndarray | None = None, code_doppler: bool = False) -> np.ndarray:
+             folded: np.ndarray | None = None, code_doppler: bool = False,
+             carrier: str = "nco") -> np.ndarray:
     """P[p][k][tau] through the correlation theorem in FP64:
     R_b = IDFT_N( DFT_N(f_b) * conj(DFT_N(c)) ), P = sum_b |R_b|^2 2^-24.
     The folded blocks are exact integers, so the only error is FP64 FFT rounding.
-    code_doppler: P[tau] = sum_b |R_b[(tau - delta_b(k)) mod N]|^2 2^-24."""
+    code_doppler: P[tau] = sum_b |R_b[(tau - delta_b(k)) mod N]|^2 2^-24.
+    carrier="exact": the blocks of fold_exact (unit-modulus carrier, so no
+    2^-24 scale), P = sum_b |R_b|^2."""
     import scipy.fft as sfft
 
     N = samples_per_ms(fs_hz)
-    if folded is None:
-        folded = wipe_fold(samples, fmt, fs_hz, f_if, lo, step, n_dopp, T_coh, N_noncoh)
-    f = folded[..., 0].astype(np.float64) + 1j * folded[..., 1].astype(np.float64)
+    scale = POWER_SCALE
+    if carrier == "exact":
+        f = fold_exact(samples, fmt, fs_hz, f_if, lo, step, n_dopp, T_coh, N_noncoh)
+        scale = 1.0
+    else:
+        if folded is None:
+            folded = wipe_fold(samples, fmt, fs_hz, f_if, lo, step, n_dopp, T_coh, N_noncoh)
+        f = folded[..., 0].astype(np.float64) + 1j * folded[..., 1].astype(np.float64)
     F = sfft.fft(f, axis=-1, workers=n_threads())
     del f
     P = np.zeros((len(prns), n_dopp, N), np.float64)
     for pi, prn in enumerate(prns):
         C = np.conj(sfft.fft(code_replica(prn, fs_hz, N).astype(np.float64)))
         R = sfft.ifft(F * C, axis=-1, workers=n_threads())
-        pw = (R.real * R.real + R.imag * R.imag) * POWER_SCALE
+        pw = (R.real * R.real + R.imag * R.imag) * scale
         acc = np.zeros((n_dopp, N), np.float64)
         for b in range(N_noncoh):  # blocks summed in ascending order
             if code_doppler:

@@ -168,8 +168,29 @@ static long long cdiv(long long a, long long b) { return (a + b - 1) / b; }
 // Lays out the requests of a batch: descriptors, prefix sums of work items
 // per stage and workspace sizes.  Device pointers of the request (samples,
 // grid, peaks) are copied; null grids get offsets in the workspace grid.
+// Parameters of the frequency-domain Doppler variant for one request: the
+// smallest P in {1, 2, 4} that makes the Doppler step a whole number kappa of
+// bins of the long DFT (length P * T_coh * N, bin spacing 1 / (P T_coh)),
+// with P * T_coh * spc a power of two <= 256 (the long DFT is a 2^a x 1023
+// prime-factor transform).  Returns false if there is none.
+static bool fd_params(const gnss::Plan &p, int &PTc, int &A, int &kappa)
+{
+    for (int P = 1; P <= 4; P *= 2) {
+        const double x = (double)P * p.Tc * p.step / 1000.0;
+        const double r = std::nearbyint(x);
+        if (r < 1.0 || std::fabs(x - r) > 1e-9 * std::max(1.0, x)) continue;
+        const int a = P * p.Tc * p.spc;
+        if (a > 256 || (a & (a - 1))) return false;
+        PTc = P * p.Tc;
+        A = a;
+        kappa = (int)r;
+        return true;
+    }
+    return false;
+}
+
 void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int corr_pt,
-                 float threshold, int precision, BatchHost &B)
+                 float threshold, int precision, int doppler_fd, BatchHost &B)
 {
     const int corr_w = precision == GNSS_FP16       ? gnss::kCorrWavesH
                        : precision == GNSS_FP16_PFA ? gnss::kCorrWavesX
@@ -177,8 +198,10 @@ void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int c
     B.d.assign(n, gnss::ReqDesc{});
     B.pre.assign((size_t)gnss::kNumStages * (n + 1), 0);
     B.grid_off.assign(n, -1);
-    long long tot[gnss::kNumStages] = {0, 0, 0, 0, 0};
-    long long vec = 0, qk = 0, part = 0, grid_int = 0;
+    B.fd = doppler_fd;
+    B.fd_bad = -1;
+    long long tot[gnss::kNumStages] = {};
+    long long vec = 0, qk = 0, part = 0, grid_int = 0, fd_f2 = 0;
     for (int r = 0; r < n; ++r) {
         const gnss::Plan &p = plans[r];
         gnss::ReqDesc &d = B.d[r];
@@ -208,9 +231,36 @@ void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int c
             B.grid_off[r] = grid_int;
             grid_int += p.grid_elems();
         }
+        long long fd_a = 0, fd_b = 0;
+        if (doppler_fd) {
+            int PTc = 0, A = 0, kappa = 0;
+            if (fd_params(p, PTc, A, kappa)) {
+                d.fd = 1;
+                d.fd_PTc = PTc;
+                d.fd_A = A;
+                d.fd_kappa = kappa;
+                d.fd_off = fd_f2;
+                d.fd_fbase = p.f_if + p.lo;
+                // inverse residue map of the A x 1023 prime-factor DFT
+                long long inv1 = 0, inv2 = 0;
+                for (long long t = 0; t < A; ++t)
+                    if ((t * gnss::kCodeLen) % A == 1 % A) { inv1 = t; break; }
+                for (long long t = 0; t < gnss::kCodeLen; ++t)
+                    if ((t * A) % gnss::kCodeLen == 1) { inv2 = t; break; }
+                d.fd_crt1 = (long long)gnss::kCodeLen * inv1;
+                d.fd_crt2 = (long long)A * inv2;
+                // first-pass and final spectra, then the final spectrum's row maxima
+                fd_f2 += 2LL * p.Nnc * A * gnss::kCodeLen + cdiv((long long)p.Nnc * PTc, 2);
+                fd_a = (long long)p.Nnc * A;
+                fd_b = (long long)p.Nnc * cdiv(gnss::kCodeLen, gnss::kFdCols);
+            } else if (B.fd_bad < 0) {
+                B.fd_bad = r;
+            }
+        }
         const long long cnt[gnss::kNumStages] = {
             (long long)p.n_dopp * p.Nnc, p.n_vec(),
-            (long long)d.n_ptiles * cdiv(d.n_items, corr_w), (long long)p.n_prn * d.n_tau_blk, (long long)p.n_prn};
+            (long long)d.n_ptiles * cdiv(d.n_items, corr_w), (long long)p.n_prn * d.n_tau_blk, (long long)p.n_prn,
+            fd_a, fd_b};
         for (int st = 0; st < gnss::kNumStages; ++st) {
             B.pre[(size_t)st * (n + 1) + r] = tot[st];
             tot[st] += cnt[st];
@@ -226,7 +276,8 @@ void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int c
     B.n = n;
     B.corr_pt = corr_pt;
     B.precision = precision;
-    B.F_bytes = (size_t)vec * gnss::kPolyLen * sizeof(int2);
+    // the frequency-domain variant has no polyphase vectors in F: its long spectra live there
+    B.F_bytes = doppler_fd ? (size_t)fd_f2 * sizeof(float2) : (size_t)vec * gnss::kPolyLen * sizeof(int2);
     B.G_bytes = gnss::g_bytes(vec, precision);
     B.Q_bytes = (size_t)qk * sizeof(float);
     B.K_bytes = (size_t)qk * sizeof(int32_t);
@@ -252,6 +303,17 @@ size_t batch_device_bytes(const BatchHost &B)
 // the device on stream s.  Returns the kernels' view of the batch in L.
 int stage_batch(gnss_ctx *c, Workspace &w, BatchHost &B, hipStream_t s, gnss::Launch &L)
 {
+    if (B.fd) {
+        if (c->precision != GNSS_FP16_PFA)
+            return set_err(GNSS_ENOTSUP, "doppler_fd needs a GNSS_FP16_PFA context");
+        if (c->code_doppler)
+            return set_err(GNSS_ENOTSUP, "doppler_fd and code_doppler are not supported together");
+        if (B.fd_bad >= 0)
+            return set_err(GNSS_ENOTSUP,
+                           "doppler_fd: request %d needs a Doppler step that is a whole number of 1/(P T_coh) "
+                           "bins for P in {1, 2, 4}, with P T_coh spc a power of two <= 256",
+                           B.fd_bad);
+    }
     int rc;
     const size_t mb = meta_bytes(B.n);
     if ((rc = ensure(c, w.F, std::max<size_t>(B.F_bytes, 1))) || (rc = ensure(c, w.G, std::max<size_t>(B.G_bytes, 1))) ||
@@ -294,6 +356,7 @@ int stage_batch(gnss_ctx *c, Workspace &w, BatchHost &B, hipStream_t s, gnss::La
     L.corr_pt = B.corr_pt;
     L.persistent = persistent_for(c, B);
     L.precision = B.precision;
+    L.fd = B.fd;
     for (int st = 0; st < gnss::kNumStages; ++st) L.total[st] = B.total[st];
     return GNSS_OK;
 }
@@ -585,6 +648,13 @@ int gnss_ctx_set(gnss_ctx *ctx, const char *key, double value)
         ctx->persistent_forced = (int)value;
         return GNSS_OK;
     }
+    if (!strcmp(key, "doppler_fd")) {
+        if (value != 0.0 && value != 1.0) return set_err(GNSS_EINVAL, "doppler_fd must be 0 or 1");
+        if (value != 0.0 && ctx->precision != GNSS_FP16_PFA)
+            return set_err(GNSS_ENOTSUP, "doppler_fd needs a GNSS_FP16_PFA context");
+        ctx->doppler_fd = (int)value;
+        return GNSS_OK;
+    }
     if (!strcmp(key, "code_doppler")) {
         if (value != 0.0 && value != 1.0) return set_err(GNSS_EINVAL, "code_doppler must be 0 or 1");
         ctx->code_doppler = (int)value;
@@ -626,7 +696,7 @@ int gnss_workspace_bytes(const gnss_request *req, size_t *bytes)
     BatchHost B;
     gnss_request r = *req;
     r.out_grid = nullptr;
-    build_batch(&p, &r, 1, 2, 2.5f, GNSS_FP32, B);  // FP32 needs the most
+    build_batch(&p, &r, 1, 2, 2.5f, GNSS_FP32, 0, B);  // FP32 needs the most
     *bytes = batch_device_bytes(B) + sample_bytes(p.fmt, (size_t)p.n_samples) + (size_t)p.n_prn * sizeof(gnss_peak);
     return GNSS_OK;
 }
@@ -642,7 +712,7 @@ int gnss_acquire_batch_device(gnss_ctx *ctx, const gnss_request *reqs, int32_t n
     if (g.rc) return g.rc;
     hipStream_t s = (hipStream_t)stream;
     BatchHost B;
-    build_batch(plans.data(), reqs, n_req, corr_ptile_for(ctx, plans.data(), n_req), ctx->threshold, ctx->precision, B);
+    build_batch(plans.data(), reqs, n_req, corr_ptile_for(ctx, plans.data(), n_req), ctx->threshold, ctx->precision, ctx->doppler_fd, B);
     gnss::Launch L;
     if ((rc = stage_batch(ctx, ctx->ws, B, s, L))) return rc;
     return launch(ctx, ctx->ws, L, s, true);
@@ -695,7 +765,7 @@ int gnss_acquire(const void *samples, int32_t fmt, size_t n, double fs, double f
     dr.out_grid = nullptr;  // workspace grid, copied out below
     dr.out_peaks = (gnss_peak *)w.peaks.p;
     BatchHost B;
-    build_batch(&p, &dr, 1, corr_ptile_for(c, &p, 1), c->threshold, c->precision, B);
+    build_batch(&p, &dr, 1, corr_ptile_for(c, &p, 1), c->threshold, c->precision, c->doppler_fd, B);
     gnss::Launch L;
     if ((rc = stage_batch(c, w, B, c->stream, L)) || (rc = launch(c, w, L, c->stream, true))) {
         (void)hipStreamSynchronize(c->stream);
@@ -725,7 +795,7 @@ int gnss_graph_create(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, gn
     if (!gr) return set_err(GNSS_ENOMEM, "host allocation failed");
     gr->ctx = ctx;
     BatchHost B;
-    build_batch(plans.data(), reqs, n_req, corr_ptile_for(ctx, plans.data(), n_req), ctx->threshold, ctx->precision, B);
+    build_batch(plans.data(), reqs, n_req, corr_ptile_for(ctx, plans.data(), n_req), ctx->threshold, ctx->precision, ctx->doppler_fd, B);
     gr->corr_pt = B.corr_pt;
     hipStream_t cs = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);

@@ -82,7 +82,7 @@ inline size_t g_bytes(long long n_vec, int precision)
 // requests (a single request is a batch of one); the correlation kernel can
 // run persistent, the others run one workgroup per work item
 // ---------------------------------------------------------------------------
-enum Stage { kStBox = 0, kStVec, kStCorr, kStColmax, kStPeak, kNumStages };
+enum Stage { kStBox = 0, kStVec, kStCorr, kStColmax, kStPeak, kStFdA, kStFdB, kNumStages };
 constexpr int kXcds = 8;
 
 // One request as the kernels see it (device memory).
@@ -100,6 +100,16 @@ struct ReqDesc {
     int n_tau_blk;        // 256-lag blocks of the detection kernels
     float threshold;
     int code_doppler;     // 1: shift each block's lags by its code-Doppler drift
+    // frequency-domain Doppler (exact-length contexts, option doppler_fd):
+    // one zero-padded DFT of length fd_A * 1023 per block serves every bin
+    int fd;               // 1: this request uses it
+    int fd_PTc;           // P * Tc: bins of the long DFT per 1 kHz
+    int fd_A;             // P * Tc * spc, a power of two
+    int fd_kappa;         // long-DFT bins per Doppler step
+    long long fd_off;     // first float2 of the request's long spectra (first pass, then final)
+    long long fd_crt1;    // 1023 (1023^-1 mod A): long index = (k1 crt1 + k2 crt2) mod M
+    long long fd_crt2;    // A (A^-1 mod 1023)
+    double fd_fbase;      // f_if + lo, removed before the long DFT
     int prns[kMaxList];
 };
 
@@ -120,7 +130,8 @@ struct Launch {
     long long total[kNumStages];  // host copy (grid sizing)
     int corr_pt;                  // PRN tile of the correlation kernel (2 or 4)
     int persistent;               // correlation kernel: 1 occupancy-sized grid with work counters, 0 a workgroup per item
-    int precision;                // GNSS_FP32 / GNSS_FP16
+    int precision;                // GNSS_FP32 / GNSS_FP16 / GNSS_FP16_PFA
+    int fd;                       // 1: frequency-domain Doppler (exact-length contexts)
 };
 
 // Device-resident tables of a context.
@@ -164,6 +175,7 @@ struct TrackDesc {
     long long start;      // first sample of epoch 0
     int fmt, epoch_len, n_epochs, n_ch, ch_off;
 };
+constexpr int kFdCols = 8;  // columns of the long DFT's second pass per workgroup
 constexpr int kTrackThreads = 256;
 constexpr int kTrackCG = 4;  // channels per pass over an epoch
 hipError_t launch_track(const TrackDesc *d_reqs, const long long *d_pre, int n_req, long long total,

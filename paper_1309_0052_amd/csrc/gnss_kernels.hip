@@ -1343,6 +1343,345 @@ __global__ __launch_bounds__(64 * kCorrWavesX) void k_corr_x(const ReqDesc *__re
 }
 
 // ===========================================================================
+// Frequency-domain Doppler (exact-length contexts, option doppler_fd).  The
+// carrier is removed once per block at the base frequency f_if + lo by an
+// exact exponential (FP64 phase, FP32 sin/cos; phase zero at the block start,
+// which leaves |R|^2 unchanged), and one zero-padded DFT of length
+// M = P T_coh N = A * 1023 serves every Doppler bin: bin k's folded block has
+// the N-point spectrum F^[q] = Y_M[P T_coh q + k kappa] (folding T_coh
+// milliseconds keeps every (P T_coh)-th bin of the long spectrum, and the
+// residual carrier k*step shifts it by k*kappa bins).  The one-chip boxcar
+// multiplies by H[q] = sum_{t<spc} e^(2 pi i t q / N), and the polyphase
+// spectra follow from
+//   G_s[j] = (1/spc) e^(2 pi i s j / N) sum_{r<spc} B^[j + 1023 r] e^(2 pi i s r / spc).
+// The long DFT is a prime-factor transform, A x 1023 (coprime): 1023-point
+// DFTs on the matrix cores over the inner index, then A-point DFTs in FP32.
+// Input map n = (1023 n1 + A m) mod M; the final spectrum is kept as
+// X[k1][a * 33 + b'] with k1 = k mod A and (a, b') = (k mod 31, k mod 33).
+// ===========================================================================
+
+// Per (block, residue) maxima of max(|re|, |im|) of the final long spectrum
+// (float bits; non-negative, so they order as unsigned integers), after the
+// request's two spectra in the long-DFT buffer.
+__device__ __forceinline__ uint32_t *fd_rowmax(const float2 *FD, const ReqDesc &d)
+{
+    return (uint32_t *)(FD + d.fd_off + 2LL * d.Nnc * d.fd_A * kCodeLen);
+}
+
+// First pass: one wave per (request, block, n1): the 1023-point DFT over m of
+// the base-wiped samples y[(1023 n1 + A m) mod M] (zero past the block),
+// scaled by its l1 exponent; written in FP32 times 2^e as Z[b][n1][a*33 + b'].
+__global__ __launch_bounds__(256) void k_fd_pass1(const ReqDesc *__restrict__ R, const BatchHdr *H,
+                                                  const long long *pre, const pfa::u4 *__restrict__ fr,
+                                                  float2 *FD)
+{
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+    pfa::FwdB B;
+    pfa::load_fwd(B, fr, l);
+    const int n_req = H->n_req;
+    const long long total = H->total[kStFdA];
+    const long long *pst = pre + (long long)kStFdA * (n_req + 1);
+    for (long long it = (long long)blockIdx.x * 4 + w; it < total; it += (long long)gridDim.x * 4) {
+        const int r = find_req(pst, n_req, uniform64(it));
+        const ReqDesc &d = R[r];
+        const long long local = it - pst[r];
+        const int A = d.fd_A, b = (int)(local / A), n1 = (int)(local % A);
+        const long long M = (long long)A * kCodeLen, L = (long long)d.Tc * d.N;
+        const long long base = (long long)b * L;
+        const double cyc = d.fd_fbase / d.fs;  // carrier cycles per sample
+        if (n1 < d.fd_PTc && l == 0) fd_rowmax(FD, d)[b * d.fd_PTc + n1] = 0u;  // for the second pass
+        float vr[3][2][4], vi[3][2][4];
+        float nrm = 0.f;
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int i31 = 16 * s + 4 * g + j, i33 = 16 * t + c;
+                    float yr = 0.f, yi = 0.f;
+                    if (i31 < pfa::kN1 && i33 < pfa::kN2) {
+                        const long long n = (1023LL * n1 + (long long)A * pfa::time_index(i31, i33)) % M;
+                        if (n < L) {
+                            int xr, xi;
+                            load_sample(d.samples, d.fmt, base + n, xr, xi);
+                            double ph = cyc * (double)n;
+                            ph -= floor(ph);
+                            float sn, cs;
+                            sincospif(2.f * (float)ph, &sn, &cs);
+                            yr = (float)xr * cs + (float)xi * sn;  // x e^(-i theta)
+                            yi = (float)xi * cs - (float)xr * sn;
+                        }
+                    }
+                    vr[t][s][j] = yr;
+                    vi[t][s][j] = yi;
+                    nrm += fabsf(yr) + fabsf(yi);
+                }
+        const int e = l1_exponent(wave_sum(nrm));
+        const float f = ldexpf(1.f, -e), fo = ldexpf(1.f, e);
+        pfa::u4 a1[3][2];
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+                a1[t][s] = pfa::u4{pfa::pack2(vr[t][s][0] * f, vr[t][s][1] * f), pfa::pack2(vr[t][s][2] * f, vr[t][s][3] * f),
+                                   pfa::pack2(vi[t][s][0] * f, vi[t][s][1] * f), pfa::pack2(vi[t][s][2] * f, vi[t][s][3] * f)};
+        pfa::f4 o[2][6];
+        pfa::forward(a1, B, o);
+        float *dst = (float *)(FD + d.fd_off + (long long)(b * A + n1) * kCodeLen);
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 6; ++v)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int a = 16 * u + 4 * g + q, bb = 16 * (v >> 1) + c;
+                    if (a < pfa::kN1 && bb < pfa::kN2) dst[2 * (a * pfa::kN2 + bb) + (v & 1)] = o[u][v][q] * fo;
+                }
+    }
+}
+
+// Second pass: one workgroup per (request, block, 8 columns sigma): the
+// columns' A x 8 values in LDS, the A-point DFTs over n1 in FP32,
+//   Y_M[i] = sum_n1 Z[b][n1][sigma] e^(-2 pi i n1 k1 / A),
+// i = (k1 crt1 + k2 crt2) mod M, k2 the frequency of sigma; stored by residue,
+// Yt[b][i mod P T_coh][i div P T_coh] (i mod P T_coh = k1 mod P T_coh, since
+// crt1 = 1 mod A and crt2 = 0 mod A), so that a Doppler bin's folded spectrum
+// (every (P T_coh)-th bin from an offset) is a contiguous circular run of one
+// row; and each row's max(|re|, |im|).  For A >= 4 a thread computes the four
+// outputs k1 + m A/4 from each LDS value: their weights differ by (-i)^(n1 m).
+__device__ __forceinline__ float2 quarter_turns(float2 t, int q)  // t (-i)^q, q in 0..3
+{
+    return q == 0 ? t : q == 1 ? make_float2(t.y, -t.x) : q == 2 ? make_float2(-t.x, -t.y) : make_float2(-t.y, t.x);
+}
+
+__global__ __launch_bounds__(256) void k_fd_pass2(const ReqDesc *__restrict__ R, const BatchHdr *H,
+                                                  const long long *pre, float2 *FD)
+{
+    __shared__ float2 s_w[256];  // e^(-2 pi i m / 256); A divides 256
+    __shared__ float2 s_z[256 * kFdCols];
+    __shared__ uint32_t s_max[256];
+    for (int m = threadIdx.x; m < 256; m += 256) {
+        float sn, cs;
+        sincospif((float)m / 128.f, &sn, &cs);
+        s_w[m] = make_float2(cs, -sn);
+    }
+    const int n_req = H->n_req;
+    const long long total = H->total[kStFdB];
+    const long long *pst = pre + (long long)kStFdB * (n_req + 1);
+    constexpr int kChunks = (kCodeLen + kFdCols - 1) / kFdCols;
+    for (long long it = blockIdx.x; it < total; it += gridDim.x) {
+        const int r = find_req(pst, n_req, it);
+        const ReqDesc &d = R[r];
+        const long long local = it - pst[r];
+        const int A = d.fd_A, PTc = d.fd_PTc;
+        const int b = (int)(local / kChunks), sig0 = (int)(local % kChunks) * kFdCols;
+        const int ncol = min(kFdCols, kCodeLen - sig0);
+        const long long M = (long long)A * kCodeLen;
+        const int N = (int)(M / PTc);
+        const float2 *z = FD + d.fd_off + (long long)b * A * kCodeLen + sig0;
+        __syncthreads();  // twiddles staged; the previous item's reads of s_z and s_max are done
+        for (int i = threadIdx.x; i < A * kFdCols; i += 256) {
+            const int n1 = i / kFdCols, cc = i % kFdCols;
+            s_z[i] = cc < ncol ? z[(long long)n1 * kCodeLen + cc] : make_float2(0.f, 0.f);
+        }
+        if (threadIdx.x < PTc) s_max[threadIdx.x] = 0u;
+        __syncthreads();
+        const int step = 256 / A;
+        float2 *yt = FD + d.fd_off + (long long)d.Nnc * M + (long long)b * M;
+        auto emit = [&](int k1, int cc, float ar, float ai) {
+            const int sigma = sig0 + cc;
+            const int k2 = pfa::freq_index(sigma / pfa::kN2, sigma % pfa::kN2);
+            const long long i = ((long long)k1 * d.fd_crt1 + (long long)k2 * d.fd_crt2) % M;
+            yt[(i % PTc) * N + i / PTc] = make_float2(ar, ai);
+            atomicMax(&s_max[k1 % PTc], __float_as_uint(fmaxf(fabsf(ar), fabsf(ai))));
+        };
+        if (A >= 4) {
+            const int qa = A / 4;
+            for (int o = threadIdx.x; o < qa * ncol; o += 256) {
+                const int k1 = o / ncol, cc = o % ncol;
+                float2 acc[4] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
+                for (int p4 = 0; p4 < A; p4 += 4) {
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr) {
+                        const int n1 = p4 + rr;
+                        const float2 v = s_z[n1 * kFdCols + cc];
+                        const float2 wv = s_w[(n1 * k1 * step) & 255];
+                        const float2 t = make_float2(v.x * wv.x - v.y * wv.y, v.x * wv.y + v.y * wv.x);
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) {
+                            const float2 u = quarter_turns(t, (rr * m) & 3);
+                            acc[m].x += u.x;
+                            acc[m].y += u.y;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int m = 0; m < 4; ++m) emit(k1 + m * qa, cc, acc[m].x, acc[m].y);
+            }
+        } else {
+            for (int o = threadIdx.x; o < A * ncol; o += 256) {
+                const int k1 = o / ncol, cc = o % ncol;
+                float ar = 0.f, ai = 0.f;
+                for (int n1 = 0; n1 < A; ++n1) {
+                    const float2 v = s_z[n1 * kFdCols + cc];
+                    const float2 wv = s_w[(n1 * k1 * step) & 255];
+                    ar = fmaf(v.x, wv.x, fmaf(-v.y, wv.y, ar));
+                    ai = fmaf(v.x, wv.y, fmaf(v.y, wv.x, ai));
+                }
+                emit(k1, cc, ar, ai);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < PTc) atomicMax(fd_rowmax(FD, d) + b * PTc + threadIdx.x, s_max[threadIdx.x]);
+    }
+}
+
+// In-register inverse DFT of S points, u_s = sum_r v_r e^(2 pi i s r / S):
+// radix 2, decimation in frequency, then the bit-reversal permutation.  tw16[m]
+// = e^(2 pi i m / 16).
+template <int S>
+__device__ __forceinline__ void idft_small(float2 (&v)[kMaxSpc], const float2 *tw16)
+{
+#pragma unroll
+    for (int half = S / 2; half >= 1; half /= 2) {
+#pragma unroll
+        for (int i0 = 0; i0 < S; i0 += 2 * half)
+#pragma unroll
+            for (int j = 0; j < half; ++j) {
+                const float2 a = v[i0 + j], b = v[i0 + j + half];
+                const float2 w = tw16[j * (8 / half)];  // e^(2 pi i j / (2 half))
+                const float2 d = make_float2(a.x - b.x, a.y - b.y);
+                v[i0 + j] = make_float2(a.x + b.x, a.y + b.y);
+                v[i0 + j + half] = make_float2(d.x * w.x - d.y * w.y, d.x * w.y + d.y * w.x);
+            }
+    }
+    float2 t[kMaxSpc];
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+        int rv = 0;
+#pragma unroll
+        for (int k = 1, m = S >> 1; k < S; k <<= 1, m >>= 1)
+            if (i & k) rv |= m;
+        t[rv] = v[i];
+    }
+#pragma unroll
+    for (int i = 0; i < S; ++i) v[i] = t[i];
+}
+
+// Synthesis: one workgroup (512 threads) per (request, Doppler bin, block),
+// the items of k_box.  For each frequency j < 1023 (one thread, reading the
+// long spectrum contiguously) the spc values F^[j + 1023 r] give the
+// polyphase spectra of the fold,
+//   F_s'[j] = (1/spc) e^(2 pi i s' j / N) sum_r F^[j + 1023 r] e^(2 pi i s' r / spc),
+// and the one-chip boxcar (g_s[m] = sum_{s'>=s} f_s'[m] + sum_{s'<s} f_s'[m+1])
+// is G_s[j] = T + (e^(2 pi i j / 1023) - 1) P_s with T = sum_s' F_s' and
+// P_s = sum_{s'<s} F_s'.  The spc spectra are staged in LDS in the stored
+// fragment layout and written out whole.  |G_s| <= spc max |F^| sets the
+// exponent e of the item's vectors (from the row maximum of the second pass).
+constexpr int kSynthThreads = 512;
+__global__ __launch_bounds__(kSynthThreads) void k_fd_synth(const ReqDesc *__restrict__ R, BatchHdr *H,
+                                                            const long long *pre, const float2 *FD, pfa::u4 *Gx,
+                                                            int *E)
+{
+    __shared__ pfa::u4 s_out[kMaxSpc * pfa::kUnits];
+    __shared__ float2 s_tw16[16];
+    __shared__ long long s_item;
+    const int n_req = H->n_req;
+    const long long total = H->total[kStBox];
+    const long long *pst = pre + (long long)kStBox * (n_req + 1);
+    const int tid = threadIdx.x;
+    if (tid < 16) {
+        float sn, cs;
+        sincospif((float)tid / 8.f, &sn, &cs);
+        s_tw16[tid] = make_float2(cs, sn);
+    }
+    bool first = true;
+    for (;;) {
+        const long long it = next_item(H, kStBox, total, &s_item, first);
+        if (it < 0) break;
+        const int r = find_req(pst, n_req, it);
+        const ReqDesc &d = R[r];
+        const int kb = (int)(it - pst[r]);
+        const int k = kb / d.Nnc, b = kb - k * d.Nnc;
+        const int N = d.N, spc = d.spc, A = d.fd_A, PTc = d.fd_PTc;
+        const long long M = (long long)A * kCodeLen;
+        const long long shift = ((long long)k * d.fd_kappa) % M;
+        // F^[q] = Y_M[(q P T_coh + k kappa) mod M] = Yt[rho][(q + delta) mod N] with
+        // k kappa = delta P T_coh + rho
+        const int rho = (int)(shift % PTc), delta = (int)(shift / PTc);
+        const float2 *row = FD + d.fd_off + (long long)d.Nnc * M + (long long)b * M + (long long)rho * N;
+        const float mx = __uint_as_float(fd_rowmax(FD, d)[b * PTc + rho]) * 1.41421357f * (float)spc;
+        int e = 0;
+        if (mx > 0.f) {
+            int x;
+            (void)frexpf(mx * (1.f + 0x1p-10f), &x);  // mx' < 2^x
+            e = x - kL1Exp;
+        }
+        const float scale = ldexpf(1.f, -e) / (float)spc;
+        __syncthreads();  // tables staged; the previous item's copy out of s_out is done
+        uint16_t *o16 = (uint16_t *)s_out;
+        for (int j = tid; j < kCodeLen; j += kSynthThreads) {
+            float2 v[kMaxSpc];
+#pragma unroll
+            for (int rr = 0; rr < kMaxSpc; ++rr) {
+                int qq = j + kCodeLen * rr + delta;
+                if (qq >= N) qq -= N;
+                v[rr] = rr < spc ? row[qq] : make_float2(0.f, 0.f);
+            }
+            switch (spc) {
+            case 2: idft_small<2>(v, s_tw16); break;
+            case 4: idft_small<4>(v, s_tw16); break;
+            case 8: idft_small<8>(v, s_tw16); break;
+            case 16: idft_small<16>(v, s_tw16); break;
+            default: break;  // spc 1: the value itself
+            }
+            float s1, c1, s2, c2;
+            sincospif(2.f * (float)j / (float)N, &s1, &c1);         // e^(2 pi i j / N)
+            sincospif(2.f * (float)j / (float)kCodeLen, &s2, &c2);  // e^(2 pi i j / 1023)
+            float2 wv = make_float2(1.f, 0.f), tsum = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int sp = 0; sp < kMaxSpc; ++sp) {
+                if (sp < spc) {
+                    const float2 f = make_float2((v[sp].x * wv.x - v[sp].y * wv.y) * scale,
+                                                 (v[sp].x * wv.y + v[sp].y * wv.x) * scale);
+                    v[sp] = f;
+                    tsum.x += f.x;
+                    tsum.y += f.y;
+                    wv = make_float2(wv.x * c1 - wv.y * s1, wv.x * s1 + wv.y * c1);
+                }
+            }
+            // fragment position of frequency j: (a, b') = (j mod 31, j mod 33)
+            const int a = j % pfa::kN1, bb = j % pfa::kN2;
+            const int t = bb >> 4, cc = bb & 15, s31 = a >> 4, gg = (a >> 2) & 3, jj = a & 3;
+            const int unit = t < 2 ? (2 * t + s31) * 64 + 16 * gg + cc : pfa::kTailUnit + 4 * s31 + gg;
+            const float2 wm1 = make_float2(c2 - 1.f, s2);
+            float2 pre_s = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int ss = 0; ss < kMaxSpc; ++ss) {
+                if (ss < spc) {
+                    const float gr = tsum.x + wm1.x * pre_s.x - wm1.y * pre_s.y;
+                    const float gi = tsum.y + wm1.x * pre_s.y + wm1.y * pre_s.x;
+                    uint16_t *u16 = o16 + ((long long)ss * pfa::kUnits + unit) * 8;
+                    u16[jj] = __builtin_bit_cast(uint16_t, (_Float16)gr);
+                    u16[4 + jj] = __builtin_bit_cast(uint16_t, (_Float16)gi);
+                    if (a == pfa::kN1 - 1) {  // the unit's padding slot a = 31 (every other slot is written)
+                        u16[3] = 0;
+                        u16[7] = 0;
+                    }
+                    pre_s.x += v[ss].x;
+                    pre_s.y += v[ss].y;
+                }
+            }
+        }
+        __syncthreads();
+        const long long vec0 = d.vec_off + (long long)kb * spc;
+        for (int i = tid; i < spc * pfa::kUnits; i += kSynthThreads) Gx[vec0 * pfa::kUnits + i] = s_out[i];
+        if (tid < spc) E[vec0 + tid] = e;
+    }
+}
+
+// ===========================================================================
 // detection: column max over Doppler, argmax, second peak, mean; refinement
 // ===========================================================================
 // Work item = (request, PRN, block of 256 lags).  Q[tau] = max_k P (lowest k
@@ -1541,6 +1880,34 @@ static unsigned grid_for(long long work, long long cap, bool persistent)
     return (unsigned)g;
 }
 
+// Frequency-domain Doppler: long DFT of every block (two passes), then the
+// block spectra of every (Doppler, block) item; replaces k_box and k_fft_x.
+static hipError_t launch_fd(const Launch &L, const Tables &T, void *d_fd, void *d_G, int *d_E, int n_cu,
+                            hipStream_t s)
+{
+    hipError_t e;
+    if (L.total[kStFdA] > 0) {
+        static int cap = 0;
+        if (!cap) cap = occupancy(k_fd_pass1, 256, n_cu);
+        hipLaunchKernelGGL(k_fd_pass1, dim3(grid_for((L.total[kStFdA] + 3) / 4, cap, false)), dim3(256), 0, s,
+                           L.reqs, L.hdr, L.pre, (const pfa::u4 *)T.frags_x, (float2 *)d_fd);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        static int cap2 = 0;
+        if (!cap2) cap2 = occupancy(k_fd_pass2, 256, n_cu);
+        hipLaunchKernelGGL(k_fd_pass2, dim3(grid_for(L.total[kStFdB], cap2, false)), dim3(256), 0, s,
+                           L.reqs, L.hdr, L.pre, (float2 *)d_fd);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (L.total[kStBox] > 0) {
+        static int cap = 0;
+        if (!cap) cap = occupancy(k_fd_synth, kSynthThreads, n_cu);
+        hipLaunchKernelGGL(k_fd_synth, dim3(grid_for(L.total[kStBox], cap, false)), dim3(kSynthThreads), 0, s,
+                           L.reqs, L.hdr, L.pre, (const float2 *)d_fd, (pfa::u4 *)d_G, d_E);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_batch(const Launch &L, const Tables &T, int2 *d_F, void *d_G, float *d_Q, int32_t *d_K,
                         double *d_part, int n_cu, hipStream_t s, hipEvent_t *marks)
 {
@@ -1557,7 +1924,9 @@ hipError_t launch_batch(const Launch &L, const Tables &T, int2 *d_F, void *d_G, 
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, L.hdr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = mark(0)) != hipSuccess) return e;
-    if (L.total[kStBox] > 0) {
+    if (x && L.fd) {
+        if ((e = launch_fd(L, T, d_F, d_G, d_E, n_cu, s)) != hipSuccess) return e;
+    } else if (L.total[kStBox] > 0) {
         static int cap = 0;
         if (!cap) cap = occupancy(k_box, 256, n_cu);
         hipLaunchKernelGGL(k_box, dim3(grid_for(L.total[kStBox], cap, false)), dim3(256), 0, s, L.reqs,
@@ -1565,7 +1934,9 @@ hipError_t launch_batch(const Launch &L, const Tables &T, int2 *d_F, void *d_G, 
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if ((e = mark(1)) != hipSuccess) return e;
-    if (L.total[kStVec] > 0 && x) {
+    if (x && L.fd) {
+        // the block spectra are already written
+    } else if (L.total[kStVec] > 0 && x) {
         static int cap = 0;
         if (!cap) cap = occupancy(k_fft_x, 256, n_cu);
         hipLaunchKernelGGL(k_fft_x, dim3(grid_for((L.total[kStVec] + 3) / 4, cap, false)), dim3(256), 0, s, d_F,
@@ -1586,7 +1957,8 @@ hipError_t launch_batch(const Launch &L, const Tables &T, int2 *d_F, void *d_G, 
     }
     if ((e = mark(2)) != hipSuccess) return e;
     if (L.total[kStCorr] > 0 && x) {
-        const float osc = ldexpf(1.f, 2 * T.cs_exp - 24) / (float)(kCodeLen * kCodeLen);
+        // the frequency-domain variant wipes with unit exponentials (no LUT scale 2^12)
+        const float osc = ldexpf(1.f, 2 * T.cs_exp - (L.fd ? 0 : 24)) / (float)(kCodeLen * kCodeLen);
         static int cap = 0;
         if (!cap) cap = occupancy(k_corr_x, 64 * kCorrWavesX, n_cu);
         hipLaunchKernelGGL(k_corr_x, dim3(grid_for(L.total[kStCorr], cap, pers)), dim3(64 * kCorrWavesX), 0, s,

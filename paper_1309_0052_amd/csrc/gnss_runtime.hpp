@@ -54,8 +54,10 @@ struct BatchHost {
     std::vector<gnss::ReqDesc> d;
     std::vector<long long> pre;
     std::vector<long long> grid_off;
-    long long total[gnss::kNumStages] = {0, 0, 0, 0, 0};
+    long long total[gnss::kNumStages] = {};
     size_t F_bytes = 0, G_bytes = 0, Q_bytes = 0, K_bytes = 0, part_bytes = 0, grid_bytes = 0;
+    int fd = 0;          // frequency-domain Doppler requested
+    int fd_bad = -1;     // first request it cannot serve, or -1
 };
 
 struct Ticket;
@@ -75,6 +77,7 @@ struct gnss_ctx {
     int persistent_forced = -1;  // correlation grid: 1 occupancy-sized with work counters, 0 one
                                  // workgroup per item, -1 tuned / default (1)
     int code_doppler = 0;   // 1: code-Doppler compensation of the non-coherent sum
+    int doppler_fd = 0;     // 1: frequency-domain Doppler (exact-length contexts)
     int max_slots = 64;     // requests per served batch
     hipStream_t stream = nullptr;
     // tables
@@ -125,7 +128,7 @@ void release_ws(gnss_ctx *c, Workspace &w);
 int make_plan(const gnss_request *r, gnss::Plan &p, bool need_outputs);
 int plan_all(const gnss_request *reqs, int n, std::vector<gnss::Plan> &plans);
 void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int corr_pt, float threshold,
-                 int precision, BatchHost &B);
+                 int precision, int doppler_fd, BatchHost &B);
 size_t meta_bytes(int n);
 size_t batch_device_bytes(const BatchHost &B);
 int stage_batch(gnss_ctx *c, Workspace &w, BatchHost &B, hipStream_t s, gnss::Launch &L);

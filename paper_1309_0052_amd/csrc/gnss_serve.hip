@@ -222,7 +222,7 @@ static int run_slot_once(gnss_ctx *c, Slot &sl)
             pl[i] = sl.members[i]->plan;
         }
         BatchHost P;
-        build_batch(pl.data(), rq.data(), n, 2, c->threshold, c->precision, P);
+        build_batch(pl.data(), rq.data(), n, 2, c->threshold, c->precision, c->doppler_fd, P);
         const size_t sizes[10] = {P.F_bytes, P.G_bytes, P.Q_bytes, P.K_bytes, P.part_bytes, P.grid_bytes,
                                   meta_bytes(n), sb, pb, gb};
         size_t off[10], need = 0;
@@ -257,7 +257,7 @@ static int run_slot_once(gnss_ctx *c, Slot &sl)
         plans[i] = t->plan;
     }
     BatchHost B;
-    build_batch(plans.data(), reqs.data(), n, corr_ptile_for(c, plans.data(), n), c->threshold, c->precision, B);
+    build_batch(plans.data(), reqs.data(), n, corr_ptile_for(c, plans.data(), n), c->threshold, c->precision, c->doppler_fd, B);
     gnss::Launch L;
     if ((rc = stage_batch(c, sl.ws, B, sl.stream, L)) || (rc = launch(c, sl.ws, L, sl.stream, false))) return rc;
     HIP_TRY(hipMemcpyAsync(sl.h_peaks, sl.peaks.p, pb, hipMemcpyDeviceToHost, sl.stream));
@@ -494,7 +494,7 @@ int gnss_submit(gnss_ctx *ctx, const gnss_request *req, uint64_t *ticket)
     t->sample_bytes = sample_bytes(p.fmt, (size_t)p.n_samples);
     BatchHost B;
     gnss_request r1 = *req;
-    build_batch(&p, &r1, 1, corr_ptile_for(ctx, &p, 1), ctx->threshold, ctx->precision, B);
+    build_batch(&p, &r1, 1, corr_ptile_for(ctx, &p, 1), ctx->threshold, ctx->precision, ctx->doppler_fd, B);
     t->need_bytes = batch_device_bytes(B) + t->sample_bytes + (size_t)p.n_prn * sizeof(gnss_peak) +
                     (req->out_grid ? (size_t)p.grid_elems() * sizeof(float) : 0);
     if (t->need_bytes > admit_budget(ctx))
@@ -599,7 +599,7 @@ int gnss_autotune(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, const 
             for (int pers : {1, 0}) {
                 std::lock_guard<std::mutex> lk(ctx->mu);
                 BatchHost B;
-                build_batch(plans.data(), reqs, n_req, pt, ctx->threshold, ctx->precision, B);
+                build_batch(plans.data(), reqs, n_req, pt, ctx->threshold, ctx->precision, ctx->doppler_fd, B);
                 gnss::Launch L;
                 if ((rc = stage_batch(ctx, ctx->ws, B, ctx->stream, L))) break;
                 L.persistent = pers;
