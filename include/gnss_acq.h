@@ -96,7 +96,7 @@ typedef struct gnss_request {
     const int32_t *prn_list; /* host memory, n_prn PRN numbers in 1..37        */
     int32_t n_prn;         /* 1..64                                            */
     double doppler_lo, doppler_hi, doppler_step; /* Hz                        */
-    int32_t T_coh_ms;      /* coherent integration, 1..16 ms                   */
+    int32_t T_coh_ms;      /* coherent integration, 1..64 ms                   */
     int32_t N_noncoh;      /* non-coherent blocks, >= 1                        */
     float *out_grid;       /* nullable; n_prn*n_dopp*N floats [prn][dopp][tau] */
     gnss_peak *out_peaks;  /* n_prn entries, same order as prn_list            */
@@ -147,6 +147,12 @@ void gnss_ctx_destroy(gnss_ctx *ctx);
  * search time; not with code_doppler.  The grid is then sum_b |R_b|^2 of the
  * exactly wiped blocks, on the scale of the NCO path's 2^-24 |R_b|^2 of its
  * 4096-scaled table; 0, the default: NCO and lookup table as in Fig. 2),
+ * "nav_pairs" (1, only on GNSS_FP16_PFA contexts:
+ * navigation-bit hypotheses for coherent integration past one 20 ms bit --
+ * coherent blocks 2i and 2i+1 are combined with both relative signs and the
+ * larger power kept, P = sum_i max(|R_2i + R_2i+1|^2, |R_2i - R_2i+1|^2), so
+ * that a data-bit flip between them does not cancel the signal; needs an even
+ * N_noncoh, else GNSS_ENOTSUP at search time; 0, the default: plain sum),
  * "max_slots" (requests per
  * served batch, 1..4096).
  * Errors: GNSS_EINVAL. */

@@ -238,13 +238,16 @@ def code_shift(b: int, T_coh: int, N: int, f_bin: float) -> int:
 
 def grid_fft(samples, fmt, fs_hz, f_if, prns, lo, step, n_dopp, T_coh, N_noncoh,
              folded: np.ndarray | None = None, code_doppler: bool = False,
-             carrier: str = "nco") -> np.ndarray:
+             carrier: str = "nco", nav_pairs: bool = False) -> np.ndarray:
     """P[p][k][tau] through the correlation theorem in FP64:
     R_b = IDFT_N( DFT_N(f_b) * conj(DFT_N(c)) ), P = sum_b |R_b|^2 2^-24.
     The folded blocks are exact integers, so the only error is FP64 FFT rounding.
     code_doppler: P[tau] = sum_b |R_b[(tau - delta_b(k)) mod N]|^2 2^-24.
     carrier="exact": the blocks of fold_exact (unit-modulus carrier, so no
-    2^-24 scale), P = sum_b |R_b|^2."""
+    2^-24 scale), P = sum_b |R_b|^2.
+    nav_pairs: navigation-bit hypotheses -- blocks 2i and 2i+1 combined with
+    both relative signs, P = sum_i max(|R_2i + R_2i+1|^2, |R_2i - R_2i+1|^2)
+    (after the code-Doppler lag shifts, if any); N_noncoh must be even."""
     import scipy.fft as sfft
 
     N = samples_per_ms(fs_hz)
@@ -262,6 +265,21 @@ def grid_fft(samples, fmt, fs_hz, f_if, prns, lo, step, n_dopp, T_coh, N_noncoh,
     for pi, prn in enumerate(prns):
         C = np.conj(sfft.fft(code_replica(prn, fs_hz, N).astype(np.float64)))
         R = sfft.ifft(F * C, axis=-1, workers=n_threads())
+        if nav_pairs:
+            if N_noncoh % 2:
+                raise ValueError("nav_pairs needs an even N_noncoh")
+            acc = np.zeros((n_dopp, N), np.float64)
+            for k in range(n_dopp):
+                shifts = [code_shift(b, T_coh, N, bin_freq(lo, step, k)) if code_doppler else 0
+                          for b in range(N_noncoh)]
+                for i in range(N_noncoh // 2):  # pairs summed in ascending order
+                    ra = np.roll(R[k, 2 * i], shifts[2 * i])
+                    rb = np.roll(R[k, 2 * i + 1], shifts[2 * i + 1])
+                    plus, minus = ra + rb, ra - rb
+                    acc[k] += np.maximum(plus.real ** 2 + plus.imag ** 2, minus.real ** 2 + minus.imag ** 2) * scale
+            P[pi] = acc
+            del R
+            continue
         pw = (R.real * R.real + R.imag * R.imag) * scale
         acc = np.zeros((n_dopp, N), np.float64)
         for b in range(N_noncoh):  # blocks summed in ascending order

@@ -133,7 +133,9 @@ int make_plan(const gnss_request *r, gnss::Plan &p, bool need_outputs)
         return set_err(GNSS_EINVAL, "Doppler window needs lo <= hi and step > 0");
     double nd = floor((r->doppler_hi - r->doppler_lo) / r->doppler_step + 1e-9) + 1.0;
     if (nd > 65536.0) return set_err(GNSS_EINVAL, "more than 65536 Doppler bins");
-    if (r->T_coh_ms < 1 || r->T_coh_ms > 16) return set_err(GNSS_EINVAL, "T_coh_ms outside [1, 16]");
+    // the folded and boxcar-summed block is exact in int32: |x LUT| <= 2 * 127 * 4096 per sample,
+    // times T_coh_ms (fold) times spc <= 16 (boxcar) stays below 2^31 up to 64 ms
+    if (r->T_coh_ms < 1 || r->T_coh_ms > 64) return set_err(GNSS_EINVAL, "T_coh_ms outside [1, 64]");
     if (r->N_noncoh < 1 || r->N_noncoh > 100000) return set_err(GNSS_EINVAL, "N_noncoh outside [1, 100000]");
     if (fs % 1023000 != 0 || fs / 1023000 > gnss::kMaxSpc)
         return set_err(GNSS_ENOTSUP, "fs %lld Hz is not k * 1.023 MHz with 1 <= k <= %d", (long long)fs,
@@ -303,6 +305,13 @@ size_t batch_device_bytes(const BatchHost &B)
 // the device on stream s.  Returns the kernels' view of the batch in L.
 int stage_batch(gnss_ctx *c, Workspace &w, BatchHost &B, hipStream_t s, gnss::Launch &L)
 {
+    if (c->nav_pairs) {
+        if (c->precision != GNSS_FP16_PFA)
+            return set_err(GNSS_ENOTSUP, "nav_pairs needs a GNSS_FP16_PFA context");
+        for (int r = 0; r < B.n; ++r)
+            if (B.d[r].Nnc % 2)
+                return set_err(GNSS_ENOTSUP, "nav_pairs: request %d has an odd N_noncoh (%d)", r, B.d[r].Nnc);
+    }
     if (B.fd) {
         if (c->precision != GNSS_FP16_PFA)
             return set_err(GNSS_ENOTSUP, "doppler_fd needs a GNSS_FP16_PFA context");
@@ -324,6 +333,7 @@ int stage_batch(gnss_ctx *c, Workspace &w, BatchHost &B, hipStream_t s, gnss::La
     for (int r = 0; r < B.n; ++r) {
         if (B.grid_off[r] >= 0) B.d[r].grid = (float *)w.grid.p + B.grid_off[r];
         B.d[r].code_doppler = c->code_doppler;
+        B.d[r].nav_pairs = c->nav_pairs;
     }
     // pinned staging: wait until the previous copy out of it has finished
     if (w.stage_ev) HIP_TRY(hipEventSynchronize(w.stage_ev));
@@ -646,6 +656,13 @@ int gnss_ctx_set(gnss_ctx *ctx, const char *key, double value)
         if (value != -1.0 && value != 0.0 && value != 1.0)
             return set_err(GNSS_EINVAL, "persistent must be 0, 1 or -1 (tuned)");
         ctx->persistent_forced = (int)value;
+        return GNSS_OK;
+    }
+    if (!strcmp(key, "nav_pairs")) {
+        if (value != 0.0 && value != 1.0) return set_err(GNSS_EINVAL, "nav_pairs must be 0 or 1");
+        if (value != 0.0 && ctx->precision != GNSS_FP16_PFA)
+            return set_err(GNSS_ENOTSUP, "nav_pairs needs a GNSS_FP16_PFA context");
+        ctx->nav_pairs = (int)value;
         return GNSS_OK;
     }
     if (!strcmp(key, "doppler_fd")) {

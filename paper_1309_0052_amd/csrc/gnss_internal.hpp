@@ -100,6 +100,7 @@ struct ReqDesc {
     int n_tau_blk;        // 256-lag blocks of the detection kernels
     float threshold;
     int code_doppler;     // 1: shift each block's lags by its code-Doppler drift
+    int nav_pairs;        // 1: blocks combined in pairs, max over the relative sign (navigation bit)
     // frequency-domain Doppler (exact-length contexts, option doppler_fd):
     // one zero-padded DFT of length fd_A * 1023 per block serves every bin
     int fd;               // 1: this request uses it

@@ -1304,6 +1304,76 @@ __global__ __launch_bounds__(64 * kCorrWavesX) void k_corr_x(const ReqDesc *__re
                         }
                     }
                 };
+                if (d.nav_pairs) {
+                    // Navigation-bit hypotheses: blocks 2i and 2i + 1 combined
+                    // coherently with both relative signs, max over the two;
+                    // R_a +- R_b is the inverse transform of (G_a +- G_b) conj(C).
+                    // The + hypothesis's power waits in the wave's part of s_stage,
+                    // which is free until the item's grid write.
+                    float *pplus = s_stage + w * 1024;
+                    for (int b = 0; b < d.Nnc; b += 2) {
+                        stage_spectrum(spectrum(b), bufs, l);
+                        stage_spectrum(spectrum(b + 1), bufs + kXBuf, l);
+                        const int ea = E[v0 + (long long)b * spc], eb = E[v0 + (long long)(b + 1) * spc];
+                        const int e = max(ea, eb);
+                        // 2^(ea - e) and 2^(eb - e) in FP16 (exact; below 2^-24 they vanish,
+                        // as that block's contribution does at FP16 precision)
+                        const float fa32 = ldexpf(1.f, ea - e), fb32 = ldexpf(1.f, eb - e);
+                        const __half2 fa = __floats2half2_rn(fa32, fa32), fb = __floats2half2_rn(fb32, fb32);
+                        const float sc = ldexpf(1.f, 2 * e);
+                        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // both blocks are in LDS
+#pragma unroll
+                        for (int hyp = 0; hyp < 2; ++hyp) {
+                            pfa::u4 a1[3][2];
+#pragma unroll
+                            for (int t = 0; t < 3; ++t)
+#pragma unroll
+                                for (int ss = 0; ss < 2; ++ss) {
+                                    const int unit = t < 2 ? (2 * t + ss) * 64 + l : pfa::kTailUnit + 4 * ss + g;
+                                    if (t < 2 || c == 0) {
+                                        const pfa::u4 ga = bufs[unit], gb = bufs[kXBuf + unit];
+                                        pfa::u4 gs;
+#pragma unroll
+                                        for (int q = 0; q < 4; ++q) {
+                                            const __half2 x = __hmul2(bits_h2(ga[q]), fa), y = __hmul2(bits_h2(gb[q]), fb);
+                                            gs[q] = h2_bits(hyp == 0 ? __hadd2(x, y) : __hsub2(x, y));
+                                        }
+                                        a1[t][ss] = cmul_conj_frag(gs, s_c[unit]);
+                                    } else {
+                                        a1[t][ss] = zero4;
+                                    }
+                                }
+                            pfa::f4 o[2][5];
+                            __builtin_amdgcn_s_setprio(1);
+                            pfa::inverse(a1, B, o);
+                            __builtin_amdgcn_s_setprio(0);
+#pragma unroll
+                            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                                for (int h = 0; h < 3; ++h)
+#pragma unroll
+                                    for (int q = 0; q < 4; ++q) {
+                                        float pw;
+                                        if (h < 2) {
+                                            const float yr = o[u][2 * h][q], yi = o[u][2 * h + 1][q];
+                                            pw = fmaf(yr, yr, yi * yi);
+                                        } else {  // column 32: re in lane c = 0, im in lane c = 1
+                                            const float t2 = o[u][4][q] * o[u][4][q];
+                                            pw = t2 + from_next_lane(t2);
+                                        }
+                                        const int n1 = 16 * u + 4 * g + q, n2 = 16 * h + c;
+                                        if (n1 < pfa::kN1 && n2 < pfa::kN2) {
+                                            float *slot = pplus + pfa::time_index(n1, n2);
+                                            if (hyp == 0)
+                                                *slot = pw;
+                                            else
+                                                acc[u][h][q] = fmaf(fmaxf(*slot, pw), sc, acc[u][h][q]);
+                                        }
+                                    }
+                            lds_fence();
+                        }
+                    }
+                } else {
                 stage_spectrum(spectrum(0), bufs, l);
                 int e_next = E[v0];
                 for (int b = 0; b < d.Nnc; ++b) {
@@ -1325,6 +1395,10 @@ __global__ __launch_bounds__(64 * kCorrWavesX) void k_corr_x(const ReqDesc *__re
                     __builtin_amdgcn_s_setprio(0);
                     power(o, sc);
                 }
+                }
+            }
+            __syncthreads();  // every wave is done with s_stage (the pair hypotheses use it)
+            if (active) {
 #pragma unroll
                 for (int u = 0; u < 2; ++u)
 #pragma unroll

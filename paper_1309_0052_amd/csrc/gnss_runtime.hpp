@@ -78,6 +78,7 @@ struct gnss_ctx {
                                  // workgroup per item, -1 tuned / default (1)
     int code_doppler = 0;   // 1: code-Doppler compensation of the non-coherent sum
     int doppler_fd = 0;     // 1: frequency-domain Doppler (exact-length contexts)
+    int nav_pairs = 0;      // 1: blocks in pairs, max over the navigation-bit sign (exact-length contexts)
     int max_slots = 64;     // requests per served batch
     hipStream_t stream = nullptr;
     // tables

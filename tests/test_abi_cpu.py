@@ -70,7 +70,7 @@ def _acquire(x, **kw):
     (dict(step=-1.0), G.GNSS_EINVAL),
     (dict(lo=100.0, hi=-100.0), G.GNSS_EINVAL),
     (dict(T=0), G.GNSS_EINVAL),
-    (dict(T=17), G.GNSS_EINVAL),
+    (dict(T=65), G.GNSS_EINVAL),
     (dict(Nn=0), G.GNSS_EINVAL),
     (dict(Nn=11), G.GNSS_EINVAL),                 # needs more samples than given
     (dict(fmt=7), G.GNSS_EINVAL),
