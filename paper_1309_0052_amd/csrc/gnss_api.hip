@@ -367,6 +367,7 @@ int stage_batch(gnss_ctx *c, Workspace &w, BatchHost &B, hipStream_t s, gnss::La
     L.persistent = persistent_for(c, B);
     L.precision = B.precision;
     L.fd = B.fd;
+    L.nav_pairs = c->nav_pairs;
     for (int st = 0; st < gnss::kNumStages; ++st) L.total[st] = B.total[st];
     return GNSS_OK;
 }

@@ -133,6 +133,7 @@ struct Launch {
     int persistent;               // correlation kernel: 1 occupancy-sized grid with work counters, 0 a workgroup per item
     int precision;                // GNSS_FP32 / GNSS_FP16 / GNSS_FP16_PFA
     int fd;                       // 1: frequency-domain Doppler (exact-length contexts)
+    int nav_pairs;                // 1: navigation-bit hypotheses (exact-length contexts)
 };
 
 // Device-resident tables of a context.

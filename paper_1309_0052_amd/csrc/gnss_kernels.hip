@@ -1224,6 +1224,7 @@ __device__ __forceinline__ pfa::u4 cmul_conj_frag(pfa::u4 g, pfa::u4 c)
 // Correlation, exact-length mode.  Work item = (request, PRN tile, chunk of
 // kCorrWavesX (Doppler, phase) items); one wave per item; the tile's PRNs in
 // turn, each over all blocks with its sums in registers, then written.
+template <bool PAIRS>
 __global__ __launch_bounds__(64 * kCorrWavesX) void k_corr_x(const ReqDesc *__restrict__ R, BatchHdr *H,
                                                              const long long *pre, const pfa::u4 *Gx,
                                                              const int *E, const pfa::u4 *__restrict__ CSx,
@@ -1304,7 +1305,7 @@ __global__ __launch_bounds__(64 * kCorrWavesX) void k_corr_x(const ReqDesc *__re
                         }
                     }
                 };
-                if (d.nav_pairs) {
+                if constexpr (PAIRS) {
                     // Navigation-bit hypotheses: blocks 2i and 2i + 1 combined
                     // coherently with both relative signs, max over the two;
                     // R_a +- R_b is the inverse transform of (G_a +- G_b) conj(C).
@@ -2033,11 +2034,21 @@ hipError_t launch_batch(const Launch &L, const Tables &T, int2 *d_F, void *d_G, 
     if (L.total[kStCorr] > 0 && x) {
         // the frequency-domain variant wipes with unit exponentials (no LUT scale 2^12)
         const float osc = ldexpf(1.f, 2 * T.cs_exp - (L.fd ? 0 : 24)) / (float)(kCodeLen * kCodeLen);
-        static int cap = 0;
-        if (!cap) cap = occupancy(k_corr_x, 64 * kCorrWavesX, n_cu);
-        hipLaunchKernelGGL(k_corr_x, dim3(grid_for(L.total[kStCorr], cap, pers)), dim3(64 * kCorrWavesX), 0, s,
-                           L.reqs, L.hdr, L.pre, (const pfa::u4 *)d_G, d_E, (const pfa::u4 *)T.cs_x,
-                           (const pfa::u4 *)T.frags_x, osc);
+        // the pair variant is a separate instantiation: its registers would halve the
+        // plain kernel's occupancy
+        if (L.nav_pairs) {
+            static int cap = 0;
+            if (!cap) cap = occupancy(k_corr_x<true>, 64 * kCorrWavesX, n_cu);
+            hipLaunchKernelGGL(k_corr_x<true>, dim3(grid_for(L.total[kStCorr], cap, pers)), dim3(64 * kCorrWavesX),
+                               0, s, L.reqs, L.hdr, L.pre, (const pfa::u4 *)d_G, d_E, (const pfa::u4 *)T.cs_x,
+                               (const pfa::u4 *)T.frags_x, osc);
+        } else {
+            static int cap = 0;
+            if (!cap) cap = occupancy(k_corr_x<false>, 64 * kCorrWavesX, n_cu);
+            hipLaunchKernelGGL(k_corr_x<false>, dim3(grid_for(L.total[kStCorr], cap, pers)), dim3(64 * kCorrWavesX),
+                               0, s, L.reqs, L.hdr, L.pre, (const pfa::u4 *)d_G, d_E, (const pfa::u4 *)T.cs_x,
+                               (const pfa::u4 *)T.frags_x, osc);
+        }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     } else if (L.total[kStCorr] > 0 && h) {
         const float osc = ldexpf(1.f, 2 * T.cs_exp - 46);
