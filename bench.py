@@ -165,6 +165,8 @@ def main():
                          "serves every bin; exact-exponential carrier)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-other-modes", action="store_true",
+                    help="skip timing the snapshot on the FP16 and exact-length modes beside FP32")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -301,10 +303,59 @@ def main():
                        "planted_found": sorted(planted & detected)},
         "source_hash": kernel_source_hash(),
     }
+    if not args.no_other_modes and args.precision == "fp32" and not args.doppler_fd:
+        out["other_modes"] = other_modes(args, G, torch, d_x, snap, srch, cells, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(snap, srch, args.cpu_seconds)
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def other_modes(args, G, torch, d_x, snap, srch, cells, stream):
+    """The same snapshot on the other precision modes of the same GPU (their
+    parity against the FP64 oracle is in tests/test_gpu_fp16.py and
+    test_gpu_fd.py): ms per step, cells/s, stage times and the correlation
+    kernel's roofline."""
+    nd = G.n_doppler(srch.lo, srch.hi, srch.step)
+    N = snap.fs_hz // 1000
+    n_prn = len(srch.prns)
+    units = n_prn * nd * srch.N_noncoh
+    flops_unit = 5.0 * N * math.log2(N) + 10.0 * N
+    res = {}
+    for name, prec, opts in (("fp16", "fp16", {}), ("fp16pfa", "fp16pfa", {}),
+                             ("fp16pfa_doppler_fd", "fp16pfa", {"doppler_fd": 1})):
+        c = G.Context(0, precision=precision_const(G, prec))
+        for k, v in opts.items():
+            c.set(k, v)
+        g = torch.empty(n_prn * nd * N, dtype=torch.float32, device="cuda")
+        pk = torch.zeros(n_prn * 48, dtype=torch.uint8, device="cuda")
+        req = G.make_request(d_x.data_ptr(), snap.fmt, snap.n, snap.fs_hz, snap.f_if_hz, srch.prns, srch.lo,
+                             srch.hi, srch.step, srch.T_coh, srch.N_noncoh, g.data_ptr(), pk.data_ptr())
+        c.autotune([req], os.path.join("/tmp", "gnss_autotune.txt"))
+        c.set("profile", 1)
+        for _ in range(args.warmup):
+            c.acquire_device(req, stream)
+        torch.cuda.synchronize()
+        c.stage_times(reset=True)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        steps = max(1, min(args.steps, 10))
+        ev[0].record(stream)
+        for _ in range(steps):
+            c.acquire_device(req, stream)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / steps
+        st = c.stage_times(reset=True)
+        corr_ms = st["corr"][0] / max(1, st["corr"][1])
+        p = pk.cpu().numpy().view(G.PEAK_DTYPE)
+        res[name] = {"ms_per_step": ms, "value": cells / (ms / 1e3), "unit": "cells/s", "dtype": DTYPE[prec],
+                     "stages_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in st.items()},
+                     "roofline": corr_roofline(prec, units * flops_unit, corr_ms,
+                                               read_traffic(CORR_KERNEL[prec][2:], args.workload) if not opts else None,
+                                               units * (N // 1023)),
+                     "detected": sorted(int(r["prn"]) for r in p if r["detected"])}
+        c.close()
+    return res
 
 
 def _cells(srch, fs_hz):
