@@ -1227,7 +1227,7 @@ __device__ __forceinline__ pfa::u4 cmul_conj_frag(pfa::u4 g, pfa::u4 c)
 template <bool PAIRS>
 __global__ __launch_bounds__(64 * kCorrWavesX) void k_corr_x(const ReqDesc *__restrict__ R, BatchHdr *H,
                                                              const long long *pre, const pfa::u4 *Gx,
-                                                             const int *E, const pfa::u4 *__restrict__ CSx,
+                                                             const int *__restrict__ E, const pfa::u4 *__restrict__ CSx,
                                                              const pfa::u4 *__restrict__ fr, float out_scale)
 {
     constexpr int W = kCorrWavesX;
@@ -1237,7 +1237,8 @@ __global__ __launch_bounds__(64 * kCorrWavesX) void k_corr_x(const ReqDesc *__re
     __shared__ pfa::u4 s_g[W * 2 * kXBuf];  // two block spectra per wave
     __shared__ long long s_item;
     const int tid = threadIdx.x;
-    const int w = tid >> 6, l = tid & 63, g = l >> 4, c = l & 15;
+    // the wave index is uniform: item indices, block addresses and exponents stay scalar
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63, g = l >> 4, c = l & 15;
     pfa::InvB B;
     pfa::load_inv(B, fr, l);
     const int n_req = H->n_req;
@@ -1287,7 +1288,12 @@ __global__ __launch_bounds__(64 * kCorrWavesX) void k_corr_x(const ReqDesc *__re
                             a1[t][ss] = has ? cmul_conj_frag(cur[unit], s_c[unit]) : zero4;
                         }
                 };
-                auto power = [&](const pfa::f4 (&o)[2][5], float sc) {
+                // |.|^2 into the sums, which are kept in units of 2^(2 e_ref), e_ref
+                // the exponent of the last block added: a block at e_ref adds its
+                // power unscaled.  Column 32 has its real part in lane c = 0 and its
+                // imaginary part in lane c = 1: each lane sums its own square and
+                // the two are added at the end.
+                auto power_unit = [&](const pfa::f4 (&o)[2][5]) {
 #pragma unroll
                     for (int u = 0; u < 2; ++u) {
 #pragma unroll
@@ -1295,14 +1301,10 @@ __global__ __launch_bounds__(64 * kCorrWavesX) void k_corr_x(const ReqDesc *__re
 #pragma unroll
                             for (int q = 0; q < 4; ++q) {
                                 const float yr = o[u][2 * h][q], yi = o[u][2 * h + 1][q];
-                                acc[u][h][q] = fmaf(fmaf(yr, yr, yi * yi), sc, acc[u][h][q]);
+                                acc[u][h][q] = fmaf(yi, yi, fmaf(yr, yr, acc[u][h][q]));
                             }
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            // column 32: re in lane c = 0, im in lane c = 1
-                            const float t2 = o[u][4][q] * o[u][4][q];
-                            acc[u][2][q] = fmaf(t2 + from_next_lane(t2), sc, acc[u][2][q]);
-                        }
+                        for (int q = 0; q < 4; ++q) acc[u][2][q] = fmaf(o[u][4][q], o[u][4][q], acc[u][2][q]);
                     }
                 };
                 if constexpr (PAIRS) {
@@ -1376,12 +1378,12 @@ __global__ __launch_bounds__(64 * kCorrWavesX) void k_corr_x(const ReqDesc *__re
                     }
                 } else {
                 stage_spectrum(spectrum(0), bufs, l);
-                int e_next = E[v0];
+                int e_cur = E[v0], e_ref = e_cur, e_max = e_cur;
                 for (int b = 0; b < d.Nnc; ++b) {
-                    const float sc = ldexpf(1.f, 2 * e_next);
                     pfa::u4 a1[3][2];
                     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // block b is in LDS
                     product(bufs + (b & 1) * kXBuf, a1);
+                    int e_next = 0;
                     if (b + 1 < d.Nnc) {
                         // the other buffer was last read by block b - 1's product
                         stage_spectrum(spectrum(b + 1), bufs + ((b + 1) & 1) * kXBuf, l);
@@ -1394,8 +1396,48 @@ __global__ __launch_bounds__(64 * kCorrWavesX) void k_corr_x(const ReqDesc *__re
                     __builtin_amdgcn_s_setprio(1);
                     pfa::inverse(a1, B, o);
                     __builtin_amdgcn_s_setprio(0);
-                    power(o, sc);
+                    if (e_cur != e_ref) {
+                        // Another block exponent: bring the sums to it (a power of
+                        // two, exact).  A block's power is below 2^30 in its own
+                        // units and Nnc < 2^17, so the sums stay below 2^47 in the
+                        // units of the largest exponent so far, e_max; scaling to
+                        // e_cur >= e_max - 30 multiplies them by at most 2^60 over
+                        // that, which stays finite.  A block more than 2^30 below
+                        // e_max adds less than 2^-60 of that block's power and is
+                        // dropped (an all-zero block has exponent 0 and power 0).
+                        if (e_cur >= e_max - 30) {
+                            const float f = ldexpf(1.f, 2 * (e_ref - e_cur));
+#pragma unroll
+                            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                                for (int h = 0; h < 3; ++h)
+#pragma unroll
+                                    for (int q = 0; q < 4; ++q) acc[u][h][q] *= f;
+                            e_ref = e_cur;
+                            e_max = max(e_max, e_cur);
+                        } else {
+#pragma unroll
+                            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                                for (int v = 0; v < 5; ++v) o[u][v] = pfa::f4{0.f, 0.f, 0.f, 0.f};
+                        }
+                    }
+                    power_unit(o);
+                    e_cur = e_next;
                 }
+                // column 32: lane c = 0 adds lane c = 1's imaginary part; then
+                // the sums in absolute units
+                const float f = ldexpf(1.f, 2 * e_ref);
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[u][2][q] += from_next_lane(acc[u][2][q]);
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int h = 0; h < 3; ++h)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) acc[u][h][q] *= f;
                 }
             }
             __syncthreads();  // every wave is done with s_stage (the pair hypotheses use it)

@@ -36,6 +36,7 @@ eta ~ sqrt(11) u ~ 3.3 u, and the same argument gives TOLX = 2 * 6 * eta =
 2.0e-2.
 """
 import time
+import types
 
 import numpy as np
 import pytest
@@ -102,6 +103,45 @@ def _check(grid, pk, P, srch, spc, planted, prec):
         "identical %d / %d, near-tie exemptions %d" % (NAME[prec], worst, max(peak_err) if peak_err else 0.0,
                                                         agree, len(ref), exempt))
     return worst
+
+
+AMP_SEQUENCES = [
+    # per-block content: "full" int8 noise at full scale, "one" a single unit sample,
+    # "zero" no signal, an integer k noise in [-k, k]
+    ("extreme", ["one", "full", "zero", 2, "full", "one"]),
+    ("mild", [10, 127, 40, 127, 3, 80]),
+]
+
+
+@pytest.mark.parametrize("seq", AMP_SEQUENCES, ids=[a[0] for a in AMP_SEQUENCES])
+def test_block_exponents_change_between_blocks(ctx16, seq):
+    """Blocks of very different amplitude get different per-vector exponents
+    (up to ~20 binades apart): the block sums are rescaled between blocks
+    (exact powers of two) and must still meet the mode's bound; a block of
+    zeros adds nothing."""
+    name, amps = seq
+    fs, Tc, Nnc = 4092000, 4, len(amps)
+    N = fs // 1000
+    L = Tc * N
+    rng = np.random.default_rng(sum(name.encode()))
+    x = np.zeros(2 * L * Nnc, np.int8)
+    for b, a in enumerate(amps):
+        blk = x[2 * L * b:2 * L * (b + 1)]
+        if a == "full":
+            blk[:] = rng.integers(-127, 128, 2 * L)
+        elif a == "one":
+            blk[2 * int(rng.integers(0, L))] = 1
+        elif a != "zero":
+            blk[:] = rng.integers(-a, a + 1, 2 * L)
+    snap = types.SimpleNamespace(samples=x, fmt=O.CPLX_I8, n=L * Nnc, fs_hz=fs, f_if_hz=0.0)
+    srch = synth.Search([5, 22], -1000.0, 1000.0, 500.0, Tc, Nnc)
+    nd = O.n_doppler(srch.lo, srch.hi, srch.step)
+    P = O.grid_fft(x, O.CPLX_I8, fs, 0.0, srch.prns, srch.lo, srch.step, nd, Tc, Nnc)
+    grid, _ = _run(ctx16, snap, srch)
+    assert np.all(np.isfinite(grid))
+    worst = grid_error(grid, P)
+    log("  %s, blocks %s: max mixed error %.3e" % (NAME[ctx16.prec], name, worst))
+    assert worst <= TOL[ctx16.prec]
 
 
 def test_fp16_rejects_unknown_precision():
