@@ -406,24 +406,47 @@ __device__ __forceinline__ int code_shift(const ReqDesc &d, int k, int b)
 // Wipe + fold of samples n0 .. n0 + len - 1 (mod N) of block b into s_f,
 // FMT-specialised; the phase of the folded milliseconds advances by N D (mod
 // 2^32) from one to the next, and |x| <= 127, |LUT| <= 4096 make the 24-bit
-// multiplies exact.  Same values as wipe_fold_one.
+// multiplies exact.  Same values as wipe_fold_one.  Samples are addressed from
+// the block's first byte (the same pointer in every thread) by 32-bit in-block
+// offsets: a block holds Tc N <= 64 * 16368 samples.
 template <int FMT>
 __device__ __forceinline__ void box_wipe(const void *samples, int N, int Tc, const uint32_t *s_lut, uint32_t D,
                                          int b, int n0, int len, int shift, int2 *s_f)
 {
     const uint32_t dN = (uint32_t)N * D;
     const long long base = (long long)b * Tc * N;
+    // 2-bit packed records: the block may start inside a byte
+    const uint32_t sub = FMT == GNSS_REAL_2BIT_PACKED ? (uint32_t)(base & 3) : 0u;
+    const long long blk_byte = FMT == GNSS_CPLX_I8 ? 2 * base : FMT == GNSS_REAL_I8 ? base : (base >> 2);
+    const GNSS_GLOBAL uint8_t *blk = (const GNSS_GLOBAL uint8_t *)samples + blk_byte;
+    const uint32_t step = FMT == GNSS_CPLX_I8 ? 2u * (uint32_t)N : (uint32_t)N;  // bytes (samples if packed)
     for (int i = threadIdx.x; i < len; i += 256) {
         int n = n0 + i - shift;  // shift in [0, N): the block read circularly delayed
         if (n < 0) n += N;
         if (n >= N) n -= N;
-        long long ng = base + n;
-        uint32_t ph = (uint32_t)ng * D;
+        uint32_t ph = (uint32_t)(base + n) * D;
+        // the milliseconds' phases are ph + c N D: additions, not one multiply each
+        asm volatile("" : "+v"(ph));
+        // byte offset (sample index if packed) of millisecond c in the block
+        uint32_t off = FMT == GNSS_CPLX_I8 ? 2u * (uint32_t)n : (uint32_t)n + sub;
         int yr = 0, yi = 0;
 #pragma unroll 4
         for (int c = 0; c < Tc; ++c) {
             int xr, xi;
-            load_sample(samples, FMT, ng, xr, xi);
+            if (FMT == GNSS_CPLX_I8) {
+                const uint32_t v = *(const GNSS_GLOBAL uint16_t *)(blk + off);  // I in the low byte
+                xr = (int)(int8_t)(v & 0xFFu);
+                xi = (int)(int8_t)(v >> 8);
+            } else if (FMT == GNSS_REAL_I8) {
+                xr = (int)(int8_t)blk[off];
+                xi = 0;
+            } else {
+                const uint32_t code = (blk[off >> 2] >> (2u * (off & 3u))) & 3u;
+                // 00:+1 01:+3 10:-1 11:-3
+                const int mag = (code & 1u) ? 3 : 1;
+                xr = (code & 2u) ? -mag : mag;
+                xi = 0;
+            }
             const uint32_t e = s_lut[ph >> 22];
             const int cs = (int)(int16_t)(e & 0xFFFFu), sn = (int)(int16_t)(e >> 16);
             if (FMT == GNSS_CPLX_I8) {
@@ -433,7 +456,7 @@ __device__ __forceinline__ void box_wipe(const void *samples, int N, int Tc, con
                 yr += __mul24(xr, cs);
                 yi -= __mul24(xr, sn);
             }
-            ng += N;
+            off += step;
             ph += dN;
         }
         s_f[bpad(i)] = make_int2(yr, yi);

@@ -153,6 +153,9 @@ def test_fp16_rejects_unknown_precision():
 SEARCH_CASES = [
     # name, fmt, fs, f_if, Tc, Nnc, prns searched, planted, lo, hi, step, cn0
     ("spc1_cplx", O.CPLX_I8, 1023000, 0.0, 1, 2, [3, 9], [9], -1000.0, 1000.0, 1000.0, 50.0),
+    # N = 1023: the 2-bit blocks start at sample offsets 0, 3, 2, 1 within a byte
+    ("spc1_packed_subbyte", O.REAL_2BIT_PACKED, 1023000, 255750.0, 1, 4, [2, 7, 11], [7], -1000.0, 1000.0,
+     500.0, 54.0),
     ("spc2_packed_ragged", O.REAL_2BIT_PACKED, 2046000, 511500.0, 2, 3, [1, 5, 9, 13, 17],
      [5, 13], -1500.0, 1500.0, 500.0, 48.0),
     ("spc4_real", O.REAL_I8, 4092000, 1023000.0, 1, 4, [2, 4, 6, 8, 10, 12], [4, 10], -1000.0,
