@@ -536,7 +536,7 @@ __global__ __launch_bounds__(256) void k_fft_poly(const int2 *F, const float2 *t
                                                   const BatchHdr *H)
 {
     __shared__ float2 s_tw[kTwElems];
-    __shared__ float2 s_xb[4][kXbufElems];
+    __shared__ float2 s_xb[4][kXbufElemsQ];  // transposes in quarters: fewer LDS bank conflicts
     stage_twiddles(s_tw, tw, threadIdx.x, 256);
     __syncthreads();
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -555,7 +555,7 @@ __global__ __launch_bounds__(256) void k_fft_poly(const int2 *F, const float2 *t
                     v[8 * u + k2b] = make_float2(0.f, 0.f);
                 }
             }
-        fft2048<true>(v, s_xb[w], s_tw, s_tw + kT1Elems, l);
+        fft2048<true, true>(v, s_xb[w], s_tw, s_tw + kT1Elems, l);
         float4 *dst = G + vec * kVec;
 #pragma unroll
         for (int jj = 0; jj < 16; ++jj)
@@ -632,7 +632,9 @@ __global__ __launch_bounds__(64 * kCorrWaves) void k_corr(const ReqDesc *__restr
 {
     constexpr int kCcBytes = PT * kVec * (int)sizeof(float4);
     constexpr int kTwBytes = kTwElems * (int)sizeof(float2);
-    constexpr int kXbBytes = kCorrWaves * kXbufElems * (int)sizeof(float2);
+    // the transposes go through a quarter-size buffer per wave in four rounds:
+    // measured faster than the full buffer (its paired accesses conflict in LDS)
+    constexpr int kXbBytes = kCorrWaves * kXbufElemsQ * (int)sizeof(float2);
     constexpr int kStageBytes = PT * 1024 * kStagePad * (int)sizeof(float);
     constexpr int kSmem = (kCcBytes + kTwBytes + kXbBytes) > kStageBytes ? (kCcBytes + kTwBytes + kXbBytes)
                                                                           : kStageBytes;
@@ -681,7 +683,7 @@ __global__ __launch_bounds__(64 * kCorrWaves) void k_corr(const ReqDesc *__restr
 
         if (active) {
             const float4 *gk = G + (d.vec_off + (long long)k * d.Nnc * spc + s) * kVec;
-            float2 *xb = s_xb + w * kXbufElems;
+            float2 *xb = s_xb + w * kXbufElemsQ;
             for (int b = 0; b < d.Nnc; ++b) {
                 const float4 *gp = gk + (long long)b * spc * kVec;
                 // PRN slots past n_prn hold the all-zero spectrum of row 0; they are
@@ -702,7 +704,7 @@ __global__ __launch_bounds__(64 * kCorrWaves) void k_corr(const ReqDesc *__restr
                         z[2 * jj + 1] = c_mul(make_float2(t.z, t.w), make_float2(c.z, c.w));
                     }
                     phase_barrier();
-                    ifft2048<true>(z, xb, s_tw, s_tw + kT1Elems, l);
+                    ifft2048<true, true>(z, xb, s_tw, s_tw + kT1Elems, l);
                     phase_barrier();
 #pragma unroll
                     for (int u = 0; u < 4; ++u)
