@@ -381,7 +381,10 @@ __device__ __forceinline__ void transpose_b_fwd(T (&v)[32], T *xb, int l)
 
 // Quarter-buffer variants of the four exchanges: the same permutations done
 // in four rounds through a buffer half the size (kXbufElemsQ elements per
-// wave), for kernels that trade the extra LDS round trips for occupancy.
+// wave).  Besides needing less LDS, they are faster on gfx950 than the full
+// buffer, whose exchanges the compiler turns into two-address LDS accesses
+// that conflict in the banks (measured: about one conflict cycle per LDS
+// instruction there, almost none here).
 // Exchange A splits by h (columns 64h .. 64h + 63 of the half) with row stride
 // kStrideAQ = 72 (= 8 mod 32 elements: a half-wave's 4 rows x 8 columns hit 32
 // distinct 8-byte banks); exchange B splits by the rows kl of one uu with the
