@@ -306,7 +306,10 @@ def main():
     if not args.no_other_modes and args.precision == "fp32" and not args.doppler_fd:
         out["other_modes"] = other_modes(args, G, torch, d_x, snap, srch, cells, stream)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(snap, srch, args.cpu_seconds)
+        try:
+            out["cpu_baseline"] = cpu_baseline(snap, srch, args.cpu_seconds)
+        except Exception as e:  # noqa: BLE001 -- reported in the line, not allowed to cost it
+            out["cpu_baseline"] = {"error": "%s: %s" % (type(e).__name__, e), "kind": "oracle"}
     ctx.close()
     print(json.dumps(out), flush=True)
 
@@ -324,7 +327,19 @@ def other_modes(args, G, torch, d_x, snap, srch, cells, stream):
     res = {}
     for name, prec, opts in (("fp16", "fp16", {}), ("fp16pfa", "fp16pfa", {}),
                              ("fp16pfa_doppler_fd", "fp16pfa", {"doppler_fd": 1})):
-        c = G.Context(0, precision=precision_const(G, prec))
+        # a failure here is reported in the line, not allowed to cost the line itself
+        try:
+            res[name] = _time_mode(args, G, torch, d_x, snap, srch, cells, stream, nd, N, n_prn, units,
+                                   flops_unit, prec, opts)
+        except Exception as e:  # noqa: BLE001
+            res[name] = {"error": "%s: %s" % (type(e).__name__, e)}
+    return res
+
+
+def _time_mode(args, G, torch, d_x, snap, srch, cells, stream, nd, N, n_prn, units, flops_unit, prec, opts):
+    """One precision mode on the resident snapshot (see other_modes)."""
+    c = G.Context(0, precision=precision_const(G, prec))
+    try:
         for k, v in opts.items():
             c.set(k, v)
         g = torch.empty(n_prn * nd * N, dtype=torch.float32, device="cuda")
@@ -348,14 +363,13 @@ def other_modes(args, G, torch, d_x, snap, srch, cells, stream):
         st = c.stage_times(reset=True)
         corr_ms = st["corr"][0] / max(1, st["corr"][1])
         p = pk.cpu().numpy().view(G.PEAK_DTYPE)
-        res[name] = {"ms_per_step": ms, "value": cells / (ms / 1e3), "unit": "cells/s", "dtype": DTYPE[prec],
-                     "stages_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in st.items()},
-                     "roofline": corr_roofline(prec, units * flops_unit, corr_ms,
-                                               read_traffic(CORR_KERNEL[prec][2:], args.workload) if not opts else None,
-                                               units * (N // 1023)),
-                     "detected": sorted(int(r["prn"]) for r in p if r["detected"])}
+        traffic = read_traffic(CORR_KERNEL[prec][2:], args.workload) if not opts else None
+        return {"ms_per_step": ms, "value": cells / (ms / 1e3), "unit": "cells/s", "dtype": DTYPE[prec],
+                "stages_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in st.items()},
+                "roofline": corr_roofline(prec, units * flops_unit, corr_ms, traffic, units * (N // 1023)),
+                "detected": sorted(int(r["prn"]) for r in p if r["detected"])}
+    finally:
         c.close()
-    return res
 
 
 def _cells(srch, fs_hz):
