@@ -818,7 +818,8 @@ __device__ __forceinline__ void stage_twiddles_h(hc2 *s_tw, const hc2 *tw, int t
 // Forward transforms, two polyphase vectors per wave (the low and high
 // halves).  Output: Gh[vec] in the packed storage order and the vector's
 // exponent E[vec].
-__global__ __launch_bounds__(256) void k_fft_poly_h(const int2 *F, const hc2 *tw, uint4 *Gh, int *E,
+// three waves per SIMD (167 VGPRs with a 20-byte spill): 15% faster than two
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_fft_poly_h(const int2 *F, const hc2 *tw, uint4 *Gh, int *E,
                                                     const BatchHdr *H)
 {
     __shared__ hc2 s_tw[kTwElems];
