@@ -1373,9 +1373,7 @@ __global__ __launch_bounds__(64 * kCorrWavesX) void k_corr_x(const ReqDesc *__re
                                     }
                                 }
                             pfa::f4 o[2][5];
-                            __builtin_amdgcn_s_setprio(1);
                             pfa::inverse(a1, B, o);
-                            __builtin_amdgcn_s_setprio(0);
 #pragma unroll
                             for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -1415,13 +1413,8 @@ __global__ __launch_bounds__(64 * kCorrWavesX) void k_corr_x(const ReqDesc *__re
                         stage_spectrum(spectrum(b + 1), bufs + ((b + 1) & 1) * kXBuf, l);
                         e_next = E[v0 + (long long)(b + 1) * spc];
                     }
-                    // the transform's matrix-core phase at raised wave priority, so
-                    // that the other wave of the SIMD fills it with vector work
-                    // rather than both waves meeting in the same phase
                     pfa::f4 o[2][5];
-                    __builtin_amdgcn_s_setprio(1);
                     pfa::inverse(a1, B, o);
-                    __builtin_amdgcn_s_setprio(0);
                     if (e_cur != e_ref) {
                         // Another block exponent: bring the sums to it (a power of
                         // two, exact).  A block's power is below 2^30 in its own
