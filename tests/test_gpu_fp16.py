@@ -144,6 +144,40 @@ def test_block_exponents_change_between_blocks(ctx16, seq):
     assert worst <= TOL[ctx16.prec]
 
 
+@pytest.mark.timeout(600)
+def test_block_exponents_at_full_scale_and_longest_blocks(ctx16):
+    """The longest coherent blocks (64 ms at 16.368 MHz) at the extremes of the
+    per-vector exponents: a constant of 1 (exponent 28), a full-scale constant
+    (35: the sums are scaled down by 2^-14), an all-zero block (exponent 0,
+    more than 2^30 below the largest: its zero power is dropped) and small
+    noise (24: scaled up by 2^22).  Within the mode's bound of the FP64
+    oracle, and finite."""
+    fs, Tc = 16368000, 64
+    N = fs // 1000
+    L = Tc * N
+    blocks = []
+    rng = np.random.default_rng(64)
+    for kind in ("one", "full", "zero", "noise"):
+        b = np.zeros(2 * L, np.int8)
+        if kind == "one":
+            b[:] = 1
+        elif kind == "full":
+            b[:] = 127
+        elif kind == "noise":
+            b[:] = rng.integers(-3, 4, 2 * L)
+        blocks.append(b)
+    x = np.concatenate(blocks)
+    Nnc = len(blocks)
+    snap = types.SimpleNamespace(samples=x, fmt=O.CPLX_I8, n=L * Nnc, fs_hz=fs, f_if_hz=0.0)
+    srch = synth.Search([3, 19], 0.0, 0.0, 1.0, Tc, Nnc)
+    P = O.grid_fft(x, O.CPLX_I8, fs, 0.0, srch.prns, 0.0, 1.0, 1, Tc, Nnc)
+    grid, _ = _run(ctx16, snap, srch)
+    assert np.all(np.isfinite(grid))
+    worst = grid_error(grid, P)
+    log("  %s, 64 ms blocks at the exponent extremes: max mixed error %.3e" % (NAME[ctx16.prec], worst))
+    assert worst <= TOL[ctx16.prec]
+
+
 def test_fp16_rejects_unknown_precision():
     with pytest.raises(G.GnssError) as ei:
         G.Context(0, precision=7)
