@@ -147,22 +147,28 @@ def test_block_exponents_change_between_blocks(ctx16, seq):
 @pytest.mark.timeout(600)
 def test_block_exponents_at_full_scale_and_longest_blocks(ctx16):
     """The longest coherent blocks (64 ms at 16.368 MHz) at the extremes of the
-    per-vector exponents: a constant of 1 (exponent 28), a full-scale constant
-    (35: the sums are scaled down by 2^-14), an all-zero block (exponent 0,
-    more than 2^30 below the largest: its zero power is dropped) and small
-    noise (24: scaled up by 2^22).  Within the mode's bound of the FP64
-    oracle, and finite."""
+    per-vector exponents: a constant of 1 (exponent 28), a full-scale complex
+    tone at 5 kHz, which folds coherently (35: the sums are scaled down by
+    2^-14), an all-zero block (exponent 0, more than 2^30 below the largest:
+    its zero power is dropped) and small noise (24: scaled up by 2^22).
+    Within the mode's bound of the FP64 oracle, and finite.  (A full-scale
+    constant instead of the tone puts all its power in the DC bin, where the
+    code spectrum is +-1 against ~32 elsewhere, so its FP16 rounding is about
+    1.6% relative: that input tests the code spectrum's precision, not the
+    block scaling.)"""
     fs, Tc = 16368000, 64
     N = fs // 1000
     L = Tc * N
     blocks = []
     rng = np.random.default_rng(64)
-    for kind in ("one", "full", "zero", "noise"):
+    ph = 2 * np.pi * 5000.0 * np.arange(L) / fs
+    for kind in ("one", "tone", "zero", "noise"):
         b = np.zeros(2 * L, np.int8)
         if kind == "one":
             b[:] = 1
-        elif kind == "full":
-            b[:] = 127
+        elif kind == "tone":
+            b[0::2] = np.round(127 * np.cos(ph)).astype(np.int8)
+            b[1::2] = np.round(127 * np.sin(ph)).astype(np.int8)
         elif kind == "noise":
             b[:] = rng.integers(-3, 4, 2 * L)
         blocks.append(b)
