@@ -123,9 +123,13 @@ int gnss_acquire(const void *samples, int32_t fmt, size_t n, double fs, double f
  * the context uses it.  Errors: GNSS_EINVAL (unknown precision or device),
  * GNSS_ENOMEM, GNSS_EDEVICE. */
 int gnss_ctx_create(gnss_ctx **out, int device, size_t hbm_budget_bytes, int precision);
+/* Waits for the context's work, stops its serving thread (unfinished tickets
+ * are dropped) and frees its tables and workspaces; NULL is a no-op. */
 void gnss_ctx_destroy(gnss_ctx *ctx);
 
-/* Context options: "threshold" (detection ratio, > 0), "hbm_budget" (bytes,
+/* Context options (the search parameters of Sec. 3's acquisition channel
+ * that the paper leaves open, the serving knobs of the cloud setting of
+ * Sec. 1, and test hooks): "threshold" (detection ratio, > 0), "hbm_budget" (bytes,
  * 0 = unlimited; device memory of tables and workspaces), "profile" (1:
  * record per-stage HIP events, see gnss_stage_times; 0: off), "corr_ptile"
  * (PRNs per correlation workgroup: 2 or 4; 0 = autotuned, default 2),
@@ -154,13 +158,19 @@ void gnss_ctx_destroy(gnss_ctx *ctx);
  * that a data-bit flip between them does not cancel the signal; needs an even
  * N_noncoh, else GNSS_ENOTSUP at search time; 0, the default: plain sum),
  * "max_slots" (requests per
- * served batch, 1..4096).
+ * served batch, 1..4096), "fault_alloc" / "fault_copy" / "fault_launch" (n >= 1:
+ * the n-th following device allocation, host/device copy or batch launch of
+ * the context fails on the host before anything is enqueued, reporting
+ * GNSS_ENOMEM, GNSS_EDEVICE and GNSS_EDEVICE; 0: off; for tests of the error
+ * paths).
  * Errors: GNSS_EINVAL. */
 int gnss_ctx_set(gnss_ctx *ctx, const char *key, double value);
 
 /* Device bytes the context's workspace needs for a request in FP32 (an
- * upper bound for FP16, whose spectra take half the space); does not
- * allocate.  Errors: as gnss_acquire's argument checks. */
+ * upper bound for FP16, whose spectra take half the space): the block and
+ * spectrum buffers of the device-resident pipeline (Sec. 5 keeps
+ * intermediates on the GPU); does not allocate.  Errors: as gnss_acquire's
+ * argument checks. */
 int gnss_workspace_bytes(const gnss_request *req, size_t *bytes);
 
 /* Acquisition on device buffers (Sec. 3, Fig. 2; the whole coherent
@@ -190,6 +200,8 @@ int gnss_acquire_batch_device(gnss_ctx *ctx, const gnss_request *reqs, int32_t n
 typedef struct gnss_graph gnss_graph;
 int gnss_graph_create(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, gnss_graph **out);
 int gnss_graph_launch(gnss_graph *graph, void *stream);
+/* Waits for the device, then frees the graph and its workspace; NULL is a
+ * no-op. */
 void gnss_graph_destroy(gnss_graph *graph);
 
 /* Picks the correlation kernel's PRN tile (2 or 4) and schedule (1:
@@ -223,13 +235,19 @@ typedef struct gnss_ticket_info {
  * slot's share of the budget. */
 int gnss_submit(gnss_ctx *ctx, const gnss_request *req, uint64_t *ticket);
 
-/* Non-blocking completion check.  When *done is 1 the outputs are written,
- * info (nullable) is filled, the ticket is released and the return value is
- * the request's status. */
+/* Non-blocking completion check of a submitted request (the cloud client's
+ * view of its upload, Sec. 1; queued and running times give the per-request
+ * latency behind the paper's throughput measure, Sec. 4).  When *done is 1
+ * the outputs are written, info (nullable) is filled, the ticket is released
+ * and the return value is the request's status (a device error fails only
+ * the tickets of the batch it occurred in).  Errors: GNSS_EINVAL (null
+ * argument, unknown ticket). */
 int gnss_poll(gnss_ctx *ctx, uint64_t ticket, int *done, gnss_ticket_info *info);
 
-/* Blocks until the ticket is done (timeout_s < 0: no limit); then as
- * gnss_poll with *done = 1.  GNSS_EBUSY on timeout (ticket kept). */
+/* Blocks until a submitted request is done (Sec. 1's cloud service; timeout_s
+ * < 0: no limit); then as gnss_poll with *done = 1.  Errors: GNSS_EINVAL
+ * (null context, unknown ticket), GNSS_EBUSY on timeout (ticket kept), or the
+ * request's own status. */
 int gnss_wait(gnss_ctx *ctx, uint64_t ticket, double timeout_s, gnss_ticket_info *info);
 
 /* ---- stage entry points (device pointers, enqueued on `stream`, a
@@ -253,8 +271,25 @@ int gnss_nco_lut(gnss_ctx *ctx, int16_t *d_cos, int16_t *d_sin, void *stream);
 /* First mixing stage + coherent folding (Sec. 3 Fig. 2; block processing,
  * Sec. 4): d_out[((k*N_noncoh + b)*N + m)*2 + {0,1}] = re/im of
  * sum_{t<T} y_k[(b*T + t)*N + m], exact int32.  Other fields of req as for
- * gnss_acquire_device (outputs ignored). */
+ * gnss_acquire_device (outputs ignored).  A standalone kernel; the search
+ * itself runs the stage of gnss_box_fold.  Calls on one context must not
+ * overlap.  Errors: GNSS_EINVAL, GNSS_ENOTSUP (fs), GNSS_ENOMEM,
+ * GNSS_EDEVICE. */
 int gnss_wipe_fold(gnss_ctx *ctx, const gnss_request *req, int32_t *d_out, void *stream);
+
+/* The search's own first stage, run alone with the kernel and launch the
+ * search uses: carrier NCO and first mixing stage (Sec. 3 Fig. 2), coherent
+ * fold of each block (block processing, Sec. 4), then the one-chip boxcar and
+ * polyphase split that turn the length-N correlation into spc length-1023
+ * ones.  With f_kb the folded block of gnss_wipe_fold, delayed circularly by
+ * the code-Doppler shift d_kb when the context's "code_doppler" option is 1
+ * (else d_kb = 0), F[n] = sum_{t<spc} f_kb[(n + t - d_kb) mod N] and
+ *   d_out[(((k*N_noncoh + b)*spc + s)*1024 + m)*2 + {0,1}] = re/im of F[spc*m + s]
+ * for m < 1023, and 0 at m = 1023; exact int32.  d_out is device memory of
+ * n_dopp*N_noncoh*spc*1024*2 int32 owned by the caller; other fields of req as
+ * for gnss_acquire_device (outputs ignored; "doppler_fd" does not apply).
+ * Calls on one context must not overlap.  Errors: as gnss_wipe_fold. */
+int gnss_box_fold(gnss_ctx *ctx, const gnss_request *req, int32_t *d_out, void *stream);
 
 /* Batched 2048-point complex FFT (the FFT/IFFT stages of Fig. 2), natural
  * order in and out, interleaved float re/im, forward exp(-2 pi i nk/2048) or
@@ -338,7 +373,9 @@ int gnss_track_device(gnss_ctx *ctx, const gnss_track_request *reqs, int32_t n_r
 #define GNSS_STAGE_DETECT 3     /* column max, peaks, refinement                */
 #define GNSS_N_STAGES 4
 
-/* While the context's "profile" option is 1, every search records HIP events
+/* Where the time goes, stage by stage (the paper's per-stage accounting of
+ * its receiver, Secs. 3-4: mixing, FFT stages, correlation, detection).
+ * While the context's "profile" option is 1, every search records HIP events
  * on its stream around each stage.  This call waits for the recorded events
  * and adds their elapsed milliseconds to ms_total[i] and the number of timed
  * launches to launches[i] (host arrays of n >= GNSS_N_STAGES entries, set to
@@ -347,6 +384,9 @@ int gnss_track_device(gnss_ctx *ctx, const gnss_track_request *reqs, int32_t n_r
 int gnss_stage_times(gnss_ctx *ctx, double *ms_total, int64_t *launches, int32_t n, int32_t reset);
 
 /* ---- errors ------------------------------------------------------------ */
+/* Text of a GNSS_E* code (static storage), and the calling thread's detail
+ * message of its last failed call (valid until that thread's next call).
+ * Plumbing of this library: the paper defines no error reporting. */
 const char *gnss_strerror(int code);
 const char *gnss_last_error(void);
 

@@ -38,7 +38,7 @@ EXPORTED = [
     "gnss_nco_lut", "gnss_wipe_fold", "gnss_fft2048", "gnss_peaks", "gnss_stage_times",
     "gnss_strerror", "gnss_last_error", "gnss_acquire_batch_device", "gnss_graph_create",
     "gnss_graph_launch", "gnss_graph_destroy", "gnss_autotune", "gnss_submit", "gnss_poll",
-    "gnss_wait", "gnss_track", "gnss_track_device", "gnss_dft1023",
+    "gnss_wait", "gnss_track", "gnss_track_device", "gnss_dft1023", "gnss_box_fold",
 ]
 
 GNSS_STAGE_WIPE_FOLD = 0
@@ -117,6 +117,7 @@ def _load() -> ctypes.CDLL:
         "gnss_code_replica": [vp, pi32, i32, dbl, sz, vp, vp],
         "gnss_nco_lut": [vp, vp, vp, vp],
         "gnss_wipe_fold": [vp, ctypes.POINTER(gnss_request), vp, vp],
+        "gnss_box_fold": [vp, ctypes.POINTER(gnss_request), vp, vp],
         "gnss_fft2048": [vp, vp, vp, i32, i32, vp],
         "gnss_dft1023": [vp, vp, vp, i32, i32, vp],
         "gnss_peaks": [vp, vp, pi32, i32, i32, i32, i32, dbl, dbl, vp, vp],
@@ -387,6 +388,9 @@ class Context:
 
     def wipe_fold(self, req: gnss_request, d_out: int, stream=None):
         _check(_lib.gnss_wipe_fold(self.handle, ctypes.byref(req), d_out, _stream_ptr(stream)))
+
+    def box_fold(self, req: gnss_request, d_out: int, stream=None):
+        _check(_lib.gnss_box_fold(self.handle, ctypes.byref(req), d_out, _stream_ptr(stream)))
 
     def fft2048(self, d_in: int, d_out: int, batch: int, inverse: bool, stream=None):
         _check(_lib.gnss_fft2048(self.handle, d_in, d_out, int(batch), 1 if inverse else 0,

@@ -51,17 +51,53 @@ size_t sample_bytes(int fmt, size_t n)
 // ---------------------------------------------------------------------------
 // device memory under the context's HBM budget
 // ---------------------------------------------------------------------------
-int ensure(gnss_ctx *c, DevBuf &b, size_t bytes)
+bool inject(std::atomic<int> &countdown)
+{
+    int v = countdown.load();
+    while (v > 0 && !countdown.compare_exchange_weak(v, v - 1)) {
+    }
+    return v == 1;
+}
+
+int copy_async(gnss_ctx *c, void *dst, const void *src, size_t bytes, hipMemcpyKind kind, hipStream_t s)
+{
+    if (inject(c->fault_copy)) return set_err(GNSS_EDEVICE, "injected copy failure (%zu bytes)", bytes);
+    HIP_TRY(hipMemcpyAsync(dst, src, bytes, kind, s));
+    return GNSS_OK;
+}
+
+int mark_use(Workspace &w, hipStream_t s)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &st));
+    if (st != hipStreamCaptureStatusNone) return GNSS_OK;
+    if (!w.use_ev) HIP_TRY(hipEventCreateWithFlags(&w.use_ev, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(w.use_ev, s));
+    w.used = true;
+    return GNSS_OK;
+}
+
+int ensure_ws(gnss_ctx *c, Workspace &w, DevBuf &b, size_t bytes)
+{
+    return ensure(c, b, bytes, w.used ? w.use_ev : nullptr);
+}
+
+int ensure(gnss_ctx *c, DevBuf &b, size_t bytes, hipEvent_t wait_ev)
 {
     if (bytes <= b.cap) return GNSS_OK;
+    if (inject(c->fault_alloc)) return set_err(GNSS_ENOMEM, "injected allocation failure (%zu bytes)", bytes);
     std::lock_guard<std::mutex> lk(c->mem_mu);
     const size_t in_use = c->dev_bytes - b.cap;
     if (c->budget && in_use + bytes > c->budget)
         return set_err(GNSS_ENOMEM, "device buffer of %zu bytes exceeds the HBM budget (%zu of %zu in use)",
                        bytes, in_use, c->budget);
     if (b.p) {
-        // the old buffer may still be in use by enqueued work
-        (void)hipDeviceSynchronize();
+        // the old buffer may still be in use by enqueued work: wait for its
+        // last use, not for the rest of the device
+        if (wait_ev) {
+            hipError_t w = hipEventSynchronize(wait_ev);
+            if (w != hipSuccess) return set_err(GNSS_EDEVICE, "hipEventSynchronize: %s", hipGetErrorString(w));
+        }
         hipError_t e = hipFree(b.p);
         c->dev_bytes -= b.cap;
         b.p = nullptr;
@@ -96,13 +132,17 @@ void release(gnss_ctx *c, DevBuf &b)
 void release_ws(gnss_ctx *c, Workspace &w)
 {
     if (w.stage_ev) (void)hipEventSynchronize(w.stage_ev);
+    if (w.use_ev && w.used) (void)hipEventSynchronize(w.use_ev);
     for (DevBuf *b : {&w.F, &w.G, &w.Q, &w.K, &w.part, &w.grid, &w.meta, &w.samples, &w.peaks, &w.tmeta, &w.tout})
         release(c, *b);
     if (w.h_stage) (void)hipHostFree(w.h_stage);
     if (w.stage_ev) (void)hipEventDestroy(w.stage_ev);
+    if (w.use_ev) (void)hipEventDestroy(w.use_ev);
     w.h_stage = nullptr;
     w.h_stage_cap = 0;
     w.stage_ev = nullptr;
+    w.use_ev = nullptr;
+    w.used = false;
 }
 
 // ---------------------------------------------------------------------------
@@ -191,8 +231,37 @@ static bool fd_params(const gnss::Plan &p, int &PTc, int &A, int &kappa)
     return false;
 }
 
+// D_k = (uint32)(int64)llround((f_if + f_k) * 2^32 / fs), f_k = lo + k*step,
+// each operation rounded once in IEEE double as written (no contraction):
+// the carrier NCO of Fig. 2 as a 32-bit phase accumulator.
+uint32_t nco_step(double fs, double f_if, double lo, double step, int k)
+{
+#pragma clang fp contract(off)
+    const double fk = lo + (double)k * step;
+    const double f = f_if + fk;
+    const double x = f * 4294967296.0 / fs;
+    return (uint32_t)(long long)llround(x);
+}
+
+// Code-Doppler drift of block b at Doppler bin k in samples, reduced to
+// [0, N): llround(b Tc N f_k / f_L1), f_L1 = 1575.42 MHz (1540 chip rates),
+// in IEEE double as written.  Delaying the folded block by it circularly
+// shifts the block's correlation by the same number of lags.
+int32_t code_shift(long long b, int Tc, int N, double lo, double step, int k)
+{
+#pragma clang fp contract(off)
+    const double fk = lo + (double)k * step;
+    const double x = (double)(b * (long long)Tc * (long long)N) * fk / 1575420000.0;
+    long long v = (long long)llround(x) % N;
+    return (int32_t)(v < 0 ? v + N : v);
+}
+
+// Largest code-Doppler shift table per request ([n_dopp][N_noncoh] int32),
+// copied to the device with every batch.
+static constexpr long long kMaxShiftTable = 1LL << 22;
+
 void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int corr_pt,
-                 float threshold, int precision, int doppler_fd, BatchHost &B)
+                 float threshold, int precision, int doppler_fd, int code_doppler, BatchHost &B)
 {
     const int corr_w = precision == GNSS_FP16       ? gnss::kCorrWavesH
                        : precision == GNSS_FP16_PFA ? gnss::kCorrWavesX
@@ -202,6 +271,11 @@ void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int c
     B.grid_off.assign(n, -1);
     B.fd = doppler_fd;
     B.fd_bad = -1;
+    B.dk.clear();
+    B.dk_off.assign(n, 0);
+    B.cshift.clear();
+    B.cshift_off.assign(n, -1);
+    B.cshift_bad = -1;
     long long tot[gnss::kNumStages] = {};
     long long vec = 0, qk = 0, part = 0, grid_int = 0, fd_f2 = 0;
     for (int r = 0; r < n; ++r) {
@@ -213,8 +287,6 @@ void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int c
         d.vec_off = vec;
         d.qk_off = qk;
         d.part_off = part;
-        d.fs = (double)p.fs_hz;
-        d.f_if = p.f_if;
         d.lo = p.lo;
         d.step = p.step;
         d.fmt = p.fmt;
@@ -229,6 +301,17 @@ void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int c
         d.n_tau_blk = (int)cdiv(p.N, gnss::kPeakThreads);
         d.threshold = threshold;
         for (int i = 0; i < gnss::kMaxList; ++i) d.prns[i] = p.prns.v[i];
+        B.dk_off[r] = (long long)B.dk.size();
+        for (int k = 0; k < p.n_dopp; ++k) B.dk.push_back(nco_step((double)p.fs_hz, p.f_if, p.lo, p.step, k));
+        if (code_doppler) {
+            if ((long long)p.n_dopp * p.Nnc > kMaxShiftTable) {
+                if (B.cshift_bad < 0) B.cshift_bad = r;
+            } else {
+                B.cshift_off[r] = (long long)B.cshift.size();
+                for (int k = 0; k < p.n_dopp; ++k)
+                    for (int b = 0; b < p.Nnc; ++b) B.cshift.push_back(code_shift(b, p.Tc, p.N, p.lo, p.step, k));
+            }
+        }
         if (!d.grid) {
             B.grid_off[r] = grid_int;
             grid_int += p.grid_elems();
@@ -242,7 +325,12 @@ void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int c
                 d.fd_A = A;
                 d.fd_kappa = kappa;
                 d.fd_off = fd_f2;
-                d.fd_fbase = p.f_if + p.lo;
+                // cycles per sample of the removed carrier, reduced to [0, 1) and
+                // scaled to 2^64 (exact: the fraction has at most 53 bits)
+                const double cyc = (p.f_if + p.lo) / (double)p.fs_hz;
+                double fr = cyc - std::floor(cyc);
+                if (!(fr >= 0.0 && fr < 1.0)) fr = 0.0;
+                d.fd_dphase = (unsigned long long)ldexpl((long double)fr, 64);
                 // inverse residue map of the A x 1023 prime-factor DFT
                 long long inv1 = 0, inv2 = 0;
                 for (long long t = 0; t < A; ++t)
@@ -283,36 +371,48 @@ void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int c
     B.G_bytes = gnss::g_bytes(vec, precision);
     B.Q_bytes = (size_t)qk * sizeof(float);
     B.K_bytes = (size_t)qk * sizeof(int32_t);
-    B.part_bytes = (size_t)part * sizeof(double);
+    B.part_bytes = (size_t)part * sizeof(float);
     B.grid_bytes = (size_t)grid_int * sizeof(float);
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t meta_bytes(int n)
+// Metadata layout: header, prefix sums, descriptors, NCO steps, shift tables.
+struct MetaLayout {
+    size_t pre, desc, dk, cshift, total;
+};
+
+static MetaLayout meta_layout(const BatchHost &B)
 {
-    return align256(sizeof(gnss::BatchHdr)) + align256((size_t)gnss::kNumStages * (n + 1) * sizeof(long long)) +
-           align256((size_t)n * sizeof(gnss::ReqDesc));
+    MetaLayout m;
+    m.pre = align256(sizeof(gnss::BatchHdr));
+    m.desc = m.pre + align256((size_t)gnss::kNumStages * (B.n + 1) * sizeof(long long));
+    m.dk = m.desc + align256((size_t)B.n * sizeof(gnss::ReqDesc));
+    m.cshift = m.dk + align256(B.dk.size() * sizeof(uint32_t));
+    m.total = m.cshift + align256(B.cshift.size() * sizeof(int32_t));
+    return m;
 }
+
+size_t meta_bytes(const BatchHost &B) { return meta_layout(B).total; }
 
 size_t batch_device_bytes(const BatchHost &B)
 {
-    return B.F_bytes + B.G_bytes + B.Q_bytes + B.K_bytes + B.part_bytes + B.grid_bytes + meta_bytes(B.n);
+    return B.F_bytes + B.G_bytes + B.Q_bytes + B.K_bytes + B.part_bytes + B.grid_bytes + meta_bytes(B);
 }
 
 // Allocates the workspace of a laid-out batch, fills in internal grid
 // pointers, writes the metadata into pinned memory and enqueues its copy to
 // the device on stream s.  Returns the kernels' view of the batch in L.
-int stage_batch(gnss_ctx *c, Workspace &w, BatchHost &B, hipStream_t s, gnss::Launch &L)
+int stage_batch(gnss_ctx *c, Workspace &w, BatchHost &B, hipStream_t s, gnss::Launch &L, bool meta_only)
 {
-    if (c->nav_pairs) {
+    if (c->nav_pairs && !meta_only) {
         if (c->precision != GNSS_FP16_PFA)
             return set_err(GNSS_ENOTSUP, "nav_pairs needs a GNSS_FP16_PFA context");
         for (int r = 0; r < B.n; ++r)
             if (B.d[r].Nnc % 2)
                 return set_err(GNSS_ENOTSUP, "nav_pairs: request %d has an odd N_noncoh (%d)", r, B.d[r].Nnc);
     }
-    if (B.fd) {
+    if (B.fd && !meta_only) {
         if (c->precision != GNSS_FP16_PFA)
             return set_err(GNSS_ENOTSUP, "doppler_fd needs a GNSS_FP16_PFA context");
         if (c->code_doppler)
@@ -323,17 +423,27 @@ int stage_batch(gnss_ctx *c, Workspace &w, BatchHost &B, hipStream_t s, gnss::La
                            "bins for P in {1, 2, 4}, with P T_coh spc a power of two <= 256",
                            B.fd_bad);
     }
+    if (B.cshift_bad >= 0)
+        return set_err(GNSS_ENOTSUP, "code_doppler: request %d has more than %lld (Doppler bin, block) pairs",
+                       B.cshift_bad, kMaxShiftTable);
     int rc;
-    const size_t mb = meta_bytes(B.n);
-    if ((rc = ensure(c, w.F, std::max<size_t>(B.F_bytes, 1))) || (rc = ensure(c, w.G, std::max<size_t>(B.G_bytes, 1))) ||
-        (rc = ensure(c, w.Q, std::max<size_t>(B.Q_bytes, 1))) || (rc = ensure(c, w.K, std::max<size_t>(B.K_bytes, 1))) ||
-        (rc = ensure(c, w.part, std::max<size_t>(B.part_bytes, 1))) ||
-        (rc = ensure(c, w.grid, std::max<size_t>(B.grid_bytes, 1))) || (rc = ensure(c, w.meta, mb)))
+    const MetaLayout ml = meta_layout(B);
+    const size_t mb = ml.total;
+    if (!meta_only &&
+        ((rc = ensure_ws(c, w, w.F, std::max<size_t>(B.F_bytes, 1))) ||
+         (rc = ensure_ws(c, w, w.G, std::max<size_t>(B.G_bytes, 1))) ||
+         (rc = ensure_ws(c, w, w.Q, std::max<size_t>(B.Q_bytes, 1))) ||
+         (rc = ensure_ws(c, w, w.K, std::max<size_t>(B.K_bytes, 1))) ||
+         (rc = ensure_ws(c, w, w.part, std::max<size_t>(B.part_bytes, 1))) ||
+         (rc = ensure_ws(c, w, w.grid, std::max<size_t>(B.grid_bytes, 1)))))
         return rc;
+    if ((rc = ensure_ws(c, w, w.meta, mb))) return rc;
+    unsigned char *dm = (unsigned char *)w.meta.p;
     for (int r = 0; r < B.n; ++r) {
         if (B.grid_off[r] >= 0) B.d[r].grid = (float *)w.grid.p + B.grid_off[r];
-        B.d[r].code_doppler = c->code_doppler;
         B.d[r].nav_pairs = c->nav_pairs;
+        B.d[r].dk = (const uint32_t *)(dm + ml.dk) + B.dk_off[r];
+        B.d[r].cshift = B.cshift_off[r] >= 0 ? (const int32_t *)(dm + ml.cshift) + B.cshift_off[r] : nullptr;
     }
     // pinned staging: wait until the previous copy out of it has finished
     if (w.stage_ev) HIP_TRY(hipEventSynchronize(w.stage_ev));
@@ -351,17 +461,16 @@ int stage_batch(gnss_ctx *c, Workspace &w, BatchHost &B, hipStream_t s, gnss::La
     hdr.n_req = B.n;
     hdr.corr_pt = B.corr_pt;
     for (int st = 0; st < gnss::kNumStages; ++st) hdr.total[st] = B.total[st];
-    const size_t off_pre = align256(sizeof(gnss::BatchHdr));
-    const size_t off_desc = off_pre + align256((size_t)gnss::kNumStages * (B.n + 1) * sizeof(long long));
     memcpy(h, &hdr, sizeof hdr);
-    memcpy(h + off_pre, B.pre.data(), B.pre.size() * sizeof(long long));
-    memcpy(h + off_desc, B.d.data(), (size_t)B.n * sizeof(gnss::ReqDesc));
+    memcpy(h + ml.pre, B.pre.data(), B.pre.size() * sizeof(long long));
+    memcpy(h + ml.desc, B.d.data(), (size_t)B.n * sizeof(gnss::ReqDesc));
+    if (!B.dk.empty()) memcpy(h + ml.dk, B.dk.data(), B.dk.size() * sizeof(uint32_t));
+    if (!B.cshift.empty()) memcpy(h + ml.cshift, B.cshift.data(), B.cshift.size() * sizeof(int32_t));
     HIP_TRY(hipMemcpyAsync(w.meta.p, h, mb, hipMemcpyHostToDevice, s));
     HIP_TRY(hipEventRecord(w.stage_ev, s));
-    unsigned char *dm = (unsigned char *)w.meta.p;
     L.hdr = (gnss::BatchHdr *)dm;
-    L.pre = (const long long *)(dm + off_pre);
-    L.reqs = (const gnss::ReqDesc *)(dm + off_desc);
+    L.pre = (const long long *)(dm + ml.pre);
+    L.reqs = (const gnss::ReqDesc *)(dm + ml.desc);
     L.n_req = B.n;
     L.corr_pt = B.corr_pt;
     L.persistent = persistent_for(c, B);
@@ -411,11 +520,16 @@ int launch(gnss_ctx *c, Workspace &w, const gnss::Launch &L, hipStream_t s, bool
         for (auto &e : ev)
             if ((rc = take_event(c, &e))) return rc;
     }
+    if (inject(c->fault_launch)) {
+        if (prof)
+            for (hipEvent_t e : ev) c->event_pool.push_back(e);
+        return set_err(GNSS_EDEVICE, "injected launch failure");
+    }
     const gnss::Tables T{c->d_lut, c->d_tw, c->d_cs, c->d_tw_h, c->d_cs_h, c->d_frags_x, c->d_cs_x, c->cs_exp};
-    HIP_TRY(gnss::launch_batch(L, T, (int2 *)w.F.p, w.G.p, (float *)w.Q.p, (int32_t *)w.K.p, (double *)w.part.p,
+    HIP_TRY(gnss::launch_batch(L, T, (int2 *)w.F.p, w.G.p, (float *)w.Q.p, (int32_t *)w.K.p, (float *)w.part.p,
                                c->n_cu, s, prof ? ev.data() : nullptr));
     if (prof) c->pending.push_back(ev);
-    return GNSS_OK;
+    return mark_use(w, s);
 }
 
 int plan_all(const gnss_request *reqs, int n, std::vector<gnss::Plan> &plans)
@@ -678,6 +792,13 @@ int gnss_ctx_set(gnss_ctx *ctx, const char *key, double value)
         ctx->code_doppler = (int)value;
         return GNSS_OK;
     }
+    if (!strcmp(key, "fault_alloc") || !strcmp(key, "fault_copy") || !strcmp(key, "fault_launch")) {
+        if (!(value >= 0.0) || value > 1e9 || value != floor(value))
+            return set_err(GNSS_EINVAL, "%s must be a whole number >= 0", key);
+        std::atomic<int> &a = key[6] == 'a' ? ctx->fault_alloc : key[6] == 'c' ? ctx->fault_copy : ctx->fault_launch;
+        a.store((int)value);
+        return GNSS_OK;
+    }
     if (!strcmp(key, "max_slots")) {
         if (!(value >= 1.0) || value > 4096.0) return set_err(GNSS_EINVAL, "max_slots outside [1, 4096]");
         ctx->max_slots = (int)value;
@@ -714,7 +835,7 @@ int gnss_workspace_bytes(const gnss_request *req, size_t *bytes)
     BatchHost B;
     gnss_request r = *req;
     r.out_grid = nullptr;
-    build_batch(&p, &r, 1, 2, 2.5f, GNSS_FP32, 0, B);  // FP32 needs the most
+    build_batch(&p, &r, 1, 2, 2.5f, GNSS_FP32, 0, 1, B);  // FP32 and the shift table: the most
     *bytes = batch_device_bytes(B) + sample_bytes(p.fmt, (size_t)p.n_samples) + (size_t)p.n_prn * sizeof(gnss_peak);
     return GNSS_OK;
 }
@@ -730,7 +851,7 @@ int gnss_acquire_batch_device(gnss_ctx *ctx, const gnss_request *reqs, int32_t n
     if (g.rc) return g.rc;
     hipStream_t s = (hipStream_t)stream;
     BatchHost B;
-    build_batch(plans.data(), reqs, n_req, corr_ptile_for(ctx, plans.data(), n_req), ctx->threshold, ctx->precision, ctx->doppler_fd, B);
+    build_batch(plans.data(), reqs, n_req, corr_ptile_for(ctx, plans.data(), n_req), ctx->threshold, ctx->precision, ctx->doppler_fd, ctx->code_doppler, B);
     gnss::Launch L;
     if ((rc = stage_batch(ctx, ctx->ws, B, s, L))) return rc;
     return launch(ctx, ctx->ws, L, s, true);
@@ -776,23 +897,25 @@ int gnss_acquire(const void *samples, int32_t fmt, size_t n, double fs, double f
     Workspace &w = c->ws;
     const size_t sb = sample_bytes(fmt, n);
     const size_t pb = (size_t)n_prn * sizeof(gnss_peak);
-    if ((rc = ensure(c, w.samples, sb)) || (rc = ensure(c, w.peaks, pb))) return rc;
-    HIP_TRY(hipMemcpyAsync(w.samples.p, samples, sb, hipMemcpyHostToDevice, c->stream));
+    if ((rc = ensure_ws(c, w, w.samples, sb)) || (rc = ensure_ws(c, w, w.peaks, pb))) return rc;
+    if ((rc = copy_async(c, w.samples.p, samples, sb, hipMemcpyHostToDevice, c->stream))) return rc;
     gnss_request dr = r;
     dr.samples = w.samples.p;
     dr.out_grid = nullptr;  // workspace grid, copied out below
     dr.out_peaks = (gnss_peak *)w.peaks.p;
     BatchHost B;
-    build_batch(&p, &dr, 1, corr_ptile_for(c, &p, 1), c->threshold, c->precision, c->doppler_fd, B);
+    build_batch(&p, &dr, 1, corr_ptile_for(c, &p, 1), c->threshold, c->precision, c->doppler_fd, c->code_doppler, B);
     gnss::Launch L;
     if ((rc = stage_batch(c, w, B, c->stream, L)) || (rc = launch(c, w, L, c->stream, true))) {
         (void)hipStreamSynchronize(c->stream);
         return rc;
     }
-    if (out_grid)
-        HIP_TRY(hipMemcpyAsync(out_grid, B.d[0].grid, (size_t)p.grid_elems() * sizeof(float), hipMemcpyDeviceToHost,
-                               c->stream));
-    HIP_TRY(hipMemcpyAsync(out_peaks, w.peaks.p, pb, hipMemcpyDeviceToHost, c->stream));
+    if ((out_grid && (rc = copy_async(c, out_grid, B.d[0].grid, (size_t)p.grid_elems() * sizeof(float),
+                                      hipMemcpyDeviceToHost, c->stream))) ||
+        (rc = copy_async(c, out_peaks, w.peaks.p, pb, hipMemcpyDeviceToHost, c->stream))) {
+        (void)hipStreamSynchronize(c->stream);
+        return rc;
+    }
     HIP_TRY(hipStreamSynchronize(c->stream));
     return GNSS_OK;
 }
@@ -813,7 +936,7 @@ int gnss_graph_create(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, gn
     if (!gr) return set_err(GNSS_ENOMEM, "host allocation failed");
     gr->ctx = ctx;
     BatchHost B;
-    build_batch(plans.data(), reqs, n_req, corr_ptile_for(ctx, plans.data(), n_req), ctx->threshold, ctx->precision, ctx->doppler_fd, B);
+    build_batch(plans.data(), reqs, n_req, corr_ptile_for(ctx, plans.data(), n_req), ctx->threshold, ctx->precision, ctx->doppler_fd, ctx->code_doppler, B);
     gr->corr_pt = B.corr_pt;
     hipStream_t cs = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
@@ -834,7 +957,7 @@ int gnss_graph_create(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, gn
     }
     if (!rc) {
         // the metadata copy is part of the graph (pinned source, contents fixed)
-        const size_t mb = meta_bytes(B.n);
+        const size_t mb = meta_bytes(B);
         e = hipMemcpyAsync(gr->ws.meta.p, gr->ws.h_stage, mb, hipMemcpyHostToDevice, cs);
         int rc2 = e == hipSuccess ? launch(ctx, gr->ws, L, cs, false)
                                   : set_err(GNSS_EDEVICE, "hipMemcpyAsync: %s", hipGetErrorString(e));
@@ -924,16 +1047,49 @@ int gnss_nco_lut(gnss_ctx *ctx, int16_t *d_cos, int16_t *d_sin, void *stream)
     return GNSS_OK;
 }
 
+// A one-request batch whose metadata (descriptor and NCO steps) is staged in
+// the context's workspace for a stage entry point; no search workspace.
+static int stage_one(gnss_ctx *ctx, const gnss_request *req, gnss::Plan &p, hipStream_t s, BatchHost &B,
+                     gnss::Launch &L)
+{
+    int rc = make_plan(req, p, false);
+    if (rc) return rc;
+    gnss_request r = *req;
+    r.out_grid = nullptr;
+    build_batch(&p, &r, 1, 2, ctx->threshold, ctx->precision, 0, ctx->code_doppler, B);
+    return stage_batch(ctx, ctx->ws, B, s, L, true);
+}
+
 int gnss_wipe_fold(gnss_ctx *ctx, const gnss_request *req, int32_t *d_out, void *stream)
 {
     if (!ctx || !d_out) return set_err(GNSS_EINVAL, "null argument");
-    gnss::Plan p;
-    int rc = make_plan(req, p, false);
-    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
     if (g.rc) return g.rc;
-    HIP_TRY(gnss::launch_wipe_fold(req->samples, p, ctx->d_lut, d_out, (hipStream_t)stream));
-    return GNSS_OK;
+    gnss::Plan p;
+    BatchHost B;
+    gnss::Launch L;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = stage_one(ctx, req, p, s, B, L);
+    if (rc) return rc;
+    HIP_TRY(gnss::launch_wipe_fold(L, p, ctx->d_lut, d_out, s));
+    return mark_use(ctx->ws, s);
+}
+
+int gnss_box_fold(gnss_ctx *ctx, const gnss_request *req, int32_t *d_out, void *stream)
+{
+    if (!ctx || !d_out) return set_err(GNSS_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    if (g.rc) return g.rc;
+    gnss::Plan p;
+    BatchHost B;
+    gnss::Launch L;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = stage_one(ctx, req, p, s, B, L);
+    if (rc) return rc;
+    HIP_TRY(gnss::launch_box(L, ctx->d_lut, (int2 *)d_out, ctx->n_cu, s));
+    return mark_use(ctx->ws, s);
 }
 
 int gnss_fft2048(gnss_ctx *ctx, const float *d_in, float *d_out, int32_t batch, int32_t inverse, void *stream)
@@ -991,6 +1147,8 @@ int gnss_peaks(gnss_ctx *ctx, const float *d_grid, const int32_t *prn_list, int3
     d.threshold = ctx->threshold;
     for (int i = 0; i < gnss::kMaxList; ++i) d.prns[i] = i < n_prn ? prn_list[i] : 0;
     B.grid_off.assign(1, -1);
+    B.dk_off.assign(1, 0);         // no NCO steps or shift tables: detection only
+    B.cshift_off.assign(1, -1);
     const long long cnt[gnss::kNumStages] = {0, 0, 0, (long long)n_prn * d.n_tau_blk, n_prn};
     B.pre.assign((size_t)gnss::kNumStages * 2, 0);
     for (int st = 0; st < gnss::kNumStages; ++st) {
@@ -1000,7 +1158,7 @@ int gnss_peaks(gnss_ctx *ctx, const float *d_grid, const int32_t *prn_list, int3
     B.F_bytes = B.G_bytes = B.grid_bytes = 0;
     B.Q_bytes = (size_t)n_prn * N * sizeof(float);
     B.K_bytes = (size_t)n_prn * N * sizeof(int32_t);
-    B.part_bytes = (size_t)n_prn * d.n_tau_blk * sizeof(double);
+    B.part_bytes = (size_t)n_prn * d.n_tau_blk * sizeof(float);
     gnss::Launch L;
     int rc = stage_batch(ctx, ctx->ws, B, (hipStream_t)stream, L);
     if (rc) return rc;

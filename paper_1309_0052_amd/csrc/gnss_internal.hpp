@@ -90,16 +90,21 @@ struct ReqDesc {
     const void *samples;
     float *grid;          // [n_prn][n_dopp][N]
     gnss_peak *peaks;     // [n_prn]
+    // Carrier NCO steps D_k, one per Doppler bin, and (option code_doppler)
+    // the code-Doppler lag shift of every (bin, block), [n_dopp][Nnc] in
+    // [0, N): both computed on the host in IEEE double as written, so the
+    // kernels do no FP64 arithmetic for them
+    const uint32_t *dk;
+    const int32_t *cshift;  // null without code_doppler
     long long vec_off;    // first polyphase vector of the request in F and G
     long long qk_off;     // offset of the request in Q and K (n_prn * N)
     long long part_off;   // offset in the partial sums (n_prn * n_tau_blk)
-    double fs, f_if, lo, step;
+    double lo, step;      // Doppler grid, for the FP64 refinement only
     int fmt, N, spc, n_dopp, Tc, Nnc, n_prn;
     int n_items;          // (Doppler, phase) items = n_dopp * spc
     int n_ptiles;         // PRN tiles of the correlation kernel
     int n_tau_blk;        // 256-lag blocks of the detection kernels
     float threshold;
-    int code_doppler;     // 1: shift each block's lags by its code-Doppler drift
     int nav_pairs;        // 1: blocks combined in pairs, max over the relative sign (navigation bit)
     // frequency-domain Doppler (exact-length contexts, option doppler_fd):
     // one zero-padded DFT of length fd_A * 1023 per block serves every bin
@@ -110,7 +115,10 @@ struct ReqDesc {
     long long fd_off;     // first float2 of the request's long spectra (first pass, then final)
     long long fd_crt1;    // 1023 (1023^-1 mod A): long index = (k1 crt1 + k2 crt2) mod M
     long long fd_crt2;    // A (A^-1 mod 1023)
-    double fd_fbase;      // f_if + lo, removed before the long DFT
+    // carrier f_if + lo removed before the long DFT: a 64-bit phase
+    // accumulator, cycles * 2^64 per sample (phase of in-block sample n =
+    // n * fd_dphase mod 2^64)
+    unsigned long long fd_dphase;
     int prns[kMaxList];
 };
 
@@ -149,15 +157,17 @@ struct Tables {
 };
 
 hipError_t launch_batch(const Launch &L, const Tables &T, int2 *d_F, void *d_G, float *d_Q, int32_t *d_K,
-                        double *d_part, int n_cu, hipStream_t s, hipEvent_t *marks);
+                        float *d_part, int n_cu, hipStream_t s, hipEvent_t *marks);
 int corr_ptile_valid(int pt);
 constexpr int kBoxChunk = 2048;
 constexpr int kPeakThreads = 256;   // threads of the column-max kernel (256-lag blocks)
 constexpr int kArgThreads = 1024;   // threads of the per-PRN argmax kernel
 
-// standalone wipe + fold (stage entry point)
-hipError_t launch_wipe_fold(const void *d_samples, const Plan &p, const uint32_t *d_lut,
+// standalone wipe + fold (stage entry point): request 0 of the staged batch
+hipError_t launch_wipe_fold(const Launch &L, const Plan &p, const uint32_t *d_lut,
                             int32_t *d_out /*[n_dopp][Nnc][N][2]*/, hipStream_t s);
+// the search's wipe + fold + boxcar + polyphase stage alone (stage entry point)
+hipError_t launch_box(const Launch &L, const uint32_t *d_lut, int2 *d_F, int n_cu, hipStream_t s);
 // detection on a caller's grid (stage entry point)
 size_t peak_scratch_part_elems(const Plan &p);
 

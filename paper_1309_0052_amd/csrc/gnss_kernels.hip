@@ -232,25 +232,6 @@ hipError_t launch_code_spectra(const uint8_t *d_codes, const float2 *d_tw, float
     return hipGetLastError();
 }
 
-// ===========================================================================
-// carrier NCO + first mixing stage + coherent fold
-// ===========================================================================
-struct WipeArgs {
-    int fmt;
-    int N, Tc;
-    double fs, f_if, lo, step;
-};
-
-// D_k = (uint32)(int64) llround((f_if + (lo + k*step)) * 2^32 / fs), without
-// contraction so that it rounds exactly as written.
-__device__ __forceinline__ uint32_t nco_step(double fs, double f_if, double lo, double step, int k)
-{
-    double fk = __dadd_rn(lo, __dmul_rn((double)k, step));
-    double f = __dadd_rn(f_if, fk);
-    double x = __ddiv_rn(__dmul_rn(f, 4294967296.0), fs);
-    return (uint32_t)(long long)llround(x);
-}
-
 __device__ __forceinline__ void load_sample(const void *samples, int fmt, long long n, int &xr, int &xi)
 {
     if (fmt == GNSS_CPLX_I8) {
@@ -289,26 +270,24 @@ __device__ __forceinline__ int2 wipe_fold_one(const void *samples, int fmt, int 
     return make_int2(yr, yi);
 }
 
-// Standalone wipe + fold (stage entry): out[((k*Nnc + b)*N + m)*2 + {0,1}].
-__global__ __launch_bounds__(256) void k_wipe_fold(const void *samples, const uint32_t *lut,
-                                                   WipeArgs a, int Nnc, int2 *out)
+// Standalone wipe + fold (stage entry) of request 0 of a staged batch:
+// out[((k*Nnc + b)*N + m)*2 + {0,1}].
+__global__ __launch_bounds__(256) void k_wipe_fold(const ReqDesc *__restrict__ R, const uint32_t *lut, int2 *out)
 {
     __shared__ uint32_t s_lut[1024];
     for (int i = threadIdx.x; i < 1024; i += 256) s_lut[i] = lut[i];
-    const int k = blockIdx.x / Nnc, b = blockIdx.x % Nnc;
-    const uint32_t D = nco_step(a.fs, a.f_if, a.lo, a.step, k);
+    const ReqDesc &d = R[0];
+    const int k = blockIdx.x / d.Nnc, b = blockIdx.x % d.Nnc;
+    const uint32_t D = d.dk[k];
     __syncthreads();
-    int2 *dst = out + (long long)blockIdx.x * a.N;
-    for (int m = threadIdx.x; m < a.N; m += 256)
-        dst[m] = wipe_fold_one(samples, a.fmt, a.N, a.Tc, s_lut, D, b, m);
+    int2 *dst = out + (long long)blockIdx.x * d.N;
+    for (int m = threadIdx.x; m < d.N; m += 256)
+        dst[m] = wipe_fold_one(d.samples, d.fmt, d.N, d.Tc, s_lut, D, b, m);
 }
 
-hipError_t launch_wipe_fold(const void *d_samples, const Plan &p, const uint32_t *d_lut,
-                            int32_t *d_out, hipStream_t s)
+hipError_t launch_wipe_fold(const Launch &L, const Plan &p, const uint32_t *d_lut, int32_t *d_out, hipStream_t s)
 {
-    WipeArgs a{p.fmt, p.N, p.Tc, (double)p.fs_hz, p.f_if, p.lo, p.step};
-    hipLaunchKernelGGL(k_wipe_fold, dim3(p.n_dopp * p.Nnc), dim3(256), 0, s, d_samples, d_lut, a,
-                       p.Nnc, (int2 *)d_out);
+    hipLaunchKernelGGL(k_wipe_fold, dim3(p.n_dopp * p.Nnc), dim3(256), 0, s, L.reqs, d_lut, (int2 *)d_out);
     return hipGetLastError();
 }
 
@@ -391,18 +370,6 @@ __device__ __forceinline__ long long next_item(BatchHdr *h, int stage, long long
 constexpr int kBoxRun = 8;
 __device__ __forceinline__ int bpad(int i) { return i + (i >> 3); }  // bank-conflict padding
 
-// Code-Doppler drift of block b at Doppler bin k in samples, reduced to
-// [0, N): llround(b Tc N f_k / f_L1) with f_L1 = 1575.42 MHz (1540 chip rates),
-// in IEEE double as written.  Delaying the folded block by it circularly
-// shifts the block's correlation by the same number of lags.
-__device__ __forceinline__ int code_shift(const ReqDesc &d, int k, int b)
-{
-    const double fk = __dadd_rn(d.lo, __dmul_rn((double)k, d.step));
-    const double x = __ddiv_rn(__dmul_rn((double)((long long)b * d.Tc * d.N), fk), 1575420000.0);
-    long long s = (long long)llround(x) % d.N;
-    return (int)(s < 0 ? s + d.N : s);
-}
-
 // Wipe + fold of samples n0 .. n0 + len - 1 (mod N) of block b into s_f,
 // FMT-specialised; the phase of the folded milliseconds advances by N D (mod
 // 2^32) from one to the next, and |x| <= 127, |LUT| <= 4096 make the 24-bit
@@ -482,8 +449,10 @@ __global__ __launch_bounds__(256) void k_box(const ReqDesc *__restrict__ R, Batc
         const int kb = (int)(it - pst[r]);  // (Doppler, block); < 2^31 by the plan checks
         const int k = kb / d.Nnc, b = kb - (kb / d.Nnc) * d.Nnc;
         const int N = d.N, spc = d.spc;
-        const uint32_t D = nco_step(d.fs, d.f_if, d.lo, d.step, k);
-        const int shift = d.code_doppler ? code_shift(d, k, b) : 0;
+        const uint32_t D = d.dk[k];
+        // code-Doppler drift of this (bin, block) in samples, in [0, N): delaying
+        // the folded block by it circularly shifts its correlation by as many lags
+        const int shift = d.cshift ? d.cshift[(long long)k * d.Nnc + b] : 0;
         int2 *dst = F + (d.vec_off + (long long)kb * spc) * kPolyLen;
         for (int n0 = 0; n0 < N; n0 += kBoxChunk) {
             const int cnt = min(kBoxChunk, N - n0);
@@ -1524,7 +1493,6 @@ __global__ __launch_bounds__(256) void k_fd_pass1(const ReqDesc *__restrict__ R,
         const int A = d.fd_A, b = (int)(local / A), n1 = (int)(local % A);
         const long long M = (long long)A * kCodeLen, L = (long long)d.Tc * d.N;
         const long long base = (long long)b * L;
-        const double cyc = d.fd_fbase / d.fs;  // carrier cycles per sample
         if (n1 < d.fd_PTc && l == 0) fd_rowmax(FD, d)[b * d.fd_PTc + n1] = 0u;  // for the second pass
         float vr[3][2][4], vi[3][2][4];
         float nrm = 0.f;
@@ -1541,10 +1509,12 @@ __global__ __launch_bounds__(256) void k_fd_pass1(const ReqDesc *__restrict__ R,
                         if (n < L) {
                             int xr, xi;
                             load_sample(d.samples, d.fmt, base + n, xr, xi);
-                            double ph = cyc * (double)n;
-                            ph -= floor(ph);
+                            // carrier phase of in-block sample n: the top 24 bits of the
+                            // 64-bit accumulator n * fd_dphase, exact as a float in [0, 1)
+                            const unsigned long long ph = (unsigned long long)n * d.fd_dphase;
+                            const float cyc = (float)(uint32_t)(ph >> 40) * 0x1p-24f;
                             float sn, cs;
-                            sincospif(2.f * (float)ph, &sn, &cs);
+                            sincospif(2.f * cyc, &sn, &cs);
                             yr = (float)xr * cs + (float)xi * sn;  // x e^(-i theta)
                             yi = (float)xi * cs - (float)xr * sn;
                         }
@@ -1821,13 +1791,15 @@ __global__ __launch_bounds__(kSynthThreads) void k_fd_synth(const ReqDesc *__res
 // detection: column max over Doppler, argmax, second peak, mean; refinement
 // ===========================================================================
 // Work item = (request, PRN, block of 256 lags).  Q[tau] = max_k P (lowest k
-// on ties), K = that k; part = the block's FP64 sum of P (summed in a fixed
-// tree, so the mean does not depend on scheduling).
+// on ties), K = that k; part = the block's FP32 sum of P: each column summed
+// in row order, then the block's columns in a fixed binary tree, so the mean
+// does not depend on scheduling.  The relative error of a sum of positive
+// terms is at most (depth of its addition tree) * 2^-24.
 __global__ __launch_bounds__(kPeakThreads) void k_colmax(const ReqDesc *__restrict__ R, BatchHdr *H,
                                                          const long long *pre, float *Q, int32_t *K,
-                                                         double *part)
+                                                         float *part)
 {
-    __shared__ double red[kPeakThreads];
+    __shared__ float red[kPeakThreads];
     const int n_req = H->n_req;
     const long long total = H->total[kStColmax];
     const long long *pst = pre + (long long)kStColmax * (n_req + 1);
@@ -1837,12 +1809,12 @@ __global__ __launch_bounds__(kPeakThreads) void k_colmax(const ReqDesc *__restri
         const long long local = it - pst[r];
         const int p = (int)(local / d.n_tau_blk), blk = (int)(local % d.n_tau_blk);
         const int N = d.N, tau = blk * kPeakThreads + threadIdx.x;
-        double colsum = 0.0;
+        float colsum = 0.f;
         if (tau < N) {
             const GNSS_GLOBAL float *col = gmem(d.grid) + (long long)p * d.n_dopp * N + tau;
             float best = col[0];
             int kb = 0;
-            colsum = (double)best;
+            colsum = best;
             int k = 1;
             // eight rows' loads in flight at a time; max and sum in row order
             for (; k + 8 <= d.n_dopp; k += 8) {
@@ -1851,7 +1823,7 @@ __global__ __launch_bounds__(kPeakThreads) void k_colmax(const ReqDesc *__restri
                 for (int j = 0; j < 8; ++j) v[j] = col[(long long)(k + j) * N];
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
-                    colsum += (double)v[j];
+                    colsum += v[j];
                     if (v[j] > best) {
                         best = v[j];
                         kb = k + j;
@@ -1860,7 +1832,7 @@ __global__ __launch_bounds__(kPeakThreads) void k_colmax(const ReqDesc *__restri
             }
             for (; k < d.n_dopp; ++k) {
                 float v = col[(long long)k * N];
-                colsum += (double)v;
+                colsum += v;
                 if (v > best) {
                     best = v;
                     kb = k;
@@ -1884,7 +1856,7 @@ __global__ __launch_bounds__(kPeakThreads) void k_colmax(const ReqDesc *__restri
 // +-spc (circular), mean, ratio test.
 __global__ __launch_bounds__(kArgThreads) void k_peak(const ReqDesc *__restrict__ R, BatchHdr *H,
                                                        const long long *pre, const float *Q,
-                                                       const int32_t *K, const double *part)
+                                                       const int32_t *K, const float *part)
 {
     __shared__ float sv[kArgThreads];
     __shared__ int st[kArgThreads];
@@ -1938,17 +1910,26 @@ __global__ __launch_bounds__(kArgThreads) void k_peak(const ReqDesc *__restrict_
             if (tid < s) sv[tid] = fmaxf(sv[tid], sv[tid + s]);
             __syncthreads();
         }
+        const float second = sv[0] == -INFINITY ? 0.f : sv[0];
+        __syncthreads();
+        // the blocks' partial sums in a fixed binary tree (FP32)
+        float ps = 0.f;
+        for (int i = tid; i < d.n_tau_blk; i += kArgThreads) ps += part[d.part_off + (long long)p * d.n_tau_blk + i];
+        sv[tid] = ps;
+        __syncthreads();
+        for (int s = kArgThreads / 2; s > 0; s >>= 1) {
+            if (tid < s) sv[tid] += sv[tid + s];
+            __syncthreads();
+        }
         if (tid == 0) {
-            float second = sv[0] == -INFINITY ? 0.f : sv[0];
-            double sum = 0.0;
-            for (int i = 0; i < d.n_tau_blk; ++i) sum += part[d.part_off + (long long)p * d.n_tau_blk + i];
+            const float sum = sv[0];
             gnss_peak rr;
             rr.prn = d.prns[p];
             rr.doppler_bin = K[d.qk_off + (long long)p * N + tstar];
             rr.code_phase = tstar;
             rr.peak = peak;
             rr.second = second;
-            rr.mean = (float)(sum / ((double)d.n_dopp * (double)N));
+            rr.mean = sum / ((float)d.n_dopp * (float)N);
             rr.ratio = second > 0.f ? peak / second : INFINITY;
             rr.detected = rr.ratio >= d.threshold ? 1 : 0;
             rr.doppler_hz = 0.0;
@@ -1966,8 +1947,11 @@ __device__ __forceinline__ double parabola(double ym, double y0, double yp)
     return 0.5 * (ym - yp) / den;
 }
 
-// FP64 sub-bin refinement (the only FP64 arithmetic on the hot path); one
-// thread per (request, PRN).
+// FP64 sub-bin refinement, one thread per (request, PRN): the only FP64
+// arithmetic of a search on the device (the carrier and code-Doppler steps
+// are computed on the host; FP64 elsewhere in this file builds the constant
+// tables once per context: the carrier LUT, twiddles and exact-length code
+// spectra).
 __global__ void k_interp(const ReqDesc *__restrict__ R, BatchHdr *H, const long long *pre)
 {
     const int n_req = H->n_req;
@@ -2016,6 +2000,20 @@ static unsigned grid_for(long long work, long long cap, bool persistent)
     return (unsigned)g;
 }
 
+// The wipe + fold + boxcar + polyphase stage of a staged batch alone, launched
+// exactly as launch_batch launches it (stage entry point).
+hipError_t launch_box(const Launch &L, const uint32_t *d_lut, int2 *d_F, int n_cu, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, L.hdr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || L.total[kStBox] == 0) return e;
+    static int cap = 0;
+    if (!cap) cap = occupancy(k_box, 256, n_cu);
+    hipLaunchKernelGGL(k_box, dim3(grid_for(L.total[kStBox], cap, false)), dim3(256), 0, s, L.reqs, L.hdr, L.pre,
+                       d_lut, d_F);
+    return hipGetLastError();
+}
+
 // Frequency-domain Doppler: long DFT of every block (two passes), then the
 // block spectra of every (Doppler, block) item; replaces k_box and k_fft_x.
 static hipError_t launch_fd(const Launch &L, const Tables &T, void *d_fd, void *d_G, int *d_E, int n_cu,
@@ -2045,7 +2043,7 @@ static hipError_t launch_fd(const Launch &L, const Tables &T, void *d_fd, void *
 }
 
 hipError_t launch_batch(const Launch &L, const Tables &T, int2 *d_F, void *d_G, float *d_Q, int32_t *d_K,
-                        double *d_part, int n_cu, hipStream_t s, hipEvent_t *marks)
+                        float *d_part, int n_cu, hipStream_t s, hipEvent_t *marks)
 {
     const uint32_t *d_lut = T.lut;
     const float2 *d_tw = T.tw;

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <array>
+#include <atomic>
 #include <condition_variable>
 #include <deque>
 #include <map>
@@ -44,6 +45,10 @@ struct Workspace {
     void *h_stage = nullptr;
     size_t h_stage_cap = 0;
     hipEvent_t stage_ev = nullptr;
+    // recorded after the last enqueued work that uses these buffers: growing a
+    // buffer waits for it (not for the whole device)
+    hipEvent_t use_ev = nullptr;
+    bool used = false;
 };
 
 // A laid-out batch on the host.
@@ -58,6 +63,14 @@ struct BatchHost {
     size_t F_bytes = 0, G_bytes = 0, Q_bytes = 0, K_bytes = 0, part_bytes = 0, grid_bytes = 0;
     int fd = 0;          // frequency-domain Doppler requested
     int fd_bad = -1;     // first request it cannot serve, or -1
+    // host-computed tables copied with the descriptors: carrier NCO steps of
+    // every (request, Doppler bin) and, with code-Doppler compensation, the
+    // lag shift of every (request, bin, block); offsets in elements
+    std::vector<uint32_t> dk;
+    std::vector<long long> dk_off;
+    std::vector<int32_t> cshift;
+    std::vector<long long> cshift_off;  // -1: no table
+    int cshift_bad = -1;  // first request whose shift table would be too large, or -1
 };
 
 struct Ticket;
@@ -103,6 +116,12 @@ struct gnss_ctx {
     gnss_rt::Server *server = nullptr;  // serving loop, created on first submit
     std::mutex mu;      // serialises calls that use ws / timing state
     std::mutex mem_mu;  // dev_bytes accounting
+    std::mutex tuned_mu;  // guards `tuned` (read by the serving thread)
+    // failure injection for tests (options "fault_alloc", "fault_copy",
+    // "fault_launch"): the n-th following device allocation, host/device copy
+    // or batch launch of this context fails on the host, before anything is
+    // enqueued; 0 = off
+    std::atomic<int> fault_alloc{0}, fault_copy{0}, fault_launch{0};
 };
 
 struct gnss_graph {
@@ -123,16 +142,34 @@ struct DeviceGuard {
 };
 
 size_t sample_bytes(int fmt, size_t n);
-int ensure(gnss_ctx *c, DevBuf &b, size_t bytes);
+// Grows b to at least `bytes` under the HBM budget.  The old buffer is freed
+// after `wait_ev` (the last enqueued use of b, if any) has completed.
+int ensure(gnss_ctx *c, DevBuf &b, size_t bytes, hipEvent_t wait_ev = nullptr);
+// ensure() for a buffer of workspace w
+int ensure_ws(gnss_ctx *c, Workspace &w, DevBuf &b, size_t bytes);
+// Records w.use_ev on s after work that uses w's buffers (not while s is
+// being captured into a graph, whose workspace never grows).
+int mark_use(Workspace &w, hipStream_t s);
+// True when the countdown reaches this call (failure injection).
+bool inject(std::atomic<int> &countdown);
+// hipMemcpyAsync with the context's copy-failure injection
+int copy_async(gnss_ctx *c, void *dst, const void *src, size_t bytes, hipMemcpyKind kind, hipStream_t s);
 void release(gnss_ctx *c, DevBuf &b);
 void release_ws(gnss_ctx *c, Workspace &w);
 int make_plan(const gnss_request *r, gnss::Plan &p, bool need_outputs);
 int plan_all(const gnss_request *reqs, int n, std::vector<gnss::Plan> &plans);
 void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int corr_pt, float threshold,
-                 int precision, int doppler_fd, BatchHost &B);
-size_t meta_bytes(int n);
+                 int precision, int doppler_fd, int code_doppler, BatchHost &B);
+// Bytes of a batch's metadata on the device: header, prefix sums,
+// descriptors and the host-computed tables.
+size_t meta_bytes(const BatchHost &B);
+// carrier NCO step and code-Doppler shift, computed on the host
+uint32_t nco_step(double fs, double f_if, double lo, double step, int k);
+int32_t code_shift(long long b, int Tc, int N, double lo, double step, int k);
 size_t batch_device_bytes(const BatchHost &B);
-int stage_batch(gnss_ctx *c, Workspace &w, BatchHost &B, hipStream_t s, gnss::Launch &L);
+// meta_only: only the metadata buffer (stage entry points that run one
+// stage into a caller's buffer); the search options are then not checked.
+int stage_batch(gnss_ctx *c, Workspace &w, BatchHost &B, hipStream_t s, gnss::Launch &L, bool meta_only = false);
 int launch(gnss_ctx *c, Workspace &w, const gnss::Launch &L, hipStream_t s, bool allow_profile);
 
 // autotuner lookup: the PRN tile for a batch of these plans

@@ -222,9 +222,9 @@ static int run_slot_once(gnss_ctx *c, Slot &sl)
             pl[i] = sl.members[i]->plan;
         }
         BatchHost P;
-        build_batch(pl.data(), rq.data(), n, 2, c->threshold, c->precision, c->doppler_fd, P);
+        build_batch(pl.data(), rq.data(), n, 2, c->threshold, c->precision, c->doppler_fd, c->code_doppler, P);
         const size_t sizes[10] = {P.F_bytes, P.G_bytes, P.Q_bytes, P.K_bytes, P.part_bytes, P.grid_bytes,
-                                  meta_bytes(n), sb, pb, gb};
+                                  meta_bytes(P), sb, pb, gb};
         size_t off[10], need = 0;
         for (int k = 0; k < 10; ++k) {
             off[k] = need;
@@ -247,8 +247,9 @@ static int run_slot_once(gnss_ctx *c, Slot &sl)
     std::vector<gnss::Plan> plans(n);
     for (int i = 0; i < n; ++i) {
         Ticket *t = sl.members[i];
-        HIP_TRY(hipMemcpyAsync((char *)sl.samples.p + sl.sample_off[i], t->h_samples, t->sample_bytes,
-                               hipMemcpyHostToDevice, sl.stream));
+        if ((rc = copy_async(c, (char *)sl.samples.p + sl.sample_off[i], t->h_samples, t->sample_bytes,
+                             hipMemcpyHostToDevice, sl.stream)))
+            return rc;
         reqs[i] = t->req;
         reqs[i].samples = (char *)sl.samples.p + sl.sample_off[i];
         reqs[i].prn_list = t->prns.data();
@@ -257,10 +258,10 @@ static int run_slot_once(gnss_ctx *c, Slot &sl)
         plans[i] = t->plan;
     }
     BatchHost B;
-    build_batch(plans.data(), reqs.data(), n, corr_ptile_for(c, plans.data(), n), c->threshold, c->precision, c->doppler_fd, B);
+    build_batch(plans.data(), reqs.data(), n, corr_ptile_for(c, plans.data(), n), c->threshold, c->precision, c->doppler_fd, c->code_doppler, B);
     gnss::Launch L;
     if ((rc = stage_batch(c, sl.ws, B, sl.stream, L)) || (rc = launch(c, sl.ws, L, sl.stream, false))) return rc;
-    HIP_TRY(hipMemcpyAsync(sl.h_peaks, sl.peaks.p, pb, hipMemcpyDeviceToHost, sl.stream));
+    if ((rc = copy_async(c, sl.h_peaks, sl.peaks.p, pb, hipMemcpyDeviceToHost, sl.stream))) return rc;
     for (int i = 0; i < n; ++i) {
         Ticket *t = sl.members[i];
         if (t->req.out_grid)
@@ -387,11 +388,8 @@ void server_stop(gnss_ctx *c)
     S.cv.notify_all();
     if (S.th.joinable()) S.th.join();
     for (Slot &sl : S.slots) {
-        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
-        release_ws(c, sl.ws);
-        release(c, sl.samples);
-        release(c, sl.peaks);
-        release(c, sl.grids);
+        // the slot's buffers are views into its arena: the arena is what is freed
+        release_slot_buffers(c, sl);
         if (sl.h_peaks) (void)hipHostFree(sl.h_peaks);
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
@@ -421,6 +419,7 @@ std::string rate_signature(const gnss::Plan *plans, int n)
 int corr_ptile_for(gnss_ctx *c, const gnss::Plan *plans, int n)
 {
     if (c->corr_pt_forced) return c->corr_pt_forced;
+    std::lock_guard<std::mutex> lk(c->tuned_mu);
     auto it = c->tuned.find(rate_signature(plans, n));
     return it != c->tuned.end() ? it->second.first : 2;
 }
@@ -430,6 +429,7 @@ int persistent_for(gnss_ctx *c, const BatchHost &B)
     if (c->persistent_forced >= 0) return c->persistent_forced;
     std::vector<gnss::Plan> spc(B.n);
     for (int i = 0; i < B.n; ++i) spc[i].spc = B.d[i].spc;
+    std::lock_guard<std::mutex> lk(c->tuned_mu);
     auto it = c->tuned.find(rate_signature(spc.data(), B.n));
     return it != c->tuned.end() ? it->second.second : 1;
 }
@@ -494,7 +494,7 @@ int gnss_submit(gnss_ctx *ctx, const gnss_request *req, uint64_t *ticket)
     t->sample_bytes = sample_bytes(p.fmt, (size_t)p.n_samples);
     BatchHost B;
     gnss_request r1 = *req;
-    build_batch(&p, &r1, 1, corr_ptile_for(ctx, &p, 1), ctx->threshold, ctx->precision, ctx->doppler_fd, B);
+    build_batch(&p, &r1, 1, corr_ptile_for(ctx, &p, 1), ctx->threshold, ctx->precision, ctx->doppler_fd, ctx->code_doppler, B);
     t->need_bytes = batch_device_bytes(B) + t->sample_bytes + (size_t)p.n_prn * sizeof(gnss_peak) +
                     (req->out_grid ? (size_t)p.grid_elems() * sizeof(float) : 0);
     if (t->need_bytes > admit_budget(ctx))
@@ -599,7 +599,7 @@ int gnss_autotune(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, const 
             for (int pers : {1, 0}) {
                 std::lock_guard<std::mutex> lk(ctx->mu);
                 BatchHost B;
-                build_batch(plans.data(), reqs, n_req, pt, ctx->threshold, ctx->precision, ctx->doppler_fd, B);
+                build_batch(plans.data(), reqs, n_req, pt, ctx->threshold, ctx->precision, ctx->doppler_fd, ctx->code_doppler, B);
                 gnss::Launch L;
                 if ((rc = stage_batch(ctx, ctx->ws, B, ctx->stream, L))) break;
                 L.persistent = pers;
@@ -628,7 +628,7 @@ int gnss_autotune(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, const 
         if (cache_path) cache_write(cache_path, cache);
     }
     {
-        std::lock_guard<std::mutex> lk(ctx->mu);
+        std::lock_guard<std::mutex> lk(ctx->tuned_mu);
         ctx->tuned[sig] = best;
     }
     if (chosen_tile) *chosen_tile = best.first;

@@ -109,7 +109,7 @@ static int track_enqueue(gnss_ctx *c, Workspace &w, const gnss_track_request *re
     const size_t off_pre = align256((size_t)n * sizeof(gnss::TrackDesc));
     const size_t off_ch = off_pre + align256((size_t)(n + 1) * sizeof(long long));
     const size_t mb = off_ch + ch.size() * sizeof(gnss::TrackCh);
-    if ((rc = ensure(c, w.tmeta, mb))) return rc;
+    if ((rc = ensure_ws(c, w, w.tmeta, mb))) return rc;
     if (w.stage_ev) HIP_TRY(hipEventSynchronize(w.stage_ev));
     if (w.h_stage_cap < mb) {
         if (w.h_stage) HIP_TRY(hipHostFree(w.h_stage));
@@ -128,7 +128,7 @@ static int track_enqueue(gnss_ctx *c, Workspace &w, const gnss_track_request *re
     unsigned char *dm = (unsigned char *)w.tmeta.p;
     HIP_TRY(gnss::launch_track((const gnss::TrackDesc *)dm, (const long long *)(dm + off_pre), n, pre[n],
                                (const gnss::TrackCh *)(dm + off_ch), c->d_codes, c->d_lut, s));
-    return GNSS_OK;
+    return mark_use(w, s);
 }
 
 }  // namespace gnss_rt
@@ -161,7 +161,7 @@ int gnss_track(const gnss_track_request *req)
     Workspace &w = c->ws;
     const size_t sb = sample_bytes(req->fmt, req->n);
     const size_t ob = (size_t)req->n_channels * req->n_epochs * 6 * sizeof(long long);
-    if ((rc = ensure(c, w.samples, sb)) || (rc = ensure(c, w.tout, ob))) return rc;
+    if ((rc = ensure_ws(c, w, w.samples, sb)) || (rc = ensure_ws(c, w, w.tout, ob))) return rc;
     HIP_TRY(hipMemcpyAsync(w.samples.p, req->samples, sb, hipMemcpyHostToDevice, c->stream));
     gnss_track_request dr = *req;
     dr.samples = w.samples.p;
