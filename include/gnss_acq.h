@@ -184,6 +184,29 @@ int gnss_workspace_bytes(const gnss_request *req, size_t *bytes);
  * GNSS_ENOMEM, GNSS_EDEVICE. */
 int gnss_acquire_device(gnss_ctx *ctx, const gnss_request *req, void *stream);
 
+/* Allocation-free form of gnss_acquire_device, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, arithmetic,
+ * kernels and results as gnss_acquire_device; the call allocates no device
+ * or pinned memory and creates no HIP objects: the request's workspace (block
+ * and spectrum buffers, column maxima, the internal grid when out_grid is
+ * NULL, and the request metadata) is laid out in a static device array of
+ * GNSS_NOALLOC_SCRATCH_BYTES bytes that every GPU running the library holds
+ * until the process ends, and the metadata goes through
+ * GNSS_NOALLOC_META_BYTES of pinned staging that gnss_ctx_create sets up.
+ * A search of the strong-signal size (4.092 MHz, 10 ms, 32 PRNs x 21 bins,
+ * internal grid) fits in every precision.  The caller owns samples,
+ * out_grid and out_peaks (device memory), as for gnss_acquire_device.
+ * Every such call on a GPU shares that GPU's array (all contexts on the
+ * device), which keeps the last call's contents; calls that overlap on one
+ * GPU, on any streams or contexts, race and give undefined results.  The
+ * host waits for the previous call's metadata copy before staging the next.
+ * Errors: as gnss_acquire_device; GNSS_ENOMEM (with the bytes needed in
+ * gnss_last_error) when the workspace or metadata exceeds those sizes. */
+#define GNSS_NOALLOC_SCRATCH_BYTES 67108864
+#define GNSS_NOALLOC_META_BYTES 1048576
+int gnss_acquire_device_noalloc(gnss_ctx *ctx, const gnss_request *req, void *stream);
+
 /* Batched acquisition on device buffers: n_req requests of any lengths,
  * sample rates, PRN lists and Doppler windows searched by one pass of the
  * stage kernels over a device table of the requests (the batch mode of the

@@ -39,7 +39,11 @@ EXPORTED = [
     "gnss_strerror", "gnss_last_error", "gnss_acquire_batch_device", "gnss_graph_create",
     "gnss_graph_launch", "gnss_graph_destroy", "gnss_autotune", "gnss_submit", "gnss_poll",
     "gnss_wait", "gnss_track", "gnss_track_device", "gnss_dft1023", "gnss_box_fold",
+    "gnss_acquire_device_noalloc",
 ]
+
+GNSS_NOALLOC_SCRATCH_BYTES = 64 << 20
+GNSS_NOALLOC_META_BYTES = 1 << 20
 
 GNSS_STAGE_WIPE_FOLD = 0
 GNSS_STAGE_FFT = 1
@@ -113,6 +117,7 @@ def _load() -> ctypes.CDLL:
         "gnss_ctx_set": [vp, ctypes.c_char_p, dbl],
         "gnss_workspace_bytes": [ctypes.POINTER(gnss_request), ctypes.POINTER(sz)],
         "gnss_acquire_device": [vp, ctypes.POINTER(gnss_request), vp],
+        "gnss_acquire_device_noalloc": [vp, ctypes.POINTER(gnss_request), vp],
         "gnss_gold_codes": [vp, pi32, i32, vp, vp],
         "gnss_code_replica": [vp, pi32, i32, dbl, sz, vp, vp],
         "gnss_nco_lut": [vp, vp, vp, vp],
@@ -318,6 +323,9 @@ class Context:
     # -- full search on device buffers --------------------------------------
     def acquire_device(self, req: gnss_request, stream=None):
         _check(_lib.gnss_acquire_device(self.handle, ctypes.byref(req), _stream_ptr(stream)))
+
+    def acquire_device_noalloc(self, req: gnss_request, stream=None):
+        _check(_lib.gnss_acquire_device_noalloc(self.handle, ctypes.byref(req), _stream_ptr(stream)))
 
     def stage_times(self, reset: bool = False):
         """{stage name: (total ms, launches)} accumulated while "profile" is 1."""

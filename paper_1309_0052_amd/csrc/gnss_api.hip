@@ -206,6 +206,7 @@ int make_plan(const gnss_request *r, gnss::Plan &p, bool need_outputs)
 // batches
 // ---------------------------------------------------------------------------
 static long long cdiv(long long a, long long b) { return (a + b - 1) / b; }
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Lays out the requests of a batch: descriptors, prefix sums of work items
 // per stage and workspace sizes.  Device pointers of the request (samples,
@@ -374,8 +375,6 @@ void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int c
     B.part_bytes = (size_t)part * sizeof(float);
     B.grid_bytes = (size_t)grid_int * sizeof(float);
 }
-
-static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Metadata layout: header, prefix sums, descriptors, NCO steps, shift tables.
 struct MetaLayout {
@@ -547,6 +546,63 @@ int plan_all(const gnss_request *reqs, int n, std::vector<gnss::Plan> &plans)
 }
 
 // ---------------------------------------------------------------------------
+// workspace of the allocation-free entry point
+// ---------------------------------------------------------------------------
+// Every GPU that loads the library holds its own copy of this array until the
+// process ends.  In host code its name is only a stand-in for the symbol:
+// kernels and copies get the device address from scratch_address().
+static __device__ __align__(256) unsigned char scratch[GNSS_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::map<int, void *> g_scratch_addr;  // device -> address of its copy
+
+// Looks up (once per device, with that device current) the device address of
+// this device's copy of `scratch`.
+int scratch_address(int device, void **out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_addr.find(device);
+    if (it != g_scratch_addr.end()) {
+        *out = it->second;
+        return GNSS_OK;
+    }
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return set_err(GNSS_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+    }
+    g_scratch_addr[device] = p;
+    *out = p;
+    return GNSS_OK;
+}
+
+// Lays the device buffers of a one-request batch out in the scratch array as
+// 256-byte-aligned views.  Fails if they do not fit.
+static int scratch_layout(gnss_ctx *c, const BatchHost &B, Workspace &w)
+{
+    const size_t sizes[7] = {B.F_bytes, B.G_bytes, B.Q_bytes, B.K_bytes, B.part_bytes, B.grid_bytes, meta_bytes(B)};
+    DevBuf *bufs[7] = {&w.F, &w.G, &w.Q, &w.K, &w.part, &w.grid, &w.meta};
+    size_t off[7], end = 0;
+    for (int i = 0; i < 7; ++i) {
+        off[i] = end;
+        end += align256(std::max<size_t>(sizes[i], 1));
+    }
+    if (end > GNSS_NOALLOC_SCRATCH_BYTES)
+        return set_err(GNSS_ENOMEM, "the request needs %zu bytes of workspace, more than the %zu of the "
+                       "allocation-free scratch", end, (size_t)GNSS_NOALLOC_SCRATCH_BYTES);
+    if (sizes[6] > w.h_stage_cap)
+        return set_err(GNSS_ENOMEM, "the request's %zu bytes of metadata exceed the %zu of the allocation-free "
+                       "staging", sizes[6], w.h_stage_cap);
+    for (int i = 0; i < 7; ++i) {
+        bufs[i]->p = (unsigned char *)c->d_scratch + off[i];
+        bufs[i]->cap = align256(std::max<size_t>(sizes[i], 1));
+        bufs[i]->owned = false;
+    }
+    return GNSS_OK;
+}
+
+// ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
 int ctx_init_tables(gnss_ctx *c)
@@ -614,6 +670,14 @@ int ctx_init_tables(gnss_ctx *c)
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, c->device));
     c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+    // set-up of the allocation-free entry point: the device address of the
+    // static scratch array, the pinned metadata staging and the events it uses
+    int rc = scratch_address(c->device, &c->d_scratch);
+    if (rc) return rc;
+    HIP_TRY(hipHostMalloc(&c->ws_na.h_stage, GNSS_NOALLOC_META_BYTES, hipHostMallocDefault));
+    c->ws_na.h_stage_cap = GNSS_NOALLOC_META_BYTES;
+    HIP_TRY(hipEventCreateWithFlags(&c->ws_na.stage_ev, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&c->ws_na.use_ev, hipEventDisableTiming));
     return GNSS_OK;
 }
 
@@ -625,6 +689,7 @@ void ctx_free(gnss_ctx *c)
     bool switched = hipGetDevice(&cur) == hipSuccess && cur != c->device && hipSetDevice(c->device) == hipSuccess;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     release_ws(c, c->ws);
+    release_ws(c, c->ws_na);
     for (auto &grp : c->pending)
         for (hipEvent_t e : grp) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
@@ -860,6 +925,29 @@ int gnss_acquire_batch_device(gnss_ctx *ctx, const gnss_request *reqs, int32_t n
 int gnss_acquire_device(gnss_ctx *ctx, const gnss_request *req, void *stream)
 {
     return gnss_acquire_batch_device(ctx, req, 1, stream);
+}
+
+int gnss_acquire_device_noalloc(gnss_ctx *ctx, const gnss_request *req, void *stream)
+{
+    if (!ctx) return set_err(GNSS_EINVAL, "ctx is null");
+    gnss::Plan p;
+    int rc = make_plan(req, p, true);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    if (g.rc) return g.rc;
+    if (!ctx->d_scratch) return set_err(GNSS_EDEVICE, "the context has no scratch address");
+    hipStream_t s = (hipStream_t)stream;
+    BatchHost B;
+    build_batch(&p, req, 1, corr_ptile_for(ctx, &p, 1), ctx->threshold, ctx->precision, ctx->doppler_fd,
+                ctx->code_doppler, B);
+    Workspace &w = ctx->ws_na;
+    if ((rc = scratch_layout(ctx, B, w))) return rc;
+    // every buffer now has the capacity the batch needs, and the staging and
+    // its events exist: staging and launch allocate nothing
+    gnss::Launch L;
+    if ((rc = stage_batch(ctx, w, B, s, L))) return rc;
+    return launch(ctx, w, L, s, false);
 }
 
 int gnss_acquire(const void *samples, int32_t fmt, size_t n, double fs, double f_if,

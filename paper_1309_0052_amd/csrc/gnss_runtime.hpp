@@ -105,6 +105,11 @@ struct gnss_ctx {
     void *d_cs_x = nullptr;     //   1023-point code spectra * 2^-cs_exp, fragment layout
     int cs_exp = 0;
     gnss_rt::Workspace ws;      // synchronous and device-buffer calls
+    // allocation-free searches: this device's copy of the static scratch
+    // array, and a workspace of views into it whose pinned metadata staging
+    // and events are created with the context
+    void *d_scratch = nullptr;
+    gnss_rt::Workspace ws_na;
     // autotuned (PRN tile, correlation schedule) per sample-rate signature
     std::map<std::string, std::pair<int, int>> tuned;
     // per-stage timing

@@ -1,0 +1,123 @@
+"""GPU tests of the allocation-free entry point (gnss_acquire_device_noalloc):
+the same search as gnss_acquire_device with its workspace in the library's
+static scratch array.  Its results must equal gnss_acquire_device's bit for
+bit (same kernels, same arithmetic, same order), on consecutive calls whose
+second is smaller than the first (the scratch keeps the previous call's
+contents), in every precision; a request too large for the scratch is
+refused with GNSS_ENOMEM and leaves the context usable."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from parity import assert_grid_close
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+G = pytest.importorskip("paper_1309_0052_amd")
+
+PRECISIONS = [G.GNSS_FP32, G.GNSS_FP16, G.GNSS_FP16_PFA]
+
+
+def _small_case():
+    """2.046 MHz packed 2-bit, 2 ms x 3 blocks, 3 PRNs x 3 bins: smaller than
+    the strong-signal search in every dimension."""
+    planted = [synth.Planted(prn=13, code_phase=901, doppler_hz=480.0, cn0_dbhz=50.0)]
+    snap = synth.make_snapshot(77, synth.REAL_2BIT_PACKED, 2046000, 511500.0, 6.3, planted, O.ca_code)
+    return snap, synth.Search([4, 13, 30], -500.0, 500.0, 500.0, 2, 3)
+
+
+class Dev:
+    def __init__(self, snap, srch, grid=True):
+        self.snap, self.srch = snap, srch
+        self.nd = O.n_doppler(srch.lo, srch.hi, srch.step)
+        self.N = snap.fs_hz // 1000
+        self.x = torch.from_numpy(np.ascontiguousarray(snap.samples)).cuda()
+        n = len(srch.prns) * self.nd * self.N
+        self.grid = torch.full((n,), -1.0, dtype=torch.float32, device="cuda") if grid else None
+        self.pk = torch.zeros(len(srch.prns) * 48, dtype=torch.uint8, device="cuda")
+        self.req = G.make_request(self.x.data_ptr(), snap.fmt, snap.n, snap.fs_hz, snap.f_if_hz, srch.prns,
+                                  srch.lo, srch.hi, srch.step, srch.T_coh, srch.N_noncoh,
+                                  self.grid.data_ptr() if grid else 0, self.pk.data_ptr())
+
+    def clear(self):
+        if self.grid is not None:
+            self.grid.fill_(-1.0)
+        self.pk.zero_()
+
+    def result(self):
+        torch.cuda.synchronize()
+        g = None
+        if self.grid is not None:
+            g = self.grid.cpu().numpy().reshape(len(self.srch.prns), self.nd, self.N).copy()
+        return g, self.pk.cpu().numpy().view(G.PEAK_DTYPE).copy()
+
+
+def _same_peaks(a, b):
+    assert a.tobytes() == b.tobytes(), (a, b)
+
+
+@pytest.mark.parametrize("prec", PRECISIONS, ids=["fp32", "fp16", "fp16pfa"])
+def test_noalloc_equals_acquire_device_twice_second_smaller(prec, strong_case):
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    snap, srch, nd, P = strong_case
+    small_snap, small_srch = _small_case()
+    with G.Context(0, precision=prec) as ctx:
+        big = Dev(snap, srch)
+        small = Dev(small_snap, small_srch)
+        ref = {}
+        for name, d in (("big", big), ("small", small)):
+            ctx.acquire_device(d.req)
+            ref[name] = d.result()
+            d.clear()
+        # the allocation-free calls: the strong-signal search, then a smaller one
+        for name, d in (("big", big), ("small", small)):
+            print("noalloc precision %d, %s request" % (prec, name), flush=True)
+            ctx.acquire_device_noalloc(d.req)
+            g, pk = d.result()
+            assert np.array_equal(g, ref[name][0]), name
+            _same_peaks(pk, ref[name][1])
+            d.clear()
+        # and the big one again after the small one, with the grid kept
+        # internal (in the scratch): same peaks
+        big_nogrid = Dev(snap, srch, grid=False)
+        ctx.acquire_device_noalloc(big_nogrid.req)
+        _, pk = big_nogrid.result()
+        _same_peaks(pk, ref["big"][1])
+    if prec == G.GNSS_FP32:
+        # the FP32 result against the FP64 oracle (the library's usual bar)
+        assert_grid_close(ref["big"][0], P)
+        Ps = O.grid_direct(small_snap.samples, small_snap.fmt, small_snap.fs_hz, small_snap.f_if_hz,
+                           small_srch.prns, small_srch.lo, small_srch.step,
+                           O.n_doppler(small_srch.lo, small_srch.hi, small_srch.step),
+                           small_srch.T_coh, small_srch.N_noncoh)
+        assert_grid_close(ref["small"][0], Ps)
+
+
+def test_noalloc_refuses_oversize_request_and_allocates_nothing(strong_case):
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    snap, srch, nd, P = strong_case
+    weak, wsrch = synth.weak_complex_int8(O.ca_code, seed=2)
+    with G.Context(0) as ctx:
+        d = Dev(snap, srch)
+        ctx.acquire_device(d.req)
+        ref = d.result()
+        d.clear()
+        # the weak-signal search needs far more than the scratch holds
+        big = Dev(weak, wsrch, grid=False)
+        with pytest.raises(G.GnssError) as ei:
+            ctx.acquire_device_noalloc(big.req)
+        assert ei.value.code == G.GNSS_ENOMEM
+        assert "scratch" in G.last_error()
+        # the context still serves allocation-free calls, and they hold no new device memory
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        for _ in range(3):
+            ctx.acquire_device_noalloc(d.req)
+            g, pk = d.result()
+            assert np.array_equal(g, ref[0])
+            _same_peaks(pk, ref[1])
+            d.clear()
+        torch.cuda.synchronize()
+        assert torch.cuda.mem_get_info()[0] == free0
