@@ -106,9 +106,23 @@ def workload(name: str, code_fn):
     return snap, srch, desc
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(snap, srch, target_s: float):
-    """The oracle (plain direct correlation, FP64, all host threads) on a
-    bounded sample of cells of the same workload; cells/s extrapolated."""
+    """The oracle (plain direct correlation, FP64) on bounded samples of cells
+    of the same workload, cells/s extrapolated: the median of three timed runs
+    on all host threads after one untimed run, and one run on a single thread
+    (each run about target_s / 4 seconds)."""
     import numpy as np
 
     import oracle as O
@@ -119,24 +133,34 @@ def cpu_baseline(snap, srch, target_s: float):
     rng = np.random.default_rng(123)
     ms = srch.T_coh * srch.N_noncoh
 
-    def run(n_cells):
+    def run(n_cells, nthr):
         cells = np.stack([rng.integers(0, len(srch.prns), n_cells), rng.integers(0, nd, n_cells),
                           rng.integers(0, N, n_cells)], axis=1)
         t0 = time.perf_counter()
         O.cells_direct(snap.samples, snap.fmt, snap.fs_hz, snap.f_if_hz, srch.prns, srch.lo,
-                       srch.step, nd, srch.T_coh, srch.N_noncoh, cells, threads=threads)
+                       srch.step, nd, srch.T_coh, srch.N_noncoh, cells, threads=nthr)
         return time.perf_counter() - t0
 
-    n = 2 * threads
-    dt = run(n)
-    while dt < 1.0 and n < (1 << 26):  # a first timing long enough to extrapolate from
-        n *= 4
-        dt = run(n)
-    n2 = max(n, int(n * target_s / dt))
-    dt2 = run(n2)
-    return {"value": n2 * ms / dt2, "unit": "cells/s", "cores": threads, "kind": "oracle",
+    def size_for(nthr, seconds):
+        n = 2 * nthr
+        dt = run(n, nthr)  # also the untimed warm-up run
+        while dt < 0.5 and n < (1 << 26):  # a first timing long enough to extrapolate from
+            n *= 4
+            dt = run(n, nthr)
+        return max(n, int(n * seconds / dt))
+
+    part = target_s / 4.0
+    n_all = size_for(threads, part)
+    rates = sorted(n_all * ms / run(n_all, threads) for _ in range(3))
+    n_one = size_for(1, part)
+    dt_one = run(n_one, 1)
+    return {"value": rates[1], "unit": "cells/s", "cores": threads, "kind": "oracle",
             "sample": "%d random (PRN, Doppler, phase) cells x %d ms by direct time-domain "
-                      "correlation, %.1f s" % (n2, ms, dt2)}
+                      "correlation, median of 3 runs of ~%.0f s on %d threads (runs: %s cells/s)"
+                      % (n_all, ms, part, threads, ", ".join("%.4g" % r for r in rates)),
+            "one_core": {"value": n_one * ms / dt_one, "unit": "cells/s", "cores": 1,
+                         "sample": "%d cells x %d ms, %.1f s" % (n_one, ms, dt_one)},
+            "cpu_model": cpu_model()}
 
 
 def main():
