@@ -14,9 +14,14 @@
  * Conventions common to every entry point
  *  - Every function returns int: GNSS_OK (0) or a negative GNSS_E* code;
  *    gnss_last_error() then gives a thread-local message.
- *  - Sample rate fs (Hz) must be an integer multiple of the chip rate
- *    1.023 MHz, at most 16.368 MHz; N = fs/1000 samples per millisecond and
- *    spc = fs/1.023e6 samples per chip.  Other rates give GNSS_ENOTSUP.
+ *  - Sample rate fs (Hz): any whole number of kHz with N = fs/1000 samples
+ *    per millisecond at most 16384 (the paper sizes its replica loops by the
+ *    recording's sampling frequency, Sec. 3); larger N gives GNSS_ENOTSUP.
+ *    At fs = k * 1.023 MHz with k <= 16 (spc = k samples per chip) the
+ *    search uses the polyphase form on 2048-point (FP32, FP16) or 1023-point
+ *    (GNSS_FP16_PFA) transforms; at every other rate it correlates each
+ *    block on zero-padded FP32 transforms of length M = 2^ceil(log2 2N),
+ *    whatever the context's precision.
  *  - Doppler bins f_k = lo + k*step (IEEE double, as written), k = 0..n_dopp-1,
  *    n_dopp = floor((hi - lo)/step + 1e-9) + 1 (both ends inclusive).
  *  - Coherent block b covers samples [b*T*N, (b+1)*T*N), T = T_coh_ms; blocks
@@ -30,7 +35,8 @@
  *    Power grid P[p][k][tau] = sum_b |R_b[tau]|^2 * 2^-24, FP32, layout
  *    [prn][doppler][tau] (tau fastest).
  *  - Detection per PRN: Q[tau] = max_k P (lowest k on ties), tau* = argmax Q
- *    (lowest tau), second = max Q over circular |tau - tau*| > spc,
+ *    (lowest tau), second = max Q over circular |tau - tau*| > fs/1.023 MHz
+ *    (one chip; at a general rate that is |tau - tau*| > floor(fs/1.023 MHz)),
  *    ratio = peak/second, detected = ratio >= threshold (default 2.5).
  *    Sub-bin refinement: 3-point parabolas in FP64 along tau (circular) and
  *    along Doppler (not at the first or last bin).
@@ -148,7 +154,7 @@ void gnss_ctx_destroy(gnss_ctx *ctx);
  * shift of k*kappa bins, and the polyphase block spectra are synthesised from
  * it; needs doppler_step*T_coh*P/1000 a whole number kappa for some P in
  * {1, 2, 4} and P*T_coh*spc a power of two <= 256, else GNSS_ENOTSUP at
- * search time; not with code_doppler.  The grid is then sum_b |R_b|^2 of the
+ * search time; not with code_doppler, not at general rates.  The grid is then sum_b |R_b|^2 of the
  * exactly wiped blocks, on the scale of the NCO path's 2^-24 |R_b|^2 of its
  * 4096-scaled table; 0, the default: NCO and lookup table as in Fig. 2),
  * "nav_pairs" (1, only on GNSS_FP16_PFA contexts:
@@ -156,7 +162,8 @@ void gnss_ctx_destroy(gnss_ctx *ctx);
  * coherent blocks 2i and 2i+1 are combined with both relative signs and the
  * larger power kept, P = sum_i max(|R_2i + R_2i+1|^2, |R_2i - R_2i+1|^2), so
  * that a data-bit flip between them does not cancel the signal; needs an even
- * N_noncoh, else GNSS_ENOTSUP at search time; 0, the default: plain sum),
+ * N_noncoh and fs = k * 1.023 MHz, else GNSS_ENOTSUP at search time; 0,
+ * the default: plain sum),
  * "max_slots" (requests per
  * served batch, 1..4096), "fault_alloc" / "fault_copy" / "fault_launch" (n >= 1:
  * the n-th following device allocation, host/device copy or batch launch of
@@ -295,9 +302,10 @@ int gnss_nco_lut(gnss_ctx *ctx, int16_t *d_cos, int16_t *d_sin, void *stream);
  * Sec. 4): d_out[((k*N_noncoh + b)*N + m)*2 + {0,1}] = re/im of
  * sum_{t<T} y_k[(b*T + t)*N + m], exact int32.  Other fields of req as for
  * gnss_acquire_device (outputs ignored).  A standalone kernel; the search
- * itself runs the stage of gnss_box_fold.  Calls on one context must not
- * overlap.  Errors: GNSS_EINVAL, GNSS_ENOTSUP (fs), GNSS_ENOMEM,
- * GNSS_EDEVICE. */
+ * itself runs the stage of gnss_box_fold at k * 1.023 MHz and the same
+ * arithmetic inside its general-rate block transform at other rates.  Calls
+ * on one context must not overlap.  Errors: GNSS_EINVAL, GNSS_ENOTSUP (N >
+ * 16384), GNSS_ENOMEM, GNSS_EDEVICE. */
 int gnss_wipe_fold(gnss_ctx *ctx, const gnss_request *req, int32_t *d_out, void *stream);
 
 /* The search's own first stage, run alone with the kernel and launch the
@@ -311,7 +319,8 @@ int gnss_wipe_fold(gnss_ctx *ctx, const gnss_request *req, int32_t *d_out, void 
  * for m < 1023, and 0 at m = 1023; exact int32.  d_out is device memory of
  * n_dopp*N_noncoh*spc*1024*2 int32 owned by the caller; other fields of req as
  * for gnss_acquire_device (outputs ignored; "doppler_fd" does not apply).
- * Calls on one context must not overlap.  Errors: as gnss_wipe_fold. */
+ * Calls on one context must not overlap.  Errors: as gnss_wipe_fold, and
+ * GNSS_ENOTSUP when fs is not k * 1.023 MHz with k <= 16 (no polyphase form). */
 int gnss_box_fold(gnss_ctx *ctx, const gnss_request *req, int32_t *d_out, void *stream);
 
 /* Batched 2048-point complex FFT (the FFT/IFFT stages of Fig. 2), natural

@@ -370,6 +370,13 @@ def samples_per_chip(fs_hz: int) -> int:
     return int(fs_hz) // CHIP_RATE_HZ
 
 
+def chip_exclusion(fs_hz: int) -> float:
+    """Half-width of the second-peak exclusion: one chip, fs / 1.023 MHz
+    samples, at any rate (the lags with circular |tau - tau*| > this are
+    candidates; at k * 1.023 MHz it is the integer k)."""
+    return int(fs_hz) / CHIP_RATE_HZ
+
+
 # ---------------------------------------------------------------------------
 # tracking correlators (Fig. 3)
 # ---------------------------------------------------------------------------

@@ -177,9 +177,14 @@ int make_plan(const gnss_request *r, gnss::Plan &p, bool need_outputs)
     // times T_coh_ms (fold) times spc <= 16 (boxcar) stays below 2^31 up to 64 ms
     if (r->T_coh_ms < 1 || r->T_coh_ms > 64) return set_err(GNSS_EINVAL, "T_coh_ms outside [1, 64]");
     if (r->N_noncoh < 1 || r->N_noncoh > 100000) return set_err(GNSS_EINVAL, "N_noncoh outside [1, 100000]");
-    if (fs % 1023000 != 0 || fs / 1023000 > gnss::kMaxSpc)
-        return set_err(GNSS_ENOTSUP, "fs %lld Hz is not k * 1.023 MHz with 1 <= k <= %d", (long long)fs,
-                       gnss::kMaxSpc);
+    // k * 1.023 MHz (k <= 16): the polyphase form on 2048-point or 1023-point
+    // transforms; any other whole number of kHz up to N = 16384: zero-padded
+    // transforms of length M = 2^ceil(log2(2N))
+    p.gen = (fs % 1023000 != 0 || fs / 1023000 > gnss::kMaxSpc) ? 1 : 0;
+    if (p.gen && fs / 1000 > gnss::kGenMaxN)
+        return set_err(GNSS_ENOTSUP, "fs %lld Hz: more than %d samples per ms (and not k * 1.023 MHz, k <= %d)",
+                       (long long)fs, gnss::kGenMaxN, gnss::kMaxSpc);
+    p.gen_M = p.gen ? gnss::gen_transform_len((int)(fs / 1000)) : 0;
     p.fmt = r->fmt;
     p.n_samples = (int64_t)r->n;
     p.fs_hz = fs;
@@ -278,7 +283,8 @@ void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int c
     B.cshift_off.assign(n, -1);
     B.cshift_bad = -1;
     long long tot[gnss::kNumStages] = {};
-    long long vec = 0, qk = 0, part = 0, grid_int = 0, fd_f2 = 0;
+    long long vec = 0, qk = 0, part = 0, grid_int = 0, fd_f2 = 0, gen_f2 = 0;
+    B.gen_first = -1;
     for (int r = 0; r < n; ++r) {
         const gnss::Plan &p = plans[r];
         gnss::ReqDesc &d = B.d[r];
@@ -297,7 +303,16 @@ void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int c
         d.Tc = p.Tc;
         d.Nnc = p.Nnc;
         d.n_prn = p.n_prn;
-        d.n_items = p.n_dopp * p.spc;
+        d.n_items = p.gen ? 0 : p.n_dopp * p.spc;
+        if (p.gen) {
+            d.gen = 1;
+            d.gen_M = p.gen_M;
+            d.gen_P = std::min(p.gen_M, gnss::kGenLds);
+            d.gen_x_off = gen_f2;
+            d.gen_c_off = gen_f2 + (long long)p.n_dopp * p.Nnc * p.gen_M;
+            gen_f2 += ((long long)p.n_dopp * p.Nnc + p.n_prn) * p.gen_M;
+            if (B.gen_first < 0) B.gen_first = r;
+        }
         d.n_ptiles = (int)cdiv(p.n_prn, corr_pt);
         d.n_tau_blk = (int)cdiv(p.N, gnss::kPeakThreads);
         d.threshold = threshold;
@@ -320,7 +335,7 @@ void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int c
         long long fd_a = 0, fd_b = 0;
         if (doppler_fd) {
             int PTc = 0, A = 0, kappa = 0;
-            if (fd_params(p, PTc, A, kappa)) {
+            if (!p.gen && fd_params(p, PTc, A, kappa)) {
                 d.fd = 1;
                 d.fd_PTc = PTc;
                 d.fd_A = A;
@@ -349,9 +364,11 @@ void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int c
             }
         }
         const long long cnt[gnss::kNumStages] = {
-            (long long)p.n_dopp * p.Nnc, p.n_vec(),
+            p.gen ? 0 : (long long)p.n_dopp * p.Nnc, p.n_vec(),
             (long long)d.n_ptiles * cdiv(d.n_items, corr_w), (long long)p.n_prn * d.n_tau_blk, (long long)p.n_prn,
-            fd_a, fd_b};
+            fd_a, fd_b,
+            p.gen ? (long long)p.n_dopp * p.Nnc : 0, p.gen ? (long long)p.n_prn : 0,
+            p.gen ? (long long)p.n_prn * p.n_dopp : 0};
         for (int st = 0; st < gnss::kNumStages; ++st) {
             B.pre[(size_t)st * (n + 1) + r] = tot[st];
             tot[st] += cnt[st];
@@ -369,7 +386,9 @@ void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int c
     B.precision = precision;
     // the frequency-domain variant has no polyphase vectors in F: its long spectra live there
     B.F_bytes = doppler_fd ? (size_t)fd_f2 * sizeof(float2) : (size_t)vec * gnss::kPolyLen * sizeof(int2);
-    B.G_bytes = gnss::g_bytes(vec, precision);
+    // the general-rate block and code spectra (FP32 complex) follow the polyphase spectra
+    B.gen_off = align256(gnss::g_bytes(vec, precision));
+    B.G_bytes = B.gen_off + (size_t)gen_f2 * sizeof(float2);
     B.Q_bytes = (size_t)qk * sizeof(float);
     B.K_bytes = (size_t)qk * sizeof(int32_t);
     B.part_bytes = (size_t)part * sizeof(float);
@@ -425,6 +444,9 @@ int stage_batch(gnss_ctx *c, Workspace &w, BatchHost &B, hipStream_t s, gnss::La
     if (B.cshift_bad >= 0)
         return set_err(GNSS_ENOTSUP, "code_doppler: request %d has more than %lld (Doppler bin, block) pairs",
                        B.cshift_bad, kMaxShiftTable);
+    if (c->nav_pairs && B.gen_first >= 0 && !meta_only)
+        return set_err(GNSS_ENOTSUP, "nav_pairs: request %d is at a sample rate that is not k * 1.023 MHz",
+                       B.gen_first);
     int rc;
     const MetaLayout ml = meta_layout(B);
     const size_t mb = ml.total;
@@ -476,6 +498,7 @@ int stage_batch(gnss_ctx *c, Workspace &w, BatchHost &B, hipStream_t s, gnss::La
     L.precision = B.precision;
     L.fd = B.fd;
     L.nav_pairs = c->nav_pairs;
+    L.gen_off = B.gen_off;
     for (int st = 0; st < gnss::kNumStages; ++st) L.total[st] = B.total[st];
     return GNSS_OK;
 }
@@ -524,7 +547,8 @@ int launch(gnss_ctx *c, Workspace &w, const gnss::Launch &L, hipStream_t s, bool
             for (hipEvent_t e : ev) c->event_pool.push_back(e);
         return set_err(GNSS_EDEVICE, "injected launch failure");
     }
-    const gnss::Tables T{c->d_lut, c->d_tw, c->d_cs, c->d_tw_h, c->d_cs_h, c->d_frags_x, c->d_cs_x, c->cs_exp};
+    const gnss::Tables T{c->d_lut,   c->d_tw,   c->d_cs,     c->d_tw_h,
+                         c->d_cs_h,  c->d_frags_x, c->d_cs_x, c->cs_exp, c->d_tw_gen, c->d_codes};
     HIP_TRY(gnss::launch_batch(L, T, (int2 *)w.F.p, w.G.p, (float *)w.Q.p, (int32_t *)w.K.p, (float *)w.part.p,
                                c->n_cu, s, prof ? ev.data() : nullptr));
     if (prof) c->pending.push_back(ev);
@@ -612,7 +636,9 @@ int ctx_init_tables(gnss_ctx *c)
     const size_t tw_b = gnss::kTwElems * sizeof(float2);
     const size_t cs_b = (size_t)(gnss::kMaxPrn + 1) * gnss::kVec * sizeof(float4);
     const bool h = c->precision == GNSS_FP16, x = c->precision == GNSS_FP16_PFA;
-    const size_t table_bytes = lut_b + codes_b + tw_b + cs_b + (h ? gnss::kTwHBytes + gnss::kCsHBytes : 0) +
+    const size_t tw_gen_b = (size_t)gnss::kGenTwLen * sizeof(float2);
+    const size_t table_bytes = lut_b + codes_b + tw_b + cs_b + tw_gen_b +
+                               (h ? gnss::kTwHBytes + gnss::kCsHBytes : 0) +
                                (x ? gnss::kFragXBytes + gnss::kCsXBytes : 0);
     if (c->budget && table_bytes > c->budget)
         return set_err(GNSS_ENOMEM, "HBM budget %zu below the %zu bytes of tables", c->budget, table_bytes);
@@ -620,7 +646,19 @@ int ctx_init_tables(gnss_ctx *c)
     HIP_TRY(hipMalloc(&c->d_codes, codes_b));
     HIP_TRY(hipMalloc(&c->d_tw, tw_b));
     HIP_TRY(hipMalloc(&c->d_cs, cs_b));
+    HIP_TRY(hipMalloc(&c->d_tw_gen, tw_gen_b));
     c->dev_bytes += table_bytes;
+    {
+        // general rates: W_32768^j = exp(-2 pi i j / 32768), each part from its
+        // IEEE double value rounded once to float (host libm; the table is
+        // only used by the FP32 zero-padded transforms)
+        std::vector<float2> tw((size_t)gnss::kGenTwLen);
+        for (int j = 0; j < gnss::kGenTwLen; ++j) {
+            const double a = 2.0 * M_PI * (double)j / (double)gnss::kGenTwLen;
+            tw[j] = make_float2((float)std::cos(a), (float)-std::sin(a));
+        }
+        HIP_TRY(hipMemcpy(c->d_tw_gen, tw.data(), tw_gen_b, hipMemcpyHostToDevice));
+    }
     c->table_bytes = table_bytes;
     HIP_TRY(gnss::launch_lut(c->d_lut, nullptr, nullptr, c->stream));
     HIP_TRY(gnss::launch_gold_codes(c->d_codes, c->stream));
@@ -639,7 +677,7 @@ int ctx_init_tables(gnss_ctx *c)
         c->cs_exp = e;
         HIP_TRY(hipMalloc(&c->d_tw_h, gnss::kTwHBytes));
         HIP_TRY(hipMalloc(&c->d_cs_h, gnss::kCsHBytes));
-        HIP_TRY(gnss::launch_tables_h(c->d_cs, c->d_tw_h, c->d_cs_h, c->cs_exp, c->stream));
+        HIP_TRY(gnss::launch_tables_h(c->d_cs, c->d_codes, c->d_tw_h, c->d_cs_h, c->cs_exp, c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));
     }
     if (x) {
@@ -697,6 +735,7 @@ void ctx_free(gnss_ctx *c)
     if (c->d_codes) (void)hipFree(c->d_codes);
     if (c->d_tw) (void)hipFree(c->d_tw);
     if (c->d_cs) (void)hipFree(c->d_cs);
+    if (c->d_tw_gen) (void)hipFree(c->d_tw_gen);
     if (c->d_tw_h) (void)hipFree(c->d_tw_h);
     if (c->d_cs_h) (void)hipFree(c->d_cs_h);
     if (c->d_frags_x) (void)hipFree(c->d_frags_x);
@@ -1176,6 +1215,9 @@ int gnss_box_fold(gnss_ctx *ctx, const gnss_request *req, int32_t *d_out, void *
     hipStream_t s = (hipStream_t)stream;
     int rc = stage_one(ctx, req, p, s, B, L);
     if (rc) return rc;
+    if (p.gen)
+        return set_err(GNSS_ENOTSUP, "the boxcar and polyphase split need fs = k * 1.023 MHz, k <= %d",
+                       gnss::kMaxSpc);
     HIP_TRY(gnss::launch_box(L, ctx->d_lut, (int2 *)d_out, ctx->n_cu, s));
     return mark_use(ctx->ws, s);
 }

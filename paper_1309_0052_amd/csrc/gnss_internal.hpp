@@ -31,14 +31,33 @@ struct Plan {
     int64_t fs_hz;
     double f_if, lo, step;
     int N;          // samples per ms
-    int spc;        // samples per chip
+    int spc;        // samples per chip (whole part of fs / 1.023 MHz for a general rate)
     int n_dopp;
     int Tc, Nnc;
     int n_prn;
     PrnList prns;   // PRN numbers (1..37)
+    // general rate (fs not k * 1.023 MHz with 1 <= k <= kMaxSpc): the
+    // length-N correlations run on zero-padded transforms of length gen_M
+    int gen;
+    int gen_M;      // power of two >= 2N
     int64_t grid_elems() const { return (int64_t)n_prn * n_dopp * N; }
-    int64_t n_vec() const { return (int64_t)n_dopp * Nnc * spc; }
+    int64_t n_vec() const { return gen ? 0 : (int64_t)n_dopp * Nnc * spc; }
 };
+
+// General rates: N <= kGenMaxN samples per ms, transforms of length
+// M = 2^ceil(log2(2N)) <= 2 kGenLds done as one (M <= kGenLds) or two
+// (M = 2 kGenLds, even and odd bins) transforms of at most kGenLds points in
+// a workgroup's LDS.
+constexpr int kGenMaxN = 16384;
+constexpr int kGenLds = 16384;
+constexpr int kGenTwLen = 2 * kGenLds;  // twiddle table W_32768^j, j < 32768
+constexpr int kGenThreads = 1024;
+inline int gen_transform_len(int N)
+{
+    int M = 64;
+    while (M < 2 * N) M *= 2;
+    return M;
+}
 
 // one-time tables
 hipError_t launch_gold_codes(uint8_t *d_codes /*[38][1023], row = prn*/, hipStream_t s);
@@ -49,9 +68,13 @@ hipError_t launch_twiddles(float2 *d_tw, hipStream_t s);
 hipError_t launch_code_spectra(const uint8_t *d_codes, const float2 *d_tw, float4 *d_cs,
                                hipStream_t s);
 // FP16 tables: packed twiddles and the code spectra scaled by 2^-cs_exp
-hipError_t launch_tables_h(const float4 *d_cs, void *d_tw_h, void *d_cs_h, int cs_exp, hipStream_t s);
+hipError_t launch_tables_h(const float4 *d_cs, const uint8_t *d_codes, void *d_tw_h, void *d_cs_h, int cs_exp,
+                           hipStream_t s);
 constexpr size_t kTwHBytes = 2176 * 8;                      // hc2 twiddles
-constexpr size_t kCsHBytes = (size_t)(kMaxPrn + 1) * 8192;  // [38][2048] half2
+constexpr size_t kCsHSpecBytes = (size_t)(kMaxPrn + 1) * 8192;  // [38][2048] half2
+// followed by one float per PRN: 2048 * 2^-cs_exp * sum(code) / 1023, the
+// inverse output's lag-independent part per unit of a block's scaled sum
+constexpr size_t kCsHBytes = kCsHSpecBytes + 256;
 // Exact-length mode tables: FP16 weight fragments of the 31- and 33-point
 // passes, and the code spectra (FP64 staging, then FP16 fragments)
 constexpr size_t kPfaVecBytes = 264 * 16;  // one stored 1023-point spectrum
@@ -71,10 +94,15 @@ inline size_t g_spectra_bytes(long long n_vec, int precision)
            : precision == GNSS_FP16_PFA ? (size_t)n_vec * kPfaVecBytes
                                         : (size_t)n_vec * kVec * 16;
 }
+inline size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+// FP16 modes: the spectra, the per-vector exponents (int) and, for GNSS_FP16,
+// the per-vector scaled sums (float2)
 inline size_t g_bytes(long long n_vec, int precision)
 {
     return precision == GNSS_FP32 ? g_spectra_bytes(n_vec, precision)
-                                  : g_spectra_bytes(n_vec, precision) + (((size_t)n_vec * 4 + 255) & ~(size_t)255);
+           : precision == GNSS_FP16_PFA
+               ? g_spectra_bytes(n_vec, precision) + round256((size_t)n_vec * 4)
+               : g_spectra_bytes(n_vec, precision) + round256((size_t)n_vec * 4) + round256((size_t)n_vec * 8);
 }
 
 // ---------------------------------------------------------------------------
@@ -82,7 +110,10 @@ inline size_t g_bytes(long long n_vec, int precision)
 // requests (a single request is a batch of one); the correlation kernel can
 // run persistent, the others run one workgroup per work item
 // ---------------------------------------------------------------------------
-enum Stage { kStBox = 0, kStVec, kStCorr, kStColmax, kStPeak, kStFdA, kStFdB, kNumStages };
+// kStGenX / kStGenC / kStGenCorr: the general-rate path (block spectra,
+// code spectra, correlation)
+enum Stage { kStBox = 0, kStVec, kStCorr, kStColmax, kStPeak, kStFdA, kStFdB, kStGenX, kStGenC, kStGenCorr,
+             kNumStages };
 constexpr int kXcds = 8;
 
 // One request as the kernels see it (device memory).
@@ -119,6 +150,11 @@ struct ReqDesc {
     // accumulator, cycles * 2^64 per sample (phase of in-block sample n =
     // n * fd_dphase mod 2^64)
     unsigned long long fd_dphase;
+    // general rate: transform length M, its LDS part (M or M/2) and the
+    // request's block spectra [n_dopp][Nnc][M] and code spectra [n_prn][M]
+    // (float2 offsets in the general-rate region of the spectrum buffer)
+    int gen, gen_M, gen_P;
+    long long gen_x_off, gen_c_off;
     int prns[kMaxList];
 };
 
@@ -142,6 +178,7 @@ struct Launch {
     int precision;                // GNSS_FP32 / GNSS_FP16 / GNSS_FP16_PFA
     int fd;                       // 1: frequency-domain Doppler (exact-length contexts)
     int nav_pairs;                // 1: navigation-bit hypotheses (exact-length contexts)
+    size_t gen_off;               // bytes of the spectrum buffer before its general-rate region
 };
 
 // Device-resident tables of a context.
@@ -154,6 +191,8 @@ struct Tables {
     const void *frags_x;  // exact-length path only
     const void *cs_x;
     int cs_exp;
+    const float2 *tw_gen;  // general rates: W_32768^j, j < 32768
+    const uint8_t *codes;  // C/A chips [38][1023] (row = PRN)
 };
 
 hipError_t launch_batch(const Launch &L, const Tables &T, int2 *d_F, void *d_G, float *d_Q, int32_t *d_K,

@@ -769,10 +769,26 @@ __global__ void k_code_spectra_h(const float4 *cs, uint4 *csh, int ecs)
                         h2_bits(__floats2half2_rn(b.x * sc, b.y * sc)), h2_bits(__floats2half2_rn(b.z * sc, b.w * sc)));
 }
 
-hipError_t launch_tables_h(const float4 *d_cs, void *d_tw_h, void *d_cs_h, int cs_exp, hipStream_t s)
+// dck[prn] = 2048 * 2^-ecs * sum(code) / 1023 (PRN 0: 0)
+__global__ void k_code_dc_h(const uint8_t *codes, float *dck, int ecs)
 {
-    hipLaunchKernelGGL(k_twiddles_h, dim3((kTwElems + 255) / 256), dim3(256), 0, s, (hc2 *)d_tw_h);
+    const int prn = blockIdx.x * blockDim.x + threadIdx.x;
+    if (prn > kMaxPrn) return;
+    int sum = 0;
+    if (prn > 0)
+        for (int m = 0; m < kCodeLen; ++m) sum += codes[prn * kCodeLen + m] ? -1 : 1;
+    dck[prn] = ldexpf(2048.f, -ecs) * (float)sum / (float)kCodeLen;
+}
+
+hipError_t launch_tables_h(const float4 *d_cs, const uint8_t *d_codes, void *d_tw_h, void *d_cs_h, int cs_exp,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(k_code_dc_h, dim3(1), dim3(64), 0, s, d_codes, (float *)((char *)d_cs_h + kCsHSpecBytes),
+                       cs_exp);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_twiddles_h, dim3((kTwElems + 255) / 256), dim3(256), 0, s, (hc2 *)d_tw_h);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_code_spectra_h, dim3(((kMaxPrn + 1) * 512 + 255) / 256), dim3(256), 0, s, d_cs,
                        (uint4 *)d_cs_h, cs_exp);
@@ -785,11 +801,17 @@ __device__ __forceinline__ void stage_twiddles_h(hc2 *s_tw, const hc2 *tw, int t
 }
 
 // Forward transforms, two polyphase vectors per wave (the low and high
-// halves).  Output: Gh[vec] in the packed storage order and the vector's
-// exponent E[vec].
+// halves).  Each vector is transformed with its mean S/1023 removed (S its
+// sum over the 1023 values), scaled by 2^-e with e from the l1 norm of the
+// mean-removed vector plus |S|; the correlation adds the mean's part back as
+// the constant S/1023 * sum(code) of every lag.  (A strong DC component would
+// otherwise cancel in the inverse transform against values far larger than
+// the result, and the FP16 roundings of those values would dominate it.)
+// Output: Gh[vec] in the packed storage order, the vector's exponent E[vec]
+// and its scaled sum Dc[vec] = S * 2^-e.
 // three waves per SIMD (167 VGPRs with a 20-byte spill): 15% faster than two
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_fft_poly_h(const int2 *F, const hc2 *tw, uint4 *Gh, int *E,
-                                                    const BatchHdr *H)
+                                                    float2 *Dc, const BatchHdr *H)
 {
     __shared__ hc2 s_tw[kTwElems];
     __shared__ hc2 s_xb[4][kXbufElemsQ];
@@ -803,18 +825,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         const bool has_b = vb < n_vec;
         const int2 *sa = F + va * kPolyLen, *sb = F + vb * kPolyLen;
         int2 a[16], b[16];
-        float na = 0.f, nb = 0.f;
+        float sar = 0.f, sai = 0.f, sbr = 0.f, sbi = 0.f;
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
             for (int k2b = 0; k2b < 4; ++k2b) {
-                const int idx = l + 64 * u + 256 * k2b;
+                const int idx = l + 64 * u + 256 * k2b;  // element 1023 is zero
                 a[4 * u + k2b] = sa[idx];
                 b[4 * u + k2b] = has_b ? sb[idx] : make_int2(0, 0);
-                na += fabsf((float)a[4 * u + k2b].x) + fabsf((float)a[4 * u + k2b].y);
-                nb += fabsf((float)b[4 * u + k2b].x) + fabsf((float)b[4 * u + k2b].y);
+                sar += (float)a[4 * u + k2b].x;
+                sai += (float)a[4 * u + k2b].y;
+                sbr += (float)b[4 * u + k2b].x;
+                sbi += (float)b[4 * u + k2b].y;
             }
-        const int ea = l1_exponent(wave_sum(na)), eb = l1_exponent(wave_sum(nb));
+        const float Sar = wave_sum(sar), Sai = wave_sum(sai), Sbr = wave_sum(sbr), Sbi = wave_sum(sbi);
+        // IEEE division: a constant vector's mean is its value exactly
+        const float mar = Sar / (float)kCodeLen, mai = Sai / (float)kCodeLen;
+        const float mbr = Sbr / (float)kCodeLen, mbi = Sbi / (float)kCodeLen;
+        float na = 0.f, nb = 0.f;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int k2b = 0; k2b < 4; ++k2b)
+                if (l + 64 * u + 256 * k2b < kCodeLen) {
+                    na += fabsf((float)a[4 * u + k2b].x - mar) + fabsf((float)a[4 * u + k2b].y - mai);
+                    nb += fabsf((float)b[4 * u + k2b].x - mbr) + fabsf((float)b[4 * u + k2b].y - mbi);
+                }
+        const int ea = l1_exponent(wave_sum(na) + fabsf(Sar) + fabsf(Sai));
+        const int eb = l1_exponent(wave_sum(nb) + fabsf(Sbr) + fabsf(Sbi));
         const float fa = ldexpf(1.f, -ea), fb = ldexpf(1.f, -eb);
         hc2 v[32];
         const __half2 zero = __floats2half2_rn(0.f, 0.f);
@@ -824,8 +862,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             for (int k2b = 0; k2b < 8; ++k2b) {
                 if (k2b < 4) {
                     const int2 x = a[4 * u + k2b], y = b[4 * u + k2b];
-                    v[8 * u + k2b] = make_hc2(__floats2half2_rn((float)x.x * fa, (float)y.x * fb),
-                                              __floats2half2_rn((float)x.y * fa, (float)y.y * fb));
+                    // the zero element 1023 stays zero
+                    const bool in = l + 64 * u + 256 * k2b < kCodeLen;
+                    const float xr = in ? ((float)x.x - mar) * fa : 0.f, xi = in ? ((float)x.y - mai) * fa : 0.f;
+                    const float yr = in ? ((float)y.x - mbr) * fb : 0.f, yi = in ? ((float)y.y - mbi) * fb : 0.f;
+                    v[8 * u + k2b] = make_hc2(__floats2half2_rn(xr, yr), __floats2half2_rn(xi, yi));
                 } else {
                     v[8 * u + k2b] = make_hc2(zero, zero);
                 }
@@ -843,7 +884,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         }
         if (l == 0) {
             E[va] = ea;
-            if (has_b) E[vb] = eb;
+            Dc[va] = make_float2(Sar * fa, Sai * fa);
+            if (has_b) {
+                E[vb] = eb;
+                Dc[vb] = make_float2(Sbr * fb, Sbi * fb);
+            }
         }
     }
 }
@@ -861,7 +906,9 @@ __device__ __forceinline__ hc2 c_mul_bcast(__half2 g, hc2 c)
 template <int PT>
 __global__ __launch_bounds__(64 * kCorrWavesH) __attribute__((amdgpu_waves_per_eu(PT == 2 ? 3 : 1))) void k_corr_h(const ReqDesc *__restrict__ R, BatchHdr *H,
                                                              const long long *pre, const uint4 *Gh,
-                                                             const int *E, const uint4 *__restrict__ CSh,
+                                                             const int *E, const float2 *Dc,
+                                                             const uint4 *__restrict__ CSh,
+                                                             const float *__restrict__ dck,
                                                              const hc2 *__restrict__ tw, float out_scale)
 {
     static_assert(PT % 2 == 0, "PRNs go in pairs");
@@ -917,6 +964,14 @@ __global__ __launch_bounds__(64 * kCorrWavesH) __attribute__((amdgpu_waves_per_e
         for (int p = 0; p < PT; ++p)
 #pragma unroll
             for (int i = 0; i < 16; ++i) acc[p][i] = 0.f;
+        // per PRN: the lag-independent part of the inverse output per unit of
+        // the scaled block sum, 2048 * 2^-ecs * sum(code) / 1023
+        float kdc[PT];
+#pragma unroll
+        for (int p = 0; p < PT; ++p) {
+            const int pi = ptile * PT + p;
+            kdc[p] = dck[pi < d.n_prn ? d.prns[pi] : 0];
+        }
 
         if (active) {
             const long long v0 = d.vec_off + (long long)k * d.Nnc * spc + s;
@@ -924,8 +979,11 @@ __global__ __launch_bounds__(64 * kCorrWavesH) __attribute__((amdgpu_waves_per_e
             for (int b = 0; b < d.Nnc; ++b) {
                 const long long vec = v0 + (long long)b * spc;
                 const float sc = ldexpf(1.f, 2 * E[vec]);
+                const float2 ds = Dc[vec];
 #pragma unroll
                 for (int pp = 0; pp < NP; ++pp) {
+                    const __half2 dre = __floats2half2_rn(kdc[2 * pp] * ds.x, kdc[2 * pp + 1] * ds.x);
+                    const __half2 dim = __floats2half2_rn(kdc[2 * pp] * ds.y, kdc[2 * pp + 1] * ds.y);
                     const uint4 *gq = Gh + vec * 512;
                     asm volatile("" : "+v"(gq));
                     phase_barrier();
@@ -948,7 +1006,7 @@ __global__ __launch_bounds__(64 * kCorrWavesH) __attribute__((amdgpu_waves_per_e
 #pragma unroll
                         for (int k2b = 0; k2b < 4; ++k2b) {
                             const hc2 o = z[8 * u + k2b];
-                            const float2 re = __half22float2(o.re), im = __half22float2(o.im);
+                            const float2 re = __half22float2(__hadd2(o.re, dre)), im = __half22float2(__hadd2(o.im, dim));
                             const float ta = fmaf(re.x, re.x, im.x * im.x);
                             const float tb = fmaf(re.y, re.y, im.y * im.y);
                             acc[2 * pp][4 * u + k2b] = fmaf(ta, sc, acc[2 * pp][4 * u + k2b]);
@@ -1121,8 +1179,14 @@ hipError_t launch_code_spectra_x_pack(const double2 *d_tmp, void *d_cs_x, int cs
 }
 
 // Forward transforms, one polyphase vector per wave: the vector in LDS, its
-// exponent from the exact l1 norm, the Good-Thomas gather into fragments,
-// two passes, and the spectrum stored as fragments with its exponent.
+// sum S and mean S/1023, the exponent from the l1 norm of the mean-removed
+// vector plus |S|, the Good-Thomas gather of the mean-removed vector into
+// fragments, two passes, and the spectrum stored as fragments with its
+// exponent.  The DC bin is stored as S itself.  Removing the mean keeps the
+// FP16 weights from leaking a strong DC component into the other bins: the
+// code spectra are +-1 at DC and about 32 elsewhere, so a leak of a few
+// 10^-6 of the DC amplitude into every bin would reach percents of the
+// correlation of a DC-dominated block (a constant offset in the samples).
 __global__ __launch_bounds__(256) void k_fft_x(const int2 *F, const pfa::u4 *__restrict__ fr, pfa::u4 *Gx, int *E,
                                                const BatchHdr *H)
 {
@@ -1134,15 +1198,24 @@ __global__ __launch_bounds__(256) void k_fft_x(const int2 *F, const pfa::u4 *__r
     int2 *xs = s_x[w];
     for (long long vec = (long long)blockIdx.x * 4 + w; vec < n_vec; vec += (long long)gridDim.x * 4) {
         const int2 *src = F + vec * kPolyLen;
-        float nrm = 0.f;
+        int2 v[kPolyLen / 64];
+        float sr = 0.f, si = 0.f;
         lds_fence();  // the previous vector's gathers are complete
 #pragma unroll
         for (int i = 0; i < kPolyLen / 64; ++i) {
-            const int2 v = src[l + 64 * i];
-            xs[l + 64 * i] = v;
-            nrm += fabsf((float)v.x) + fabsf((float)v.y);
+            v[i] = src[l + 64 * i];  // element 1023 is zero
+            xs[l + 64 * i] = v[i];
+            sr += (float)v[i].x;
+            si += (float)v[i].y;
         }
-        const int e = l1_exponent(wave_sum(nrm));
+        const float Sr = wave_sum(sr), Si = wave_sum(si);
+        // IEEE division: a constant vector's mean is its value exactly
+        const float mr = Sr / (float)kCodeLen, mi = Si / (float)kCodeLen;
+        float nrm = 0.f;
+#pragma unroll
+        for (int i = 0; i < kPolyLen / 64; ++i)
+            if (l + 64 * i < kCodeLen) nrm += fabsf((float)v[i].x - mr) + fabsf((float)v[i].y - mi);
+        const int e = l1_exponent(wave_sum(nrm) + fabsf(Sr) + fabsf(Si));
         const float f = ldexpf(1.f, -e);
         lds_fence();
         pfa::u4 a1[3][2];
@@ -1154,16 +1227,23 @@ __global__ __launch_bounds__(256) void k_fft_x(const int2 *F, const pfa::u4 *__r
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int n1 = 16 * s + 4 * g + j, n2 = 16 * t + c;
-                    int2 v = make_int2(0, 0);
-                    if (n1 < pfa::kN1 && n2 < pfa::kN2) v = xs[pfa::time_index(n1, n2)];
-                    re[j] = (float)v.x * f;
-                    im[j] = (float)v.y * f;
+                    re[j] = 0.f;
+                    im[j] = 0.f;
+                    if (n1 < pfa::kN1 && n2 < pfa::kN2) {
+                        const int2 x = xs[pfa::time_index(n1, n2)];
+                        re[j] = ((float)x.x - mr) * f;
+                        im[j] = ((float)x.y - mi) * f;
+                    }
                 }
                 a1[t][s] = pfa::u4{pfa::pack2(re[0], re[1]), pfa::pack2(re[2], re[3]), pfa::pack2(im[0], im[1]),
                                    pfa::pack2(im[2], im[3])};
             }
         pfa::f4 o[2][6];
         pfa::forward(a1, B, o);
+        if (l == 0) {  // bin 0 (a = 0, b = 0): the vector's sum
+            o[0][0].x = Sr * f;
+            o[0][1].x = Si * f;
+        }
         pfa::u4 *dst = Gx + vec * pfa::kUnits;
 #pragma unroll
         for (int t = 0; t < 2; ++t)
@@ -1788,6 +1868,270 @@ __global__ __launch_bounds__(kSynthThreads) void k_fd_synth(const ReqDesc *__res
 }
 
 // ===========================================================================
+// General sample rates: fs a whole number of kHz that is not k * 1.023 MHz
+// (k <= 16), so the replica has no whole number of samples per chip and the
+// polyphase form does not apply.  The length-N circular correlation of each
+// folded block is done on zero-padded transforms of length M = 2^ceil(log2
+// 2N): the block f at [0, N), the replica over two code periods cc[j] =
+// c[j mod N] at [0, 2N), and
+//   R[tau] = sum_n f[n] c[(n - tau) mod N] = IDFT_M(DFT_M(f) conj(DFT_M(cc)))[M - N + tau] / M
+// (no wrap-around because M >= 2N).  FP32 throughout, in every context
+// precision.  A transform of P <= 16384 points runs in one workgroup's LDS
+// (1024 threads, radix-4 passes with one radix-2 pass for odd log2 P); for
+// M = 32768 the even and odd bins are two 16384-point transforms:
+//   X[2k] = DFT_P(x[j] + x[j + P])[k],  X[2k + 1] = DFT_P((x[j] - x[j + P]) W_M^j)[k],
+// and the inverse's upper half (the only outputs needed, as N <= M/2) is
+//   out[P + k] = A[k] - W_M^-k B[k],  A = IDFT_P(Z even bins), B = IDFT_P(Z odd bins).
+// The forward transforms are decimation in frequency (natural order in,
+// digit-reversed out) and the inverse is their exact adjoint (digit-reversed
+// in, natural out), so spectra are multiplied in the order they are stored.
+// ===========================================================================
+
+// W_{4s}^(j m) from the table of W_32768^i (forward sign)
+__device__ __forceinline__ float2 gen_tw(const float2 *tw, int s, int jm)
+{
+    return tw[(jm * (kGenTwLen / 4 / s)) & (kGenTwLen - 1)];
+}
+
+// Forward radix-4 pass, span s: (x0..x3) at i0 + {0, s, 2s, 3s} -> the four
+// outputs of the 4-point DFT times W_{4s}^(j r), r = 0..3, in place.
+__device__ __forceinline__ void gen_fwd4(float2 *x, int P, int s, const float2 *tw)
+{
+    for (int t = threadIdx.x; t < P / 4; t += kGenThreads) {
+        const int j = t & (s - 1), i0 = ((t - j) << 2) + j;
+        const float2 x0 = x[i0], x1 = x[i0 + s], x2 = x[i0 + 2 * s], x3 = x[i0 + 3 * s];
+        const float2 a0 = c_add(x0, x2), a1 = c_sub(x0, x2), b0 = c_add(x1, x3);
+        const float2 d = c_sub(x1, x3), b1 = make_float2(d.y, -d.x);  // -i (x1 - x3)
+        x[i0] = c_add(a0, b0);
+        x[i0 + s] = c_mul(c_add(a1, b1), gen_tw(tw, s, j));
+        x[i0 + 2 * s] = c_mul(c_sub(a0, b0), gen_tw(tw, s, 2 * j));
+        x[i0 + 3 * s] = c_mul(c_sub(a1, b1), gen_tw(tw, s, 3 * j));
+    }
+}
+
+// Adjoint of gen_fwd4 (inverse transform, unnormalised).
+__device__ __forceinline__ void gen_inv4(float2 *x, int P, int s, const float2 *tw)
+{
+    for (int t = threadIdx.x; t < P / 4; t += kGenThreads) {
+        const int j = t & (s - 1), i0 = ((t - j) << 2) + j;
+        const float2 u0 = x[i0];
+        const float2 u1 = c_mulc(x[i0 + s], gen_tw(tw, s, j));
+        const float2 u2 = c_mulc(x[i0 + 2 * s], gen_tw(tw, s, 2 * j));
+        const float2 u3 = c_mulc(x[i0 + 3 * s], gen_tw(tw, s, 3 * j));
+        const float2 p0 = c_add(u0, u2), p1 = c_sub(u0, u2), q0 = c_add(u1, u3);
+        const float2 d = c_sub(u1, u3), q1 = make_float2(-d.y, d.x);  // +i (u1 - u3)
+        x[i0] = c_add(p0, q0);
+        x[i0 + s] = c_add(p1, q1);
+        x[i0 + 2 * s] = c_sub(p0, q0);
+        x[i0 + 3 * s] = c_sub(p1, q1);
+    }
+}
+
+// Radix-2 pass of span 1 (its own adjoint).
+__device__ __forceinline__ void gen_pass2(float2 *x, int P)
+{
+    for (int t = threadIdx.x; t < P / 2; t += kGenThreads) {
+        const float2 x0 = x[2 * t], x1 = x[2 * t + 1];
+        x[2 * t] = c_add(x0, x1);
+        x[2 * t + 1] = c_sub(x0, x1);
+    }
+}
+
+// P-point forward transform in LDS (natural order in, digit-reversed out).
+// Callers synchronise before (the data are written) and after.
+__device__ void gen_forward(float2 *x, int P, const float2 *tw)
+{
+    int s = P / 4;
+    for (; s >= 1; s /= 4) {
+        gen_fwd4(x, P, s, tw);
+        __syncthreads();
+    }
+    if ((P & 0x55555555) == 0) {  // log2 P odd: the last radix-4 span was 2
+        gen_pass2(x, P);
+        __syncthreads();
+    }
+}
+
+// Exact adjoint of gen_forward: digit-reversed in, natural order out,
+// unnormalised exp(+2 pi i nk / P).
+__device__ void gen_inverse(float2 *x, int P, const float2 *tw)
+{
+    int s;
+    if ((P & 0x55555555) == 0) {
+        gen_pass2(x, P);
+        __syncthreads();
+        s = 2;
+    } else {
+        s = 1;
+    }
+    for (; s <= P / 4; s *= 4) {
+        gen_inv4(x, P, s, tw);
+        __syncthreads();
+    }
+}
+
+// Code spectra of a general-rate request: item = (request, PRN).
+// CC[p][h P + i] = DFT_M(cc)[bin of storage position i of half h].
+__global__ __launch_bounds__(kGenThreads) void k_gen_code(const ReqDesc *__restrict__ R, const BatchHdr *H,
+                                                          const long long *pre, const uint8_t *codes,
+                                                          const float2 *tw, float2 *gen)
+{
+    __shared__ float2 x[kGenLds];
+    const int n_req = H->n_req;
+    const long long total = H->total[kStGenC];
+    const long long *pst = pre + (long long)kStGenC * (n_req + 1);
+    for (long long it = blockIdx.x; it < total; it += gridDim.x) {
+        const int r = find_req(pst, n_req, it);
+        const ReqDesc &d = R[r];
+        const int pi = (int)(it - pst[r]);
+        const uint8_t *code = codes + (long long)d.prns[pi] * kCodeLen;
+        const int N = d.N, M = d.gen_M, P = d.gen_P;
+        const long long fs = (long long)N * 1000;
+        float2 *dst = gen + d.gen_c_off + (long long)pi * M;
+        // c[j mod N] for j < 2N, else 0
+        auto cc = [&](int j) -> float {
+            if (j >= 2 * N) return 0.f;
+            const long long n = j >= N ? j - N : j;
+            return code[(n * 1023000LL / fs) % kCodeLen] ? -1.f : 1.f;
+        };
+        for (int h = 0; h < M / P; ++h) {
+            __syncthreads();
+            for (int j = threadIdx.x; j < P; j += kGenThreads) {
+                if (M == P) {
+                    x[j] = make_float2(cc(j), 0.f);
+                } else if (h == 0) {
+                    x[j] = make_float2(cc(j) + cc(j + P), 0.f);
+                } else {
+                    const float v = cc(j) - cc(j + P);
+                    const float2 w = tw[j];  // W_M^j, M = 32768
+                    x[j] = make_float2(v * w.x, v * w.y);
+                }
+            }
+            __syncthreads();
+            gen_forward(x, P, tw);
+            for (int j = threadIdx.x; j < P; j += kGenThreads) dst[(long long)h * P + j] = x[j];
+        }
+    }
+}
+
+// Block spectra of a general-rate request: item = (request, Doppler bin,
+// block).  The carrier NCO, first mixing stage and fold of the block (the
+// integer arithmetic of the polyphase path), delayed circularly by the
+// code-Doppler shift if any, then the zero-padded forward transform.
+__global__ __launch_bounds__(kGenThreads) void k_gen_x(const ReqDesc *__restrict__ R, const BatchHdr *H,
+                                                       const long long *pre, const uint32_t *lut, const float2 *tw,
+                                                       float2 *gen)
+{
+    __shared__ float2 x[kGenLds];
+    __shared__ uint32_t s_lut[1024];
+    for (int i = threadIdx.x; i < 1024; i += kGenThreads) s_lut[i] = lut[i];
+    const int n_req = H->n_req;
+    const long long total = H->total[kStGenX];
+    const long long *pst = pre + (long long)kStGenX * (n_req + 1);
+    for (long long it = blockIdx.x; it < total; it += gridDim.x) {
+        const int r = find_req(pst, n_req, it);
+        const ReqDesc &d = R[r];
+        const long long local = it - pst[r];
+        const int k = (int)(local / d.Nnc), b = (int)(local % d.Nnc);
+        const int N = d.N, M = d.gen_M, P = d.gen_P;
+        const uint32_t D = d.dk[k];
+        const int shift = d.cshift ? d.cshift[(long long)k * d.Nnc + b] : 0;
+        float2 f[kGenMaxN / kGenThreads];  // the folded block, n = tid + 1024 i
+        __syncthreads();  // s_lut staged; the previous item's reads of x are done
+#pragma unroll
+        for (int i = 0; i < kGenMaxN / kGenThreads; ++i) {
+            const int n = threadIdx.x + kGenThreads * i;
+            f[i] = make_float2(0.f, 0.f);
+            if (n < N) {
+                int m = n - shift;
+                if (m < 0) m += N;
+                const int2 v = wipe_fold_one(d.samples, d.fmt, N, d.Tc, s_lut, D, b, m);
+                f[i] = make_float2((float)v.x, (float)v.y);
+            }
+        }
+        float2 *dst = gen + d.gen_x_off + local * M;
+        for (int h = 0; h < M / P; ++h) {
+#pragma unroll
+            for (int i = 0; i < kGenMaxN / kGenThreads; ++i) {
+                const int n = threadIdx.x + kGenThreads * i;
+                if (n < P) {
+                    // N <= P: the block has no samples at n + P
+                    float2 v = f[i];
+                    if (h == 1) v = c_mul(v, tw[n]);
+                    x[n] = v;
+                }
+            }
+            __syncthreads();
+            gen_forward(x, P, tw);
+            for (int j = threadIdx.x; j < P; j += kGenThreads) dst[(long long)h * P + j] = x[j];
+            __syncthreads();
+        }
+    }
+}
+
+// Correlation of a general-rate request: item = (request, PRN, Doppler bin);
+// over the blocks, Z = X conj(CC), the inverse transform, |.|^2 of the lags'
+// outputs summed in registers; the grid gets sum |out|^2 2^-24 / M^2.
+__global__ __launch_bounds__(kGenThreads) void k_gen_corr(const ReqDesc *__restrict__ R, const BatchHdr *H,
+                                                          const long long *pre, const float2 *tw,
+                                                          const float2 *gen)
+{
+    __shared__ float2 x[kGenLds];
+    constexpr int kPer = kGenMaxN / kGenThreads;
+    const int n_req = H->n_req;
+    const long long total = H->total[kStGenCorr];
+    const long long *pst = pre + (long long)kStGenCorr * (n_req + 1);
+    for (long long it = blockIdx.x; it < total; it += gridDim.x) {
+        const int r = find_req(pst, n_req, it);
+        const ReqDesc &d = R[r];
+        const long long local = it - pst[r];
+        const int pi = (int)(local / d.n_dopp), k = (int)(local % d.n_dopp);
+        const int N = d.N, M = d.gen_M, P = d.gen_P;
+        const float2 *C = gen + d.gen_c_off + (long long)pi * M;
+        float acc[kPer];
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) acc[i] = 0.f;
+        for (int b = 0; b < d.Nnc; ++b) {
+            const float2 *X = gen + d.gen_x_off + ((long long)k * d.Nnc + b) * M;
+            float2 a[kPer];
+            for (int h = 0; h < M / P; ++h) {
+                __syncthreads();  // the previous inverse's outputs are read
+                for (int j = threadIdx.x; j < P; j += kGenThreads)
+                    x[j] = c_mulc(X[(long long)h * P + j], C[(long long)h * P + j]);
+                __syncthreads();
+                gen_inverse(x, P, tw);
+                // lag tau is output M - N + tau; for M = 2P it is P + kk, kk = P - N + tau
+#pragma unroll
+                for (int i = 0; i < kPer; ++i) {
+                    const int tau = threadIdx.x + kGenThreads * i;
+                    if (tau < N) {
+                        const int kk = P - N + tau;
+                        const float2 o = x[kk];
+                        if (M == P) {
+                            acc[i] = fmaf(o.x, o.x, fmaf(o.y, o.y, acc[i]));
+                        } else if (h == 0) {
+                            a[i] = o;
+                        } else {
+                            // A - W_M^-kk B
+                            const float2 v = c_sub(a[i], c_mulc(o, tw[kk]));
+                            acc[i] = fmaf(v.x, v.x, fmaf(v.y, v.y, acc[i]));
+                        }
+                    }
+                }
+            }
+        }
+        // 2^-24 (LUT scale) / M^2 (two unnormalised transforms), an exact power of two
+        const float scale = ldexpf(1.f, -24 - 2 * (31 - __clz(M)));
+        GNSS_GLOBAL float *row = gmem(d.grid) + ((long long)pi * d.n_dopp + k) * N;
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int tau = threadIdx.x + kGenThreads * i;
+            if (tau < N) row[tau] = acc[i] * scale;
+        }
+    }
+}
+
+// ===========================================================================
 // detection: column max over Doppler, argmax, second peak, mean; refinement
 // ===========================================================================
 // Work item = (request, PRN, block of 256 lags).  Q[tau] = max_k P (lowest k
@@ -2052,6 +2396,8 @@ hipError_t launch_batch(const Launch &L, const Tables &T, int2 *d_F, void *d_G, 
     // FP16 modes: packed spectra, then the per-vector exponents
     uint4 *d_Gh = (uint4 *)d_G;
     int *d_E = (int *)((char *)d_G + g_spectra_bytes(L.total[kStVec], L.precision));
+    float2 *d_Dc = (float2 *)((char *)d_E + round256((size_t)L.total[kStVec] * 4));  // GNSS_FP16 only
+    const float *d_dck = h ? (const float *)((const char *)T.cs_h + kCsHSpecBytes) : nullptr;
     hipError_t e;
     const bool pers = L.persistent != 0;
     auto mark = [&](int i) -> hipError_t { return marks ? hipEventRecord(marks[i], s) : hipSuccess; };
@@ -2086,10 +2432,24 @@ hipError_t launch_batch(const Launch &L, const Tables &T, int2 *d_F, void *d_G, 
         static int cap = 0;
         if (!cap) cap = occupancy(k_fft_poly_h, 256, n_cu);
         hipLaunchKernelGGL(k_fft_poly_h, dim3(grid_for((L.total[kStVec] + 7) / 8, cap, false)), dim3(256), 0,
-                           s, d_F, (const hc2 *)T.tw_h, d_Gh, d_E, L.hdr);
+                           s, d_F, (const hc2 *)T.tw_h, d_Gh, d_E, d_Dc, L.hdr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (L.total[kStGenX] > 0) {  // general rates: code spectra and block spectra
+        float2 *d_gen = (float2 *)((char *)d_G + L.gen_off);
+        hipLaunchKernelGGL(k_gen_code, dim3(grid_for(L.total[kStGenC], 65535, false)), dim3(kGenThreads), 0, s,
+                           L.reqs, L.hdr, L.pre, T.codes, T.tw_gen, d_gen);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_gen_x, dim3(grid_for(L.total[kStGenX], 65535, false)), dim3(kGenThreads), 0, s,
+                           L.reqs, L.hdr, L.pre, d_lut, T.tw_gen, d_gen);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if ((e = mark(2)) != hipSuccess) return e;
+    if (L.total[kStGenCorr] > 0) {
+        hipLaunchKernelGGL(k_gen_corr, dim3(grid_for(L.total[kStGenCorr], 65535, false)), dim3(kGenThreads), 0,
+                           s, L.reqs, L.hdr, L.pre, T.tw_gen, (const float2 *)((char *)d_G + L.gen_off));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     if (L.total[kStCorr] > 0 && x) {
         // the frequency-domain variant wipes with unit exponentials (no LUT scale 2^12)
         const float osc = ldexpf(1.f, 2 * T.cs_exp - (L.fd ? 0 : 24)) / (float)(kCodeLen * kCodeLen);
@@ -2115,12 +2475,12 @@ hipError_t launch_batch(const Launch &L, const Tables &T, int2 *d_F, void *d_G, 
             static int cap = 0;
             if (!cap) cap = occupancy(k_corr_h<2>, 64 * kCorrWavesH, n_cu);
             hipLaunchKernelGGL(k_corr_h<2>, dim3(grid_for(L.total[kStCorr], cap, pers)), dim3(64 * kCorrWavesH),
-                               0, s, L.reqs, L.hdr, L.pre, d_Gh, d_E, (const uint4 *)T.cs_h, (const hc2 *)T.tw_h, osc);
+                               0, s, L.reqs, L.hdr, L.pre, d_Gh, d_E, d_Dc, (const uint4 *)T.cs_h, d_dck, (const hc2 *)T.tw_h, osc);
         } else {
             static int cap = 0;
             if (!cap) cap = occupancy(k_corr_h<4>, 64 * kCorrWavesH, n_cu);
             hipLaunchKernelGGL(k_corr_h<4>, dim3(grid_for(L.total[kStCorr], cap, pers)), dim3(64 * kCorrWavesH),
-                               0, s, L.reqs, L.hdr, L.pre, d_Gh, d_E, (const uint4 *)T.cs_h, (const hc2 *)T.tw_h, osc);
+                               0, s, L.reqs, L.hdr, L.pre, d_Gh, d_E, d_Dc, (const uint4 *)T.cs_h, d_dck, (const hc2 *)T.tw_h, osc);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     } else if (L.total[kStCorr] > 0) {

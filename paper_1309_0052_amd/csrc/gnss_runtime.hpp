@@ -63,6 +63,8 @@ struct BatchHost {
     size_t F_bytes = 0, G_bytes = 0, Q_bytes = 0, K_bytes = 0, part_bytes = 0, grid_bytes = 0;
     int fd = 0;          // frequency-domain Doppler requested
     int fd_bad = -1;     // first request it cannot serve, or -1
+    int gen_first = -1;  // first request at a general rate (zero-padded transforms), or -1
+    size_t gen_off = 0;  // bytes of the spectrum buffer before the general-rate region
     // host-computed tables copied with the descriptors: carrier NCO steps of
     // every (request, Doppler bin) and, with code-Doppler compensation, the
     // lag shift of every (request, bin, block); offsets in elements
@@ -104,6 +106,7 @@ struct gnss_ctx {
     void *d_frags_x = nullptr;  // exact-length contexts: weight fragments of the 31/33-point passes
     void *d_cs_x = nullptr;     //   1023-point code spectra * 2^-cs_exp, fragment layout
     int cs_exp = 0;
+    float2 *d_tw_gen = nullptr; // general rates: W_32768^j, j < 32768
     gnss_rt::Workspace ws;      // synchronous and device-buffer calls
     // allocation-free searches: this device's copy of the static scratch
     // array, and a workspace of views into it whose pinned metadata staging

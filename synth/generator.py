@@ -210,17 +210,19 @@ def weak_complex_int8(code_fn, seed: int = 2):
 
 def batch_workload(code_fn, seed: int = 4, n: int = 256, ms_range=(20, 200), rates=None,
                    prn_range=(8, 32), window_khz=(2.0, 10.0), planted_range=(1, 6),
-                   cn0_range=(30.0, 45.0)):
+                   cn0_range=(30.0, 45.0), workers: int = 1):
     """Heterogeneous snapshots for batched search: lengths U{20..200} ms, fs
     uniform over {4.092, 8.184, 16.368} MHz, format uniform over real 2-bit
     (f_IF = fs/4) and complex int8 (f_IF = 0), PRN subsets of U{8..32} PRNs
     from 1-32, Doppler window +-W with W ~ U[2, 10] kHz snapped to 500 Hz,
     1-6 planted PRNs inside the subset at C/N0 U[30, 45] dB-Hz with Doppler
     inside the window; searched with 1 ms coherent x L non-coherent blocks,
-    500 Hz bins.  Returns a list of (Snapshot, Search)."""
+    500 Hz bins.  Returns a list of (Snapshot, Search).  workers > 1 generates
+    the snapshots on that many threads (the same snapshots: every one is drawn
+    from its own seed)."""
     rates = rates or [4092000, 8184000, 16368000]
     rng = np.random.default_rng([seed, 4])
-    out = []
+    jobs = []
     for i in range(n):
         L = int(rng.integers(ms_range[0], ms_range[1] + 1))
         fs = int(rates[int(rng.integers(0, len(rates)))])
@@ -237,7 +239,13 @@ def batch_workload(code_fn, seed: int = 4, n: int = 256, ms_range=(20, 200), rat
                            cn0_dbhz=float(rng.uniform(*cn0_range)),
                            carrier_phase=float(rng.uniform(0.0, 2.0 * np.pi)))
                    for p in pl_prns]
-        snap = make_snapshot(int(rng.integers(0, 2 ** 31)), fmt, fs, f_if, float(L), planted,
-                             code_fn)
-        out.append((snap, Search(prns, -W, W, 500.0, 1, L)))
-    return out
+        jobs.append(((int(rng.integers(0, 2 ** 31)), fmt, fs, f_if, float(L), planted),
+                     Search(prns, -W, W, 500.0, 1, L)))
+    if workers <= 1:
+        return [(make_snapshot(*a, code_fn), srch) for a, srch in jobs]
+    from concurrent.futures import ThreadPoolExecutor
+
+    chips = {p: np.asarray(code_fn(p), np.uint8) for p in range(1, 33)}  # code_fn stays on this thread
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        snaps = list(ex.map(lambda a: make_snapshot(*a, chips.__getitem__), [a for a, _ in jobs]))
+    return [(snap, srch) for snap, (_, srch) in zip(snaps, jobs)]

@@ -61,8 +61,9 @@ def _acquire(x, **kw):
     (dict(fs=4092500.0), G.GNSS_EINVAL),          # not a multiple of 1 kHz
     (dict(fs=4092000.5), G.GNSS_EINVAL),          # not an integer
     (dict(fs=-4092000.0), G.GNSS_EINVAL),
-    (dict(fs=5000000.0), G.GNSS_ENOTSUP),         # not k * 1.023 MHz
-    (dict(fs=17391000.0), G.GNSS_ENOTSUP),        # 17 samples per chip
+    (dict(fs=16385000.0), G.GNSS_ENOTSUP),        # not k * 1.023 MHz and N > 16384
+    (dict(fs=17391000.0), G.GNSS_ENOTSUP),        # 17 samples per chip: N > 16384
+    (dict(fs=5000000.0), G.GNSS_EINVAL),          # a general rate: 50000 samples needed
     (dict(prns=[0]), G.GNSS_EINVAL),
     (dict(prns=[38]), G.GNSS_EINVAL),
     (dict(prns=list(range(1, 38)) * 2), G.GNSS_EINVAL),  # 74 > 64

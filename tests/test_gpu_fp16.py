@@ -145,27 +145,31 @@ def test_block_exponents_change_between_blocks(ctx16, seq):
 
 
 @pytest.mark.timeout(600)
-def test_block_exponents_at_full_scale_and_longest_blocks(ctx16):
+@pytest.mark.parametrize("kinds", [("one", "full", "zero", "noise"), ("one", "tone", "zero", "noise")],
+                         ids=["constants", "tone"])
+def test_block_exponents_at_full_scale_and_longest_blocks(ctx16, kinds):
     """The longest coherent blocks (64 ms at 16.368 MHz) at the extremes of the
-    per-vector exponents: a constant of 1 (exponent 28), a full-scale complex
-    tone at 5 kHz, which folds coherently (35: the sums are scaled down by
-    2^-14), an all-zero block (exponent 0, more than 2^30 below the largest:
-    its zero power is dropped) and small noise (24: scaled up by 2^22).
-    Within the mode's bound of the FP64 oracle, and finite.  (A full-scale
-    constant instead of the tone puts all its power in the DC bin, where the
-    code spectrum is +-1 against ~32 elsewhere, so its FP16 rounding is about
-    1.6% relative: that input tests the code spectrum's precision, not the
-    block scaling.)"""
+    per-vector exponents: a constant of 1 (exponent 28), a full-scale constant
+    or a full-scale complex tone at 5 kHz, which folds coherently (35: the
+    sums are scaled down by 2^-14), an all-zero block (exponent 0, more than
+    2^30 below the largest: its zero power is dropped) and small noise (24:
+    scaled up by 2^22).  Within the mode's bound of the FP64 oracle, and
+    finite.  The constants put almost all of a block's power in the DC bin,
+    where the code spectrum is +-1 against ~32 elsewhere: both modes remove
+    each vector's mean before the FP16 transform, which keeps the FP16
+    weights from leaking that bin into the others."""
     fs, Tc = 16368000, 64
     N = fs // 1000
     L = Tc * N
     blocks = []
     rng = np.random.default_rng(64)
     ph = 2 * np.pi * 5000.0 * np.arange(L) / fs
-    for kind in ("one", "tone", "zero", "noise"):
+    for kind in kinds:
         b = np.zeros(2 * L, np.int8)
         if kind == "one":
             b[:] = 1
+        elif kind == "full":
+            b[:] = 127
         elif kind == "tone":
             b[0::2] = np.round(127 * np.cos(ph)).astype(np.int8)
             b[1::2] = np.round(127 * np.sin(ph)).astype(np.int8)
@@ -180,8 +184,55 @@ def test_block_exponents_at_full_scale_and_longest_blocks(ctx16):
     grid, _ = _run(ctx16, snap, srch)
     assert np.all(np.isfinite(grid))
     worst = grid_error(grid, P)
-    log("  %s, 64 ms blocks at the exponent extremes: max mixed error %.3e" % (NAME[ctx16.prec], worst))
+    log("  %s, 64 ms blocks %s: max mixed error %.3e" % (NAME[ctx16.prec], "/".join(kinds), worst))
     assert worst <= TOL[ctx16.prec]
+
+
+DC_CASES = [
+    # name, fmt, fs, f_if, DC offset (I, Q) added before quantisation, in noise sigmas
+    ("cplx_offset", O.CPLX_I8, 16368000, 0.0, (3.0, -2.0)),
+    ("cplx_large_offset", O.CPLX_I8, 4092000, 0.0, (6.0, 5.0)),
+    ("real_offset", O.REAL_I8, 4092000, 0.0, (1.5, 0.0)),
+]
+
+
+@pytest.mark.parametrize("case", DC_CASES, ids=[c[0] for c in DC_CASES])
+def test_dc_offset_records_match_direct_oracle(ctx16, case):
+    """Records with a constant offset in the samples (an ordinary front-end
+    imperfection) searched over bins that include the carrier's own
+    frequency, where the offset folds into each block's DC bin: within the
+    mode's bound of the FP64 direct oracle, the planted satellites found."""
+    name, fmt, fs, f_if, (oi, oq) = case
+    N = fs // 1000
+    Tc, Nnc = 2, 3
+    rng = np.random.default_rng(sum(name.encode()))
+    n = Tc * Nnc * N + N // 2
+    pl = [synth.Planted(prn=p, code_phase=int(rng.integers(0, N)), doppler_hz=d, cn0_dbhz=52.0,
+                        carrier_phase=float(rng.uniform(0, 2 * np.pi))) for p, d in ((6, 500.0), (21, -1000.0))]
+    prns = [6, 21, 14]
+    codes = {p.prn: O.ca_code(p.prn) for p in pl}
+    t = np.arange(n)
+    sig_i = rng.standard_normal(n) + oi
+    sig_q = rng.standard_normal(n) + oq
+    for p in pl:
+        c = 1.0 - 2.0 * codes[p.prn][((t - p.code_phase) * 1023000 // fs) % 1023].astype(np.float64)
+        amp = np.sqrt(2 * 10 ** (p.cn0_dbhz / 10) / fs)
+        ph = 2 * np.pi * (f_if + p.doppler_hz) * t / fs + p.carrier_phase
+        sig_i += amp * c * np.cos(ph)
+        sig_q += amp * c * np.sin(ph)
+    if fmt == O.CPLX_I8:
+        x = np.empty(2 * n, np.int8)
+        x[0::2] = np.clip(np.rint(16 * sig_i), -127, 127).astype(np.int8)
+        x[1::2] = np.clip(np.rint(16 * sig_q), -127, 127).astype(np.int8)
+    else:
+        x = np.clip(np.rint(16 * sig_i), -127, 127).astype(np.int8)
+    snap = types.SimpleNamespace(samples=x, fmt=fmt, n=n, fs_hz=fs, f_if_hz=f_if, planted=pl)
+    srch = synth.Search(prns, -1500.0, 1500.0, 500.0, Tc, Nnc)
+    nd = O.n_doppler(srch.lo, srch.hi, srch.step)
+    grid, pk = _run(ctx16, snap, srch)
+    P = O.grid_direct(x, fmt, fs, f_if, prns, srch.lo, srch.step, nd, Tc, Nnc)
+    log("fp16 DC offset %s: fs=%d offset=(%.1f, %.1f) sigma" % (name, fs, oi, oq))
+    _check(grid, pk, P, srch, fs // 1023000, pl, ctx16.prec)
 
 
 def test_fp16_rejects_unknown_precision():

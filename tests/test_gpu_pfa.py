@@ -120,3 +120,33 @@ def test_dft1023_argument_errors(ctxx):
         with pytest.raises(G.GnssError) as ei:
             c32.dft1023(d.data_ptr(), e.data_ptr(), 1, False)
         assert ei.value.code == G.GNSS_ENOTSUP
+
+
+def test_dft1023_matches_the_fp16_rounding_model(ctxx):
+    """The numpy model of the mode's roundings (fp16_pfa_model.py: FP16 input
+    and weights, FP16 31-pass output, FP32 sums) reproduces the GPU transform
+    far below the FP16 error itself, including the leak of a constant's DC
+    bin into the other bins through the FP16 weights (the mechanism behind
+    the mean removal of the correlation path, test_fp16_dc_model.py)."""
+    import fp16_pfa_model as M
+
+    rng = np.random.default_rng(33)
+    rows = [rng.normal(size=1023) + 1j * rng.normal(size=1023) for _ in range(6)]
+    const = np.full(1023, 127.0 + 127.0j) * 2.0 ** 22
+    rows.append(const)
+    x = np.array(rows).astype(np.complex64).astype(np.complex128)
+    got = _dft(ctxx, x, False)
+    for i in range(len(rows)):
+        model = M.forward(x[i], mean_removed=False)
+        exact = np.fft.fft(x[i])
+        rms = np.sqrt(np.mean(np.abs(exact) ** 2))
+        d_model = np.max(np.abs(got[i] - model)) / rms
+        d_exact = np.max(np.abs(got[i] - exact)) / rms
+        log("  row %d: GPU vs model %.2e of RMS, GPU vs FP64 %.2e" % (i, d_model, d_exact))
+        assert d_model <= 0.2 * d_exact + 1e-6, (i, d_model, d_exact)
+    # the constant: the GPU's non-DC bins are the model's leak
+    leak_gpu = np.abs(got[-1][1:])
+    leak_model = np.abs(M.forward(x[-1], mean_removed=False)[1:])
+    log("  constant: max leak GPU %.3e, model %.3e of the DC bin" %
+        (leak_gpu.max() / abs(got[-1][0]), leak_model.max() / abs(got[-1][0])))
+    assert np.max(np.abs(got[-1][1:] - M.forward(x[-1], mean_removed=False)[1:])) <= 0.1 * leak_model.max()

@@ -151,3 +151,68 @@ def test_invalid_arguments_rejected():
         O.ca_code(38)
     with pytest.raises(ValueError):
         O.grid_direct(np.zeros(5000, np.int8), O.REAL_I8, 4092500, 0.0, [1], 0.0, 1.0, 1, 1, 1)
+
+
+# ---------------------------------------------------------------------------
+# sample rates that are not a multiple of the chip rate (any whole number of
+# kHz): the replica samples chip floor(n 1023000 / fs) and has no whole number
+# of samples per chip
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("fs", [2500000, 5000000, 4000000])
+def test_general_rate_doppler0_matches_numpy_circular_correlation(fs):
+    rng = np.random.default_rng(fs // 1000)
+    N, Tc, Nnc = fs // 1000, 1, 2
+    re = rng.integers(-127, 128, Tc * Nnc * N).astype(np.int8)
+    im = rng.integers(-127, 128, Tc * Nnc * N).astype(np.int8)
+    x = _cplx_record(re, im)
+    P = O.grid_direct(x, O.CPLX_I8, fs, 0.0, [7], 0.0, 100.0, 1, Tc, Nnc)[0, 0]
+    c = O.code_replica(7, fs, N).astype(np.float64)
+    # the replica is the chip-rate code sampled at n * 1023000 / fs, written out here
+    chips = 1.0 - 2.0 * O.ca_code(7).astype(np.float64)
+    assert np.array_equal(c, chips[(np.arange(N) * 1023000) // fs % 1023])
+    xc = re.astype(np.float64) + 1j * im.astype(np.float64)
+    expect = np.zeros(N)
+    for b in range(Nnc):
+        blk = xc[b * N:(b + 1) * N]
+        R = np.array([np.dot(blk, np.roll(c, tau)) for tau in range(N)])
+        expect += np.abs(R) ** 2
+    assert np.all(np.abs(P - expect) <= 1e-15 * expect)
+
+
+@pytest.mark.parametrize("fs", [5000000, 7777000])
+def test_general_rate_noiseless_code_peaks_at_its_phase(fs):
+    """x[n] = c_p[(n - d) mod N] at 0 Hz: P[d] = Nnc (Tc N)^2 exactly and it is
+    the unique maximum."""
+    N, Tc, Nnc, d, prn = fs // 1000, 1, 2, 1234, 22
+    rep = O.code_replica(prn, fs, N).astype(np.int64)
+    sig = np.tile(np.roll(rep, d), Tc * Nnc)
+    x = _cplx_record(sig.astype(np.int8), np.zeros_like(sig, dtype=np.int8))
+    P = O.grid_direct(x, O.CPLX_I8, fs, 0.0, [prn], 0.0, 100.0, 1, Tc, Nnc)[0, 0]
+    assert P[d] == Nnc * float(Tc * N) ** 2
+    others = np.delete(P, d)
+    assert others.max() < P[d]
+
+
+def test_general_rate_fft_route_matches_direct_route():
+    fs = 7777000
+    pl = [synth.Planted(prn=11, code_phase=4321, doppler_hz=750.0, cn0_dbhz=50.0)]
+    snap = synth.make_snapshot(77, O.REAL_I8, fs, 1944250.0, 3.5, pl, O.ca_code)
+    args = (snap.samples, snap.fmt, fs, snap.f_if_hz, [11, 2], 0.0, 750.0, 2, 1, 3)
+    Pd = O.grid_direct(*args)
+    Pf = O.grid_fft(*args)
+    for i in range(2):
+        assert np.all(np.abs(Pd[i] - Pf[i]) <= 1e-12 * (Pd[i] + Pd[i].mean()))
+    r = O.peaks(Pd, [11, 2], O.chip_exclusion(fs), 2.5, 0.0, 750.0)
+    assert r[0].detected and r[0].code_phase == 4321 and r[0].doppler_bin == 1
+
+
+def test_chip_exclusion_is_one_chip():
+    assert O.chip_exclusion(4092000) == 4
+    assert O.chip_exclusion(5000000) == pytest.approx(4.8876, abs=1e-4)
+    # a second peak 5 samples away is a candidate at 5 MHz, 4 samples away is not
+    G = np.zeros((1, 5000))
+    G[0, 100] = 10.0
+    G[0, 104] = 9.0
+    G[0, 105] = 2.0
+    r = O.peak_one(G, 1, O.chip_exclusion(5000000), 2.5, 0.0, 1.0)
+    assert r.second == 2.0 and r.ratio == 5.0
