@@ -176,8 +176,10 @@ def main():
     ap.add_argument("--serve-kind", default="mixed", choices=["mixed", "strong"],
                     help="serve: heterogeneous batch-style requests or strong-signal snapshots")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget")
-    ap.add_argument("--corr-ptile", type=int, default=0, choices=[0, 2, 4],
+    ap.add_argument("--corr-ptile", type=int, default=0, choices=[0, 1, 2, 4, 8],
                     help="PRN tile of the correlation kernel; 0: autotuned for the workload")
+    ap.add_argument("--corr-waves", type=int, default=0, choices=[0, 4, 6, 8, 12],
+                    help="waves per correlation workgroup; 0: autotuned for the workload")
     ap.add_argument("--persistent", type=int, default=-1, choices=[-1, 0, 1],
                     help="correlation grid: 1 occupancy-sized with work counters, 0 one workgroup "
                          "per item, -1 the library default")
@@ -211,6 +213,8 @@ def main():
     ctx = G.Context(0, precision=prec)
     if args.corr_ptile:
         ctx.set("corr_ptile", args.corr_ptile)
+    if args.corr_waves:
+        ctx.set("corr_waves", args.corr_waves)
     if args.persistent >= 0:
         ctx.set("persistent", args.persistent)
     if args.doppler_fd:

@@ -138,7 +138,13 @@ void gnss_ctx_destroy(gnss_ctx *ctx);
  * Sec. 1, and test hooks): "threshold" (detection ratio, > 0), "hbm_budget" (bytes,
  * 0 = unlimited; device memory of tables and workspaces), "profile" (1:
  * record per-stage HIP events, see gnss_stage_times; 0: off), "corr_ptile"
- * (PRNs per correlation workgroup: 2 or 4; 0 = autotuned, default 2),
+ * (PRNs per correlation workgroup: GNSS_FP32 1, 2 or 4, GNSS_FP16 2 or 4,
+ * GNSS_FP16_PFA 1, 2, 4 or 8; 0 = autotuned, by default 1 for GNSS_FP32 and
+ * 2 otherwise), "corr_waves" (waves, i.e. (Doppler, phase) items, per
+ * correlation workgroup: GNSS_FP32 tile 1 runs 12, 6 or 4 at three waves per
+ * SIMD, tiles 2 and 4 run 8; the FP16 kernels have one width each; 0 =
+ * autotuned, by default 12 for tile 1; a width the tile does not have falls
+ * back to its default),
  * "persistent" (grid of the correlation kernel, the dominant one: 1 an
  * occupancy-sized grid whose workgroups take items from per-XCD work counters
  * and then from the other XCDs' ranges; 0 one workgroup per item; -1, the
@@ -234,13 +240,17 @@ int gnss_graph_launch(gnss_graph *graph, void *stream);
  * no-op. */
 void gnss_graph_destroy(gnss_graph *graph);
 
-/* Picks the correlation kernel's PRN tile (2 or 4) and schedule (1:
- * persistent with work counters, 0: one workgroup per item) for batches with
- * the sample rates of `reqs` by timing the four pairs on the device (reqs are
+/* Picks the correlation kernel's launch for batches with the sample rates of
+ * `reqs` (the batch mode of the paper's Listing 3(b) needs a launch shape the
+ * paper's hardware fixed by hand): PRN tile, waves per workgroup (the shapes
+ * the precision has, see "corr_ptile" and "corr_waves" of gnss_ctx_set) and
+ * schedule (1: persistent with work counters, 0: one workgroup per item), by
+ * timing every combination on the device (fastest of 3 runs; reqs are
  * device-buffer requests, their outputs are overwritten), or takes them from
  * the text cache file `cache_path` (nullable) keyed by device, precision and
  * rate signature; writes the cache and sets the context to use the choice
- * (options "corr_ptile" 2/4 and "persistent" 0/1 override it).
+ * (options "corr_ptile", "corr_waves" and "persistent" override it); the
+ * cache file holds "key tile schedule waves" lines.
  * *chosen_tile and *chosen_persistent (nullable) get it. */
 int gnss_autotune(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, const char *cache_path,
                   int32_t *chosen_tile, int32_t *chosen_persistent);

@@ -266,12 +266,10 @@ int32_t code_shift(long long b, int Tc, int N, double lo, double step, int k)
 // copied to the device with every batch.
 static constexpr long long kMaxShiftTable = 1LL << 22;
 
-void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int corr_pt,
+void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, gnss::CorrShape corr,
                  float threshold, int precision, int doppler_fd, int code_doppler, BatchHost &B)
 {
-    const int corr_w = precision == GNSS_FP16       ? gnss::kCorrWavesH
-                       : precision == GNSS_FP16_PFA ? gnss::kCorrWavesX
-                                                    : gnss::kCorrWaves;
+    const int corr_pt = corr.pt, corr_w = corr.w;
     B.d.assign(n, gnss::ReqDesc{});
     B.pre.assign((size_t)gnss::kNumStages * (n + 1), 0);
     B.grid_off.assign(n, -1);
@@ -383,6 +381,7 @@ void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int c
     }
     B.n = n;
     B.corr_pt = corr_pt;
+    B.corr_w = corr_w;
     B.precision = precision;
     // the frequency-domain variant has no polyphase vectors in F: its long spectra live there
     B.F_bytes = doppler_fd ? (size_t)fd_f2 * sizeof(float2) : (size_t)vec * gnss::kPolyLen * sizeof(int2);
@@ -494,6 +493,7 @@ int stage_batch(gnss_ctx *c, Workspace &w, BatchHost &B, hipStream_t s, gnss::La
     L.reqs = (const gnss::ReqDesc *)(dm + ml.desc);
     L.n_req = B.n;
     L.corr_pt = B.corr_pt;
+    L.corr_w = B.corr_w;
     L.persistent = persistent_for(c, B);
     L.precision = B.precision;
     L.fd = B.fd;
@@ -865,9 +865,17 @@ int gnss_ctx_set(gnss_ctx *ctx, const char *key, double value)
         ctx->budget = (size_t)value;
         return GNSS_OK;
     }
+    if (!strcmp(key, "corr_waves")) {
+        if (value != 0.0 && (value != floor(value) || (value != 4.0 && value != 6.0 && value != 8.0 && value != 12.0)))
+            return set_err(GNSS_EINVAL, "corr_waves must be 0 (tuned) or 4, 6, 8 or 12");
+        ctx->corr_w_forced = (int)value;
+        return GNSS_OK;
+    }
     if (!strcmp(key, "corr_ptile")) {
-        if (value != 0.0 && !gnss::corr_ptile_valid((int)value))
-            return set_err(GNSS_EINVAL, "corr_ptile must be 2, 4 or 0 (tuned)");
+        if (value != 0.0 && (value != floor(value) || !gnss::corr_ptile_valid((int)value, ctx->precision)))
+            return set_err(GNSS_EINVAL, "corr_ptile must be 0 (tuned) or, for this precision, %s",
+                           ctx->precision == GNSS_FP32 ? "1, 2 or 4"
+                           : ctx->precision == GNSS_FP16 ? "2 or 4" : "1, 2, 4 or 8");
         ctx->corr_pt_forced = (int)value;
         return GNSS_OK;
     }
@@ -939,7 +947,7 @@ int gnss_workspace_bytes(const gnss_request *req, size_t *bytes)
     BatchHost B;
     gnss_request r = *req;
     r.out_grid = nullptr;
-    build_batch(&p, &r, 1, 2, 2.5f, GNSS_FP32, 0, 1, B);  // FP32 and the shift table: the most
+    build_batch(&p, &r, 1, gnss::CorrShape{2, gnss::kCorrWaves}, 2.5f, GNSS_FP32, 0, 1, B);  // FP32 and the shift table: the most
     *bytes = batch_device_bytes(B) + sample_bytes(p.fmt, (size_t)p.n_samples) + (size_t)p.n_prn * sizeof(gnss_peak);
     return GNSS_OK;
 }
@@ -955,7 +963,7 @@ int gnss_acquire_batch_device(gnss_ctx *ctx, const gnss_request *reqs, int32_t n
     if (g.rc) return g.rc;
     hipStream_t s = (hipStream_t)stream;
     BatchHost B;
-    build_batch(plans.data(), reqs, n_req, corr_ptile_for(ctx, plans.data(), n_req), ctx->threshold, ctx->precision, ctx->doppler_fd, ctx->code_doppler, B);
+    build_batch(plans.data(), reqs, n_req, corr_shape_for(ctx, plans.data(), n_req), ctx->threshold, ctx->precision, ctx->doppler_fd, ctx->code_doppler, B);
     gnss::Launch L;
     if ((rc = stage_batch(ctx, ctx->ws, B, s, L))) return rc;
     return launch(ctx, ctx->ws, L, s, true);
@@ -978,7 +986,7 @@ int gnss_acquire_device_noalloc(gnss_ctx *ctx, const gnss_request *req, void *st
     if (!ctx->d_scratch) return set_err(GNSS_EDEVICE, "the context has no scratch address");
     hipStream_t s = (hipStream_t)stream;
     BatchHost B;
-    build_batch(&p, req, 1, corr_ptile_for(ctx, &p, 1), ctx->threshold, ctx->precision, ctx->doppler_fd,
+    build_batch(&p, req, 1, corr_shape_for(ctx, &p, 1), ctx->threshold, ctx->precision, ctx->doppler_fd,
                 ctx->code_doppler, B);
     Workspace &w = ctx->ws_na;
     if ((rc = scratch_layout(ctx, B, w))) return rc;
@@ -1031,7 +1039,7 @@ int gnss_acquire(const void *samples, int32_t fmt, size_t n, double fs, double f
     dr.out_grid = nullptr;  // workspace grid, copied out below
     dr.out_peaks = (gnss_peak *)w.peaks.p;
     BatchHost B;
-    build_batch(&p, &dr, 1, corr_ptile_for(c, &p, 1), c->threshold, c->precision, c->doppler_fd, c->code_doppler, B);
+    build_batch(&p, &dr, 1, corr_shape_for(c, &p, 1), c->threshold, c->precision, c->doppler_fd, c->code_doppler, B);
     gnss::Launch L;
     if ((rc = stage_batch(c, w, B, c->stream, L)) || (rc = launch(c, w, L, c->stream, true))) {
         (void)hipStreamSynchronize(c->stream);
@@ -1063,8 +1071,9 @@ int gnss_graph_create(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, gn
     if (!gr) return set_err(GNSS_ENOMEM, "host allocation failed");
     gr->ctx = ctx;
     BatchHost B;
-    build_batch(plans.data(), reqs, n_req, corr_ptile_for(ctx, plans.data(), n_req), ctx->threshold, ctx->precision, ctx->doppler_fd, ctx->code_doppler, B);
+    build_batch(plans.data(), reqs, n_req, corr_shape_for(ctx, plans.data(), n_req), ctx->threshold, ctx->precision, ctx->doppler_fd, ctx->code_doppler, B);
     gr->corr_pt = B.corr_pt;
+    gr->corr_w = B.corr_w;
     hipStream_t cs = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -1183,7 +1192,7 @@ static int stage_one(gnss_ctx *ctx, const gnss_request *req, gnss::Plan &p, hipS
     if (rc) return rc;
     gnss_request r = *req;
     r.out_grid = nullptr;
-    build_batch(&p, &r, 1, 2, ctx->threshold, ctx->precision, 0, ctx->code_doppler, B);
+    build_batch(&p, &r, 1, gnss::CorrShape{2, gnss::corr_waves(ctx->precision, 2)}, ctx->threshold, ctx->precision, 0, ctx->code_doppler, B);
     return stage_batch(ctx, ctx->ws, B, s, L, true);
 }
 

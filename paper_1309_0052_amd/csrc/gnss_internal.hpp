@@ -16,7 +16,8 @@ constexpr int kMaxSpc = 16;            // samples per chip: fs <= 16.368 MHz
 constexpr int kMaxN = kCodeLen * kMaxSpc;
 constexpr int kVec = 1024;             // float4 per storage-order spectrum (2048 complex)
 constexpr int kPolyLen = 1024;         // int2 per polyphase component (1023 + 1 zero)
-constexpr int kCorrWaves = 8;          // waves per FP32 correlation workgroup
+constexpr int kCorrWaves = 8;          // waves per FP32 correlation workgroup (PRN tiles 2, 4)
+constexpr int kCorrWaves1 = 12;        // ... PRN tile 1 (three waves per SIMD)
 constexpr int kCorrWavesH = 4;         // waves per FP16 correlation workgroup
 constexpr int kCorrWavesX = 4;         // waves per exact-length correlation workgroup
 
@@ -173,7 +174,8 @@ struct Launch {
     const long long *pre;  // [kNumStages][n_req + 1] work-item prefix sums
     int n_req;
     long long total[kNumStages];  // host copy (grid sizing)
-    int corr_pt;                  // PRN tile of the correlation kernel (2 or 4)
+    int corr_pt;                  // PRN tile of the correlation kernel
+    int corr_w;                   // its waves per workgroup
     int persistent;               // correlation kernel: 1 occupancy-sized grid with work counters, 0 a workgroup per item
     int precision;                // GNSS_FP32 / GNSS_FP16 / GNSS_FP16_PFA
     int fd;                       // 1: frequency-domain Doppler (exact-length contexts)
@@ -197,7 +199,23 @@ struct Tables {
 
 hipError_t launch_batch(const Launch &L, const Tables &T, int2 *d_F, void *d_G, float *d_Q, int32_t *d_K,
                         float *d_part, int n_cu, hipStream_t s, hipEvent_t *marks);
-int corr_ptile_valid(int pt);
+int corr_ptile_valid(int pt, int precision);
+// Launch shape of the correlation kernel: PRNs per workgroup (pt) and waves
+// per workgroup (w, one (Doppler, phase) item per wave).
+struct CorrShape {
+    int pt, w;
+};
+// the waves per workgroup a PRN tile runs with unless tuned
+inline int corr_waves(int precision, int pt)
+{
+    return precision == GNSS_FP16 ? kCorrWavesH
+           : precision == GNSS_FP16_PFA ? kCorrWavesX
+           : pt == 1 ? kCorrWaves1
+                     : kCorrWaves;
+}
+// instantiated shapes: FP32 tile 1 with 12, 6 or 4 waves (three waves per
+// SIMD), tiles 2 and 4 with 8; the FP16 kernels have one width each
+bool corr_shape_valid(CorrShape c, int precision);
 constexpr int kBoxChunk = 2048;
 constexpr int kPeakThreads = 256;   // threads of the column-max kernel (256-lag blocks)
 constexpr int kArgThreads = 1024;   // threads of the per-PRN argmax kernel

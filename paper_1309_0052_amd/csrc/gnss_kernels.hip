@@ -593,8 +593,10 @@ __device__ __forceinline__ void store_tile(const float (&acc)[PT][16], float *s_
 // Work item = (request, PRN tile, chunk of kCorrWaves (Doppler, phase)
 // items); one wave per (Doppler, phase) item, looping over the blocks and the
 // tile's PT PRNs with the sums in registers.
-template <int PT>
-__global__ __launch_bounds__(64 * kCorrWaves) void k_corr(const ReqDesc *__restrict__ R, BatchHdr *H,
+// W waves per workgroup, WPE the waves per SIMD the registers are budgeted for
+// (PRN tile 1 at three waves per SIMD: 164 VGPRs; tiles 2 and 4 at two).
+template <int PT, int W, int WPE>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE))) void k_corr(const ReqDesc *__restrict__ R, BatchHdr *H,
                                                           const long long *pre, const float4 *G,
                                                           const float4 *__restrict__ CS,
                                                           const float2 *__restrict__ tw)
@@ -603,8 +605,8 @@ __global__ __launch_bounds__(64 * kCorrWaves) void k_corr(const ReqDesc *__restr
     constexpr int kTwBytes = kTwElems * (int)sizeof(float2);
     // the transposes go through a quarter-size buffer per wave in four rounds:
     // measured faster than the full buffer (its paired accesses conflict in LDS)
-    constexpr int kXbBytes = kCorrWaves * kXbufElemsQ * (int)sizeof(float2);
-    constexpr int kStageBytes = PT * 1024 * kStagePad * (int)sizeof(float);
+    constexpr int kXbBytes = W * kXbufElemsQ * (int)sizeof(float2);
+    constexpr int kStageBytes = PT * 1024 * (W + 1) * (int)sizeof(float);
     constexpr int kSmem = (kCcBytes + kTwBytes + kXbBytes) > kStageBytes ? (kCcBytes + kTwBytes + kXbBytes)
                                                                           : kStageBytes;
     __shared__ __align__(16) unsigned char smem[kSmem];
@@ -630,16 +632,16 @@ __global__ __launch_bounds__(64 * kCorrWaves) void k_corr(const ReqDesc *__restr
         // code spectra of the tile's PRNs and the twiddles (in a persistent
         // launch this overwrites the staging area of the previous item's
         // write: the barrier inside next_item separates them)
-        for (int i = tid; i < PT * kVec; i += 64 * kCorrWaves) {
+        for (int i = tid; i < PT * kVec; i += 64 * W) {
             int p = i / kVec, e = i - p * kVec;
             int pi = ptile * PT + p;
             int prn = pi < d.n_prn ? d.prns[pi] : 0;
             s_cc[i] = CS[(long long)prn * kVec + e];
         }
-        stage_twiddles(s_tw, tw, tid, 64 * kCorrWaves);
+        stage_twiddles(s_tw, tw, tid, 64 * W);
         __syncthreads();
 
-        const int item = chunk * kCorrWaves + w;
+        const int item = chunk * W + w;
         const bool active = item < d.n_items;
         const int spc = d.spc;
         const int k = item / spc, s = item - k * spc;
@@ -686,11 +688,23 @@ __global__ __launch_bounds__(64 * kCorrWaves) void k_corr(const ReqDesc *__restr
             }
         }
 
-        store_tile<PT, kCorrWaves>(acc, s_stage, d, ptile, chunk, w, l, tid, 0x1p-46f);
+        store_tile<PT, W>(acc, s_stage, d, ptile, chunk, w, l, tid, 0x1p-46f);
     }
 }
 
-int corr_ptile_valid(int pt) { return pt == 2 || pt == 4; }
+bool corr_shape_valid(CorrShape c, int precision)
+{
+    if (!corr_ptile_valid(c.pt, precision)) return false;
+    if (precision != GNSS_FP32 || c.pt != 1) return c.w == corr_waves(precision, c.pt);
+    return c.w == 12 || c.w == 6 || c.w == 4;
+}
+
+int corr_ptile_valid(int pt, int precision)
+{
+    return precision == GNSS_FP32 ? (pt == 1 || pt == 2 || pt == 4)
+           : precision == GNSS_FP16 ? (pt == 2 || pt == 4)
+                                    : (pt == 1 || pt == 2 || pt == 4 || pt == 8);
+}
 
 // ===========================================================================
 // FP16 path: packed half-precision transforms with block floating point
@@ -2484,16 +2498,31 @@ hipError_t launch_batch(const Launch &L, const Tables &T, int2 *d_F, void *d_G, 
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     } else if (L.total[kStCorr] > 0) {
-        if (L.corr_pt == 2) {
+        if (L.corr_pt == 1 && L.corr_w == 4) {
             static int cap = 0;
-            if (!cap) cap = occupancy(k_corr<2>, 64 * kCorrWaves, n_cu);
-            hipLaunchKernelGGL(k_corr<2>, dim3(grid_for(L.total[kStCorr], cap, pers)), dim3(64 * kCorrWaves),
-                               0, s, L.reqs, L.hdr, L.pre, (const float4 *)d_G, d_cs, d_tw);
+            if (!cap) cap = occupancy(k_corr<1, 4, 3>, 64 * 4, n_cu);
+            hipLaunchKernelGGL((k_corr<1, 4, 3>), dim3(grid_for(L.total[kStCorr], cap, pers)), dim3(64 * 4), 0, s,
+                               L.reqs, L.hdr, L.pre, (const float4 *)d_G, d_cs, d_tw);
+        } else if (L.corr_pt == 1 && L.corr_w == 6) {
+            static int cap = 0;
+            if (!cap) cap = occupancy(k_corr<1, 6, 3>, 64 * 6, n_cu);
+            hipLaunchKernelGGL((k_corr<1, 6, 3>), dim3(grid_for(L.total[kStCorr], cap, pers)), dim3(64 * 6), 0, s,
+                               L.reqs, L.hdr, L.pre, (const float4 *)d_G, d_cs, d_tw);
+        } else if (L.corr_pt == 1) {
+            static int cap = 0;
+            if (!cap) cap = occupancy(k_corr<1, 12, 3>, 64 * 12, n_cu);
+            hipLaunchKernelGGL((k_corr<1, 12, 3>), dim3(grid_for(L.total[kStCorr], cap, pers)), dim3(64 * 12), 0, s,
+                               L.reqs, L.hdr, L.pre, (const float4 *)d_G, d_cs, d_tw);
+        } else if (L.corr_pt == 2) {
+            static int cap = 0;
+            if (!cap) cap = occupancy(k_corr<2, kCorrWaves, 2>, 64 * kCorrWaves, n_cu);
+            hipLaunchKernelGGL((k_corr<2, kCorrWaves, 2>), dim3(grid_for(L.total[kStCorr], cap, pers)),
+                               dim3(64 * kCorrWaves), 0, s, L.reqs, L.hdr, L.pre, (const float4 *)d_G, d_cs, d_tw);
         } else {
             static int cap = 0;
-            if (!cap) cap = occupancy(k_corr<4>, 64 * kCorrWaves, n_cu);
-            hipLaunchKernelGGL(k_corr<4>, dim3(grid_for(L.total[kStCorr], cap, pers)), dim3(64 * kCorrWaves),
-                               0, s, L.reqs, L.hdr, L.pre, (const float4 *)d_G, d_cs, d_tw);
+            if (!cap) cap = occupancy(k_corr<4, kCorrWaves, 2>, 64 * kCorrWaves, n_cu);
+            hipLaunchKernelGGL((k_corr<4, kCorrWaves, 2>), dim3(grid_for(L.total[kStCorr], cap, pers)),
+                               dim3(64 * kCorrWaves), 0, s, L.reqs, L.hdr, L.pre, (const float4 *)d_G, d_cs, d_tw);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }

@@ -55,6 +55,7 @@ struct Workspace {
 struct BatchHost {
     int n = 0;
     int corr_pt = 2;
+    int corr_w = 8;
     int precision = GNSS_FP32;
     std::vector<gnss::ReqDesc> d;
     std::vector<long long> pre;
@@ -78,6 +79,11 @@ struct BatchHost {
 struct Ticket;
 struct Server;
 
+// An autotuned correlation launch: PRN tile, waves per workgroup, schedule.
+struct CorrTune {
+    int pt = 2, w = 8, pers = 1;
+};
+
 }  // namespace gnss_rt
 
 struct gnss_ctx {
@@ -89,6 +95,7 @@ struct gnss_ctx {
     int precision = GNSS_FP32;
     float threshold = 2.5f;
     int corr_pt_forced = 0; // 0: tuned / default
+    int corr_w_forced = 0;  // waves per correlation workgroup; 0: tuned / default
     int persistent_forced = -1;  // correlation grid: 1 occupancy-sized with work counters, 0 one
                                  // workgroup per item, -1 tuned / default (1)
     int code_doppler = 0;   // 1: code-Doppler compensation of the non-coherent sum
@@ -114,7 +121,7 @@ struct gnss_ctx {
     void *d_scratch = nullptr;
     gnss_rt::Workspace ws_na;
     // autotuned (PRN tile, correlation schedule) per sample-rate signature
-    std::map<std::string, std::pair<int, int>> tuned;
+    std::map<std::string, gnss_rt::CorrTune> tuned;
     // per-stage timing
     bool profile = false;
     std::vector<hipEvent_t> event_pool;
@@ -137,6 +144,7 @@ struct gnss_graph {
     gnss_rt::Workspace ws;
     hipGraphExec_t exec = nullptr;
     int corr_pt = 2;
+    int corr_w = 8;
 };
 
 namespace gnss_rt {
@@ -166,7 +174,7 @@ void release(gnss_ctx *c, DevBuf &b);
 void release_ws(gnss_ctx *c, Workspace &w);
 int make_plan(const gnss_request *r, gnss::Plan &p, bool need_outputs);
 int plan_all(const gnss_request *reqs, int n, std::vector<gnss::Plan> &plans);
-void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, int corr_pt, float threshold,
+void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, gnss::CorrShape corr, float threshold,
                  int precision, int doppler_fd, int code_doppler, BatchHost &B);
 // Bytes of a batch's metadata on the device: header, prefix sums,
 // descriptors and the host-computed tables.
@@ -181,7 +189,7 @@ int stage_batch(gnss_ctx *c, Workspace &w, BatchHost &B, hipStream_t s, gnss::La
 int launch(gnss_ctx *c, Workspace &w, const gnss::Launch &L, hipStream_t s, bool allow_profile);
 
 // autotuner lookup: the PRN tile for a batch of these plans
-int corr_ptile_for(gnss_ctx *c, const gnss::Plan *plans, int n);
+gnss::CorrShape corr_shape_for(gnss_ctx *c, const gnss::Plan *plans, int n);
 int persistent_for(gnss_ctx *c, const BatchHost &B);
 std::string rate_signature(const gnss::Plan *plans, int n);
 

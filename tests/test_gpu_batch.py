@@ -98,9 +98,12 @@ def test_batch_equals_alone_and_oracle(ctx, small):
 def test_tile_and_schedule_do_not_change_results(ctx, small):
     items, reqs, alone = small
     try:
-        for pt in (2, 4):
+        # FP32 shapes (PRN tile, waves per workgroup): tile 1 at three waves per SIMD
+        # with 12, 6 or 4 waves per workgroup, tiles 2 and 4 with 8
+        for pt, w in ((1, 12), (1, 6), (1, 4), (2, 8), (4, 8)):
             for sched in (0, 1):
                 ctx.set("corr_ptile", pt)
+                ctx.set("corr_waves", w)
                 ctx.set("persistent", sched)
                 for r in reqs:
                     r.clear()
@@ -110,6 +113,7 @@ def test_tile_and_schedule_do_not_change_results(ctx, small):
                     assert np.array_equal(g, alone[i][0]) and np.array_equal(p, alone[i][1]), (pt, sched, i)
     finally:
         ctx.set("corr_ptile", 0)
+        ctx.set("corr_waves", 0)
         ctx.set("persistent", -1)
 
 
@@ -137,8 +141,10 @@ def test_autotune_and_cache(ctx, small, tmp_path):
     items, reqs, alone = small
     path = str(tmp_path / "tune.txt")
     pt, sched = ctx.autotune([r.req for r in reqs], path)
-    assert pt in (2, 4) and sched in (0, 1)
-    assert os.path.exists(path) and open(path).read().split()[-2:] == [str(pt), str(sched)]
+    assert pt in (1, 2, 4) and sched in (0, 1)
+    # "key tile schedule waves"
+    words = open(path).read().split()
+    assert os.path.exists(path) and words[-3:-1] == [str(pt), str(sched)] and int(words[-1]) in (4, 6, 8, 12)
     assert ctx.autotune([r.req for r in reqs], path) == (pt, sched)  # from the cache
     for r in reqs:
         r.clear()
