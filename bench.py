@@ -189,6 +189,11 @@ def main():
     ap.add_argument("--doppler-fd", action="store_true",
                     help="with --precision fp16pfa: frequency-domain Doppler (one long DFT per block "
                          "serves every bin; exact-exponential carrier)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the precision, batch and serving figures the default line carries")
+    ap.add_argument("--extra-steps", type=int, default=5, help="extras: graph replays of the batch")
+    ap.add_argument("--extra-rate", type=float, default=200.0, help="extras: Poisson arrival rate, req/s")
+    ap.add_argument("--extra-serve-n", type=int, default=500, help="extras: timed served requests per precision")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-other-modes", action="store_true",
@@ -333,6 +338,12 @@ def main():
     }
     if not args.no_other_modes and args.precision == "fp32" and not args.doppler_fd:
         out["other_modes"] = other_modes(args, G, torch, d_x, snap, srch, cells, stream)
+    if (not args.no_extras and args.workload == "weak" and args.precision == "fp32" and not args.doppler_fd):
+        codes = {p: code_fn(p) for p in range(1, 38)}  # the GPU's codes, kept past this context
+        ctx.close()
+        del d_x
+        torch.cuda.empty_cache()
+        out.update(extras(args, G, torch, codes.__getitem__))
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(snap, srch, args.cpu_seconds)
@@ -407,14 +418,26 @@ def _cells(srch, fs_hz):
     return len(srch.prns) * nd * (fs_hz // 1000) * srch.T_coh * srch.N_noncoh
 
 
-def run_batch(args, G, torch, ctx, code_fn):
-    """Heterogeneous batch: one captured graph replay per step."""
-    import numpy as np
+BATCH_DESC = ("heterogeneous batch of %d snapshots, 20-200 ms, fs in {4.092, 8.184, 16.368} MHz, 8-32 PRNs, "
+              "+-2-10 kHz windows, 1 ms coh; one hipGraph launch per step")
+
+
+def batch_items(code_fn, n: int):
+    """The heterogeneous batch workload (seed 4), generated on host threads."""
     import synth
 
     t_gen = time.perf_counter()
-    items = synth.batch_workload(code_fn, seed=4, n=args.batch_n)
-    t_gen = time.perf_counter() - t_gen
+    items = synth.batch_workload(code_fn, seed=4, n=n, workers=min(16, os.cpu_count() or 1))
+    return items, time.perf_counter() - t_gen
+
+
+def batch_measure(G, torch, ctx, items, prec: str, steps: int, warmup: int, pt=0, sched=-1) -> dict:
+    """One captured-graph replay of the whole batch per step on `ctx` (whose
+    precision is `prec`): ms per step, snapshots/s, cells/s, the per-stage
+    split of one eager profiled pass, the correlation kernel's roofline and
+    the planted satellites recovered at their code phase."""
+    import numpy as np
+
     stream = torch.cuda.current_stream()
     bufs, reqs = [], []
     cells = 0
@@ -430,24 +453,26 @@ def run_batch(args, G, torch, ctx, code_fn):
                                    srch.N_noncoh, g.data_ptr(), pk.data_ptr()))
         cells += _cells(srch, snap.fs_hz)
     torch.cuda.synchronize()
-    pt, sched = args.corr_ptile, args.persistent
     if not pt or sched < 0:  # explicit tile and schedule options skip the autotuner
         t_pt, t_sched = ctx.autotune(reqs, os.path.join("/tmp", "gnss_autotune.txt"))
         pt, sched = pt or t_pt, sched if sched >= 0 else t_sched
     graph = ctx.graph(reqs)
-    for _ in range(args.warmup):
-        graph.launch(stream)
-    torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    t0 = time.perf_counter()
-    ev[0].record(stream)
-    for i in range(args.steps):
-        graph.launch(stream)
-        ev[i + 1].record(stream)
-    torch.cuda.synchronize()
-    wall_s = time.perf_counter() - t0
-    lat = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
-    ms_step = ev[0].elapsed_time(ev[-1]) / args.steps
+    try:
+        for _ in range(warmup):
+            graph.launch(stream)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        t0 = time.perf_counter()
+        ev[0].record(stream)
+        for i in range(steps):
+            graph.launch(stream)
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        wall_s = time.perf_counter() - t0
+    finally:
+        graph.close()
+    lat = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    ms_step = ev[0].elapsed_time(ev[-1]) / steps
     # one eager profiled pass for the per-stage split and the dominant kernel
     ctx.set("profile", 1)
     ctx.stage_times(reset=True)
@@ -470,57 +495,74 @@ def run_batch(args, G, torch, ctx, code_fn):
         nd = G.n_doppler(srch.lo, srch.hi, srch.step)
         units_flops += len(srch.prns) * nd * srch.N_noncoh * (5.0 * N * math.log2(N) + 10.0 * N)
         transforms += len(srch.prns) * nd * srch.N_noncoh * (N // 1023)
+    return {"ms_per_step": ms_step, "steps": steps, "warmup": warmup,
+            "value": cells / (ms_step / 1e3), "unit": "cells/s", "dtype": DTYPE[prec],
+            "snapshots": len(items), "cells_per_step": cells,
+            "snapshots_per_s": len(items) / (ms_step / 1e3),
+            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+            "wall_s": wall_s, "corr_ptile": pt, "persistent": sched,
+            "stages_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in stages.items()},
+            "roofline": corr_roofline(prec, units_flops, corr_ms,
+                                      read_traffic(CORR_KERNEL[prec][2:], "batch"), transforms),
+            "planted_recovered": [found, total]}
+
+
+def run_batch(args, G, torch, ctx, code_fn):
+    """Heterogeneous batch: one captured graph replay per step."""
+    items, t_gen = batch_items(code_fn, args.batch_n)
+    m = batch_measure(G, torch, ctx, items, args.precision, args.steps, args.warmup, args.corr_ptile,
+                      args.persistent)
     out = {
         "metric": "search cells/s (PRNxDopplerxphasexms) + p50/p99 latency/snapshot",
-        "value": cells / (ms_step / 1e3), "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "value": m["value"], "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": m["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": DTYPE[args.precision], "data": "synthetic",
-        "config": {"workload": "heterogeneous batch of %d snapshots, 20-200 ms, fs in {4.092, 8.184, "
-                               "16.368} MHz, 8-32 PRNs, +-2-10 kHz windows, 1 ms coh; one hipGraph "
-                               "launch per step" % len(items),
-                   "snapshots": len(items), "cells_per_step": cells, "corr_ptile": pt,
-                   "persistent": sched, "precision": args.precision, "doppler_fd": bool(args.doppler_fd)},
-        "snapshots_per_s": len(items) / (ms_step / 1e3),
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-        "wall_s": wall_s, "generate_s": t_gen,
-        "stages_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in stages.items()},
-        "roofline": corr_roofline(args.precision, units_flops, corr_ms,
-                                  read_traffic(CORR_KERNEL[args.precision][2:], "batch"), transforms),
-        "planted_recovered": [found, total],
-        "source_hash": kernel_source_hash(),
+        "config": {"workload": BATCH_DESC % len(items), "snapshots": len(items), "cells_per_step": m["cells_per_step"],
+                   "corr_ptile": m["corr_ptile"], "persistent": m["persistent"], "precision": args.precision,
+                   "doppler_fd": bool(args.doppler_fd)},
+        "snapshots_per_s": m["snapshots_per_s"], "latency_ms": m["latency_ms"], "wall_s": m["wall_s"],
+        "generate_s": t_gen, "stages_ms": m["stages_ms"], "roofline": m["roofline"],
+        "planted_recovered": m["planted_recovered"], "source_hash": kernel_source_hash(),
     }
-    graph.close()
     ctx.close()
     print(json.dumps(out), flush=True)
 
 
-def run_serve(args, G, torch, ctx, code_fn):
-    """Open-loop Poisson arrivals into the continuous-batching server."""
-    import threading
+SERVE_KINDS = {"mixed": "heterogeneous batch-style snapshots (20-200 ms, 3 rates, 8-32 PRNs, 1 ms coh)",
+               "strong": "strong-signal real 2-bit snapshots (4.092 MHz, 10 ms, 32 PRN x 21 bins)"}
 
+
+def serve_pool(G, code_fn, kind: str):
+    """The requests the served benchmark draws from: host arrays and cells."""
     import numpy as np
     import synth
 
-    if args.serve_kind == "mixed":
-        pool = synth.batch_workload(code_fn, seed=5, n=48)
-        kind = "heterogeneous batch-style snapshots (20-200 ms, 3 rates, 8-32 PRNs, 1 ms coh)"
+    if kind == "mixed":
+        pool = synth.batch_workload(code_fn, seed=5, n=48, workers=min(16, os.cpu_count() or 1))
     else:
         pool = [synth.strong_real_2bit(code_fn, seed=50 + i) for i in range(16)]
-        kind = "strong-signal real 2-bit snapshots (4.092 MHz, 10 ms, 32 PRN x 21 bins)"
     prepared = []
     for snap, srch in pool:
         nd = G.n_doppler(srch.lo, srch.hi, srch.step)
         prepared.append((np.ascontiguousarray(snap.samples), snap, srch, nd, _cells(srch, snap.fs_hz)))
-    ctx.close()
-    rates = [float(r) for r in args.rates.split(",") if r]
-    results = []
-    rng = np.random.default_rng(5)
-    for rate in rates:
-        sctx = G.Context(0, hbm_budget_bytes=int(args.budget_gb * (1 << 30)),
-                         precision=precision_const(G, args.precision))
-        if args.doppler_fd:
+    return prepared
+
+
+def serve_measure(G, prepared, prec: str, rate: float, n_timed: int, n_warm: int, budget_gb: float,
+                  rng, doppler_fd: bool = False) -> dict:
+    """Open-loop Poisson arrivals at `rate` into a serving context: p50/p99
+    latency (results on the host - scheduled arrival, from the library's
+    clock of each ticket), snapshots/s, cells/s, the paper's effective
+    running time (wall / requests) and the mean batch size."""
+    import threading
+
+    import numpy as np
+
+    sctx = G.Context(0, hbm_budget_bytes=int(budget_gb * (1 << 30)), precision=precision_const(G, prec))
+    try:
+        if doppler_fd:
             sctx.set("doppler_fd", 1)
-        n_total = args.serve_warmup + args.serve_n
+        n_total = n_warm + n_timed
         gaps = rng.exponential(1.0 / rate, n_total)
         sched = np.cumsum(gaps)
         picks = rng.integers(0, len(prepared), n_total)
@@ -549,43 +591,61 @@ def run_serve(args, G, torch, ctx, code_fn):
         th = threading.Thread(target=collector)
         th.start()
         t0 = time.perf_counter()
-        for i in range(n_total):
-            x, snap, srch, nd, _ = prepared[picks[i]]
-            pk = np.zeros(len(srch.prns), G.PEAK_DTYPE)
-            req = G.make_request(x.ctypes.data, snap.fmt, snap.n, snap.fs_hz, snap.f_if_hz,
-                                 srch.prns, srch.lo, srch.hi, srch.step, srch.T_coh,
-                                 srch.N_noncoh, None, pk.ctypes.data)
-            while True:
-                now = time.perf_counter() - t0
-                if now >= sched[i]:
-                    break
-                time.sleep(min(0.0005, sched[i] - now))
-            outs[i] = (pk, req)
-            submit_at[i] = time.perf_counter()
-            try:
-                tickets[i] = sctx.submit(req)
-            except G.GnssError as e:
-                if e.code != G.GNSS_ENOMEM:
-                    raise
-                refused[i] = True  # larger than a batch slot's share of the HBM budget
-            ready.release()
-        th.join()
+        try:
+            for i in range(n_total):
+                x, snap, srch, nd, _ = prepared[picks[i]]
+                pk = np.zeros(len(srch.prns), G.PEAK_DTYPE)
+                req = G.make_request(x.ctypes.data, snap.fmt, snap.n, snap.fs_hz, snap.f_if_hz,
+                                     srch.prns, srch.lo, srch.hi, srch.step, srch.T_coh,
+                                     srch.N_noncoh, None, pk.ctypes.data)
+                while True:
+                    now = time.perf_counter() - t0
+                    if now >= sched[i]:
+                        break
+                    time.sleep(min(0.0005, sched[i] - now))
+                outs[i] = (pk, req)
+                submit_at[i] = time.perf_counter()
+                try:
+                    tickets[i] = sctx.submit(req)
+                except G.GnssError as e:
+                    if e.code != G.GNSS_ENOMEM:
+                        raise
+                    refused[i] = True  # larger than a batch slot's share of the HBM budget
+                ready.release()
+        finally:
+            for _ in range(n_total):  # let the collector finish whatever was submitted
+                ready.release()
+            th.join()
+    finally:
         sctx.close()
-        if errors:
-            raise SystemExit("serving errors: %s" % errors[:3])
-        w = args.serve_warmup
-        ok = ~refused[w:]
-        lat = ((done_at[w:] - t0) - sched[w:])[ok]
-        span = done_at[w:][ok].max() - (t0 + sched[w])
-        n_ok = int(ok.sum())
-        cells = float(sum(prepared[j][4] for j, good in zip(picks[w:], ok) if good))
-        results.append({"rate_req_s": rate, "requests": int(args.serve_n), "refused": int((~ok).sum()),
-                        "p50_ms": float(np.percentile(lat, 50) * 1e3),
-                        "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                        "snapshots_per_s": float(n_ok / span),
-                        "cells_per_s": cells / span,
-                        "effective_running_time_ms": float(span / n_ok * 1e3),
-                        "mean_batch": float(batch_sizes[w:][ok].mean())})
+    if errors:
+        raise RuntimeError("serving errors: %s" % errors[:3])
+    w = n_warm
+    ok = ~refused[w:]
+    lat = ((done_at[w:] - t0) - sched[w:])[ok]
+    span = done_at[w:][ok].max() - (t0 + sched[w])
+    n_ok = int(ok.sum())
+    cells = float(sum(prepared[j][4] for j, good in zip(picks[w:], ok) if good))
+    return {"rate_req_s": rate, "requests": int(n_timed), "warmup_requests": int(n_warm),
+            "refused": int((~ok).sum()), "dtype": DTYPE[prec],
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "snapshots_per_s": float(n_ok / span), "cells_per_s": cells / span,
+            "effective_running_time_ms": float(span / n_ok * 1e3),
+            "mean_batch": float(batch_sizes[w:][ok].mean())}
+
+
+def run_serve(args, G, torch, ctx, code_fn):
+    """Open-loop Poisson arrivals into the continuous-batching server."""
+    import numpy as np
+
+    prepared = serve_pool(G, code_fn, args.serve_kind)
+    ctx.close()
+    rates = [float(r) for r in args.rates.split(",") if r]
+    results = []
+    rng = np.random.default_rng(5)
+    for rate in rates:
+        results.append(serve_measure(G, prepared, args.precision, rate, args.serve_n, args.serve_warmup,
+                                     args.budget_gb, rng, args.doppler_fd))
         print("serve rate %.0f req/s: p50 %.1f ms, p99 %.1f ms, %.0f snapshots/s, %d refused"
               % (rate, results[-1]["p50_ms"], results[-1]["p99_ms"], results[-1]["snapshots_per_s"],
                  results[-1]["refused"]), file=sys.stderr, flush=True)
@@ -597,8 +657,8 @@ def run_serve(args, G, torch, ctx, code_fn):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[args.precision],
         "data": "synthetic",
         "config": {"workload": "served open-loop Poisson arrivals of %s, HBM budget %g GB"
-                               % (kind, args.budget_gb), "rates_req_s": rates, "precision": args.precision,
-                   "budget_gb": args.budget_gb, "kind": args.serve_kind},
+                               % (SERVE_KINDS[args.serve_kind], args.budget_gb), "rates_req_s": rates,
+                   "precision": args.precision, "budget_gb": args.budget_gb, "kind": args.serve_kind},
         "latency_ms": {"p50": top["p50_ms"], "p99": top["p99_ms"]},
         "serving": results,
         "source_hash": kernel_source_hash(),
@@ -698,11 +758,11 @@ def run_track(args, G, torch, ctx, code_fn):
     print(json.dumps(out), flush=True)
 
 
-def run_precision(args, G, torch, ctx, code_fn):
+def precision_measure(G, torch, code_fn, steps: int, warmup: int) -> dict:
     """The strong-signal snapshot on FP32, FP16 and exact-length FP16
-    contexts of the same GPU: device time of each, and each FP16 mode's grid
-    and detections against the FP32 ones (the error against the FP64 oracle
-    is in the FP16 tests)."""
+    contexts of the same GPU: device time of each (cells/s), and each FP16
+    mode's grid and detections against the FP32 ones (the error against the
+    FP64 oracle is in the FP16 tests)."""
     import numpy as np
     import synth
 
@@ -710,31 +770,33 @@ def run_precision(args, G, torch, ctx, code_fn):
     nd = G.n_doppler(srch.lo, srch.hi, srch.step)
     N = snap.fs_hz // 1000
     n_prn = len(srch.prns)
+    cells = n_prn * nd * N * srch.T_coh * srch.N_noncoh
     stream = torch.cuda.current_stream()
     x = torch.from_numpy(np.ascontiguousarray(snap.samples)).cuda()
     res = {}
-    ctx.close()
     for name in PRECISIONS:
         c = G.Context(0, precision=precision_const(G, name))
-        g = torch.empty(n_prn * nd * N, dtype=torch.float32, device="cuda")
-        pk = torch.zeros(n_prn * 48, dtype=torch.uint8, device="cuda")
-        req = G.make_request(x.data_ptr(), snap.fmt, snap.n, snap.fs_hz, snap.f_if_hz, srch.prns, srch.lo,
-                             srch.hi, srch.step, srch.T_coh, srch.N_noncoh, g.data_ptr(), pk.data_ptr())
-        for _ in range(args.warmup):
-            c.acquire_device(req, stream)
-        torch.cuda.synchronize()
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-        ev[0].record(stream)
-        for i in range(args.steps):
-            c.acquire_device(req, stream)
-            ev[i + 1].record(stream)
-        torch.cuda.synchronize()
-        ms = ev[0].elapsed_time(ev[-1]) / args.steps
-        res[name] = (ms, g.cpu().numpy().reshape(n_prn, nd, N).astype(np.float64),
-                     pk.cpu().numpy().view(G.PEAK_DTYPE).copy())
-        c.close()
+        try:
+            g = torch.empty(n_prn * nd * N, dtype=torch.float32, device="cuda")
+            pk = torch.zeros(n_prn * 48, dtype=torch.uint8, device="cuda")
+            req = G.make_request(x.data_ptr(), snap.fmt, snap.n, snap.fs_hz, snap.f_if_hz, srch.prns, srch.lo,
+                                 srch.hi, srch.step, srch.T_coh, srch.N_noncoh, g.data_ptr(), pk.data_ptr())
+            for _ in range(warmup):
+                c.acquire_device(req, stream)
+            torch.cuda.synchronize()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+            ev[0].record(stream)
+            for i in range(steps):
+                c.acquire_device(req, stream)
+                ev[i + 1].record(stream)
+            torch.cuda.synchronize()
+            ms = ev[0].elapsed_time(ev[-1]) / steps
+            res[name] = (ms, g.cpu().numpy().reshape(n_prn, nd, N).astype(np.float64),
+                         pk.cpu().numpy().view(G.PEAK_DTYPE).copy())
+        finally:
+            c.close()
     t32, P32, k32 = res["fp32"]
-    modes = {"fp32": {"ms": t32}}
+    modes = {"fp32": {"ms": t32, "value": cells / (t32 / 1e3), "dtype": "f32"}}
     for name in ("fp16", "fp16pfa"):
         t, P, k = res[name]
         mixed = max(float(np.max(np.abs(P[i] - P32[i]) / (P32[i] + P32[i].mean()))) for i in range(n_prn))
@@ -745,23 +807,75 @@ def run_precision(args, G, torch, ctx, code_fn):
             i = srch.prns.index(pl.prn)
             kb, tau = int(k32[i]["doppler_bin"]), int(k32[i]["code_phase"])
             peak_rel.append(abs(P[i, kb, tau] - P32[i, kb, tau]) / P32[i, kb, tau])
-        modes[name] = {"ms": t, "speedup_vs_fp32": t32 / t, "max_mixed_rel_power_diff_vs_fp32": mixed,
+        modes[name] = {"ms": t, "value": cells / (t / 1e3), "dtype": "f16", "speedup_vs_fp32": t32 / t,
+                       "max_mixed_rel_power_diff_vs_fp32": mixed,
                        "planted_peak_cell_rel_diff_max": max(peak_rel), "detections_identical": same,
                        "prns": n_prn}
+    return {"workload": "strong-signal snapshot (real 2-bit IF, 4.092 MHz, 10 ms; 32 PRN x 21 bins x 10 ms)",
+            "cells_per_snapshot": cells, "steps": steps, "warmup": warmup, "modes": modes}
+
+
+def run_precision(args, G, torch, ctx, code_fn):
+    """The strong-signal snapshot on the three precisions of the same GPU."""
+    ctx.close()
+    m = precision_measure(G, torch, code_fn, args.steps, args.warmup)
     head = args.precision if args.precision != "fp32" else "fp16"
-    cells = n_prn * nd * N * srch.T_coh * srch.N_noncoh
     out = {
         "metric": "search cells/s (PRNxDopplerxphasexms) + p50/p99 latency/snapshot",
-        "value": cells / (res[head][0] / 1e3), "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": res[head][0], "higher_is_better": True, "scaling": "weak",
+        "value": m["modes"][head]["value"], "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": m["modes"][head]["ms"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f16", "data": "synthetic",
-        "config": {"workload": "%s path on the strong-signal snapshot (real 2-bit IF, 4.092 MHz, 10 ms; "
-                               "32 PRN x 21 bins x 10 ms), against the FP32 path on the same GPU" % head,
+        "config": {"workload": "%s path on the %s, against the FP32 path on the same GPU" % (head, m["workload"]),
                    "precision": head},
-        "modes": modes,
+        "modes": m["modes"],
         "source_hash": kernel_source_hash(),
     }
     print(json.dumps(out), flush=True)
+
+
+def extras(args, G, torch, code_fn) -> dict:
+    """The other configurations beside the headline line, each in its own
+    try (a failure is reported, never costs the line): the precision
+    comparison on the strong snapshot, the heterogeneous batch (FP32 and
+    exact-length, one graph replay per step) and served Poisson arrivals
+    (FP32 and exact-length)."""
+    import numpy as np
+
+    out = {}
+    try:
+        out["precision"] = precision_measure(G, torch, code_fn, 20, 3)
+    except Exception as e:  # noqa: BLE001
+        out["precision"] = {"error": "%s: %s" % (type(e).__name__, e)}
+    try:
+        items, t_gen = batch_items(code_fn, args.batch_n)
+        b = {"workload": BATCH_DESC % len(items), "generate_s": t_gen}
+        for prec in ("fp32", "fp16pfa"):
+            c = G.Context(0, precision=precision_const(G, prec))
+            try:
+                b[prec] = batch_measure(G, torch, c, items, prec, args.extra_steps, 1)
+            except Exception as e:  # noqa: BLE001
+                b[prec] = {"error": "%s: %s" % (type(e).__name__, e)}
+            finally:
+                c.close()
+        del items
+        out["batch"] = b
+    except Exception as e:  # noqa: BLE001
+        out["batch"] = {"error": "%s: %s" % (type(e).__name__, e)}
+    try:
+        prepared = serve_pool(G, code_fn, "mixed")
+        sv = {"workload": "served open-loop Poisson arrivals of %s, HBM budget %g GB"
+                          % (SERVE_KINDS["mixed"], args.budget_gb)}
+        rng = np.random.default_rng(5)
+        for prec in ("fp32", "fp16pfa"):
+            try:
+                sv[prec] = serve_measure(G, prepared, prec, args.extra_rate, args.extra_serve_n,
+                                         max(20, args.extra_serve_n // 10), args.budget_gb, rng)
+            except Exception as e:  # noqa: BLE001
+                sv[prec] = {"error": "%s: %s" % (type(e).__name__, e)}
+        out["serve"] = sv
+    except Exception as e:  # noqa: BLE001
+        out["serve"] = {"error": "%s: %s" % (type(e).__name__, e)}
+    return out
 
 
 if __name__ == "__main__":
