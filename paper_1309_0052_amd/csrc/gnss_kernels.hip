@@ -376,7 +376,7 @@ __device__ __forceinline__ int bpad(int i) { return i + (i >> 3); }  // bank-con
 // multiplies exact.  Same values as wipe_fold_one.  Samples are addressed from
 // the block's first byte (the same pointer in every thread) by 32-bit in-block
 // offsets: a block holds Tc N <= 64 * 16368 samples.
-template <int FMT>
+template <int FMT, int NT>
 __device__ __forceinline__ void box_wipe(const void *samples, int N, int Tc, const uint32_t *s_lut, uint32_t D,
                                          int b, int n0, int len, int shift, int2 *s_f)
 {
@@ -387,7 +387,7 @@ __device__ __forceinline__ void box_wipe(const void *samples, int N, int Tc, con
     const long long blk_byte = FMT == GNSS_CPLX_I8 ? 2 * base : FMT == GNSS_REAL_I8 ? base : (base >> 2);
     const GNSS_GLOBAL uint8_t *blk = (const GNSS_GLOBAL uint8_t *)samples + blk_byte;
     const uint32_t step = FMT == GNSS_CPLX_I8 ? 2u * (uint32_t)N : (uint32_t)N;  // bytes (samples if packed)
-    for (int i = threadIdx.x; i < len; i += 256) {
+    for (int i = threadIdx.x; i < len; i += NT) {
         int n = n0 + i - shift;  // shift in [0, N): the block read circularly delayed
         if (n < 0) n += N;
         if (n >= N) n -= N;
@@ -430,10 +430,68 @@ __device__ __forceinline__ void box_wipe(const void *samples, int N, int Tc, con
     }
 }
 
+// LDS chunk buffer of box_item: kBoxChunk + spc - 1 wiped samples, padded
+constexpr int kBoxBuf = (kBoxChunk + kMaxSpc) + (kBoxChunk + kMaxSpc) / 8 + 8;
+
+// The wipe, fold, boxcar and polyphase split of one (Doppler k, block b) item
+// of request d by NT threads: dst[s * kPolyLen + m] = F[spc m + s] for m <
+// 1023 and 0 at m = 1023 (dst in global memory for the staged path, in LDS
+// for the fused exact-length path; the same integer arithmetic either way).
+template <int NT, typename DstPtr>
+__device__ __forceinline__ void box_item(const ReqDesc &d, int k, int b, const uint32_t *s_lut, int2 *s_f,
+                                         DstPtr dst)
+{
+    const int N = d.N, spc = d.spc;
+    const uint32_t D = d.dk[k];
+    // code-Doppler drift of this (bin, block) in samples, in [0, N): delaying
+    // the folded block by it circularly shifts its correlation by as many lags
+    const int shift = d.cshift ? d.cshift[(long long)k * d.Nnc + b] : 0;
+    for (int n0 = 0; n0 < N; n0 += kBoxChunk) {
+        const int cnt = min(kBoxChunk, N - n0);
+        const int len = cnt + spc - 1;
+        __syncthreads();  // LUT staged / previous chunk's boxcar done
+        if (d.fmt == GNSS_CPLX_I8)
+            box_wipe<GNSS_CPLX_I8, NT>(d.samples, N, d.Tc, s_lut, D, b, n0, len, shift, s_f);
+        else if (d.fmt == GNSS_REAL_I8)
+            box_wipe<GNSS_REAL_I8, NT>(d.samples, N, d.Tc, s_lut, D, b, n0, len, shift, s_f);
+        else
+            box_wipe<GNSS_REAL_2BIT_PACKED, NT>(d.samples, N, d.Tc, s_lut, D, b, n0, len, shift, s_f);
+        __syncthreads();
+        const int n_runs = (cnt + kBoxRun - 1) / kBoxRun;
+        for (int rr = threadIdx.x; rr < n_runs; rr += NT) {
+            const int i0 = rr * kBoxRun;
+            int sx = 0, sy = 0;
+            for (int t = 0; t < spc; ++t) {
+                int2 v = s_f[bpad(i0 + t)];
+                sx += v.x;
+                sy += v.y;
+            }
+            const int n = n0 + i0;
+            int m = n / spc, s = n - m * spc;
+#pragma unroll
+            for (int j = 0; j < kBoxRun; ++j) {
+                const int i = i0 + j;
+                if (i >= cnt) break;
+                dst[s * kPolyLen + m] = make_int2(sx, sy);
+                if (i + 1 < cnt) {
+                    int2 vi = s_f[bpad(i + spc)], vo = s_f[bpad(i)];
+                    sx += vi.x - vo.x;
+                    sy += vi.y - vo.y;
+                }
+                if (++s == spc) {
+                    s = 0;
+                    ++m;
+                }
+            }
+        }
+    }
+    if (threadIdx.x < spc) dst[threadIdx.x * kPolyLen + (kPolyLen - 1)] = make_int2(0, 0);
+}
+
 __global__ __launch_bounds__(256) void k_box(const ReqDesc *__restrict__ R, BatchHdr *H, const long long *pre,
                                              const uint32_t *lut, int2 *F)
 {
-    __shared__ int2 s_f[(kBoxChunk + kMaxSpc) + (kBoxChunk + kMaxSpc) / 8 + 8];
+    __shared__ int2 s_f[kBoxBuf];
     __shared__ uint32_t s_lut[1024];
     __shared__ long long s_item;
     for (int i = threadIdx.x; i < 1024; i += 256) s_lut[i] = lut[i];
@@ -448,52 +506,7 @@ __global__ __launch_bounds__(256) void k_box(const ReqDesc *__restrict__ R, Batc
         const ReqDesc &d = R[r];
         const int kb = (int)(it - pst[r]);  // (Doppler, block); < 2^31 by the plan checks
         const int k = kb / d.Nnc, b = kb - (kb / d.Nnc) * d.Nnc;
-        const int N = d.N, spc = d.spc;
-        const uint32_t D = d.dk[k];
-        // code-Doppler drift of this (bin, block) in samples, in [0, N): delaying
-        // the folded block by it circularly shifts its correlation by as many lags
-        const int shift = d.cshift ? d.cshift[(long long)k * d.Nnc + b] : 0;
-        int2 *dst = F + (d.vec_off + (long long)kb * spc) * kPolyLen;
-        for (int n0 = 0; n0 < N; n0 += kBoxChunk) {
-            const int cnt = min(kBoxChunk, N - n0);
-            const int len = cnt + spc - 1;
-            __syncthreads();  // LUT staged / previous chunk's boxcar done
-            if (d.fmt == GNSS_CPLX_I8)
-                box_wipe<GNSS_CPLX_I8>(d.samples, N, d.Tc, s_lut, D, b, n0, len, shift, s_f);
-            else if (d.fmt == GNSS_REAL_I8)
-                box_wipe<GNSS_REAL_I8>(d.samples, N, d.Tc, s_lut, D, b, n0, len, shift, s_f);
-            else
-                box_wipe<GNSS_REAL_2BIT_PACKED>(d.samples, N, d.Tc, s_lut, D, b, n0, len, shift, s_f);
-            __syncthreads();
-            const int n_runs = (cnt + kBoxRun - 1) / kBoxRun;
-            for (int rr = threadIdx.x; rr < n_runs; rr += 256) {
-                const int i0 = rr * kBoxRun;
-                int sx = 0, sy = 0;
-                for (int t = 0; t < spc; ++t) {
-                    int2 v = s_f[bpad(i0 + t)];
-                    sx += v.x;
-                    sy += v.y;
-                }
-                const int n = n0 + i0;
-                int m = n / spc, s = n - m * spc;
-#pragma unroll
-                for (int j = 0; j < kBoxRun; ++j) {
-                    const int i = i0 + j;
-                    if (i >= cnt) break;
-                    dst[s * kPolyLen + m] = make_int2(sx, sy);
-                    if (i + 1 < cnt) {
-                        int2 vi = s_f[bpad(i + spc)], vo = s_f[bpad(i)];
-                        sx += vi.x - vo.x;
-                        sy += vi.y - vo.y;
-                    }
-                    if (++s == spc) {
-                        s = 0;
-                        ++m;
-                    }
-                }
-            }
-        }
-        if (threadIdx.x < spc) dst[threadIdx.x * kPolyLen + (kPolyLen - 1)] = make_int2(0, 0);
+        box_item<256>(d, k, b, s_lut, s_f, F + (d.vec_off + (long long)kb * d.spc) * kPolyLen);
     }
 }
 
@@ -535,7 +548,6 @@ __global__ __launch_bounds__(256) void k_fft_poly(const int2 *F, const float2 *t
 // ===========================================================================
 // stage B: fused conj-multiply -> IFFT -> |.|^2 -> non-coherent sum
 // ===========================================================================
-constexpr int kStagePad = kCorrWaves + 1;
 
 // Grid write of a correlation work item.  Lag tau = spc*q + s interleaves the
 // waves' phases, so the sums are staged in LDS ([1024 q][W + 1] floats per
@@ -1192,90 +1204,102 @@ hipError_t launch_code_spectra_x_pack(const double2 *d_tmp, void *d_cs_x, int cs
     return hipGetLastError();
 }
 
-// Forward transforms, one polyphase vector per wave: the vector in LDS, its
-// sum S and mean S/1023, the exponent from the l1 norm of the mean-removed
-// vector plus |S|, the Good-Thomas gather of the mean-removed vector into
-// fragments, two passes, and the spectrum stored as fragments with its
-// exponent.  The DC bin is stored as S itself.  Removing the mean keeps the
-// FP16 weights from leaking a strong DC component into the other bins: the
-// code spectra are +-1 at DC and about 32 elsewhere, so a leak of a few
-// 10^-6 of the DC amplitude into every bin would reach percents of the
-// correlation of a DC-dominated block (a constant offset in the samples).
+// Forward transform of one polyphase vector held in LDS (xs, 1024 int2, the
+// last zero) by one wave: its sum S and mean S/1023, the exponent from the l1
+// norm of the mean-removed vector plus |S|, the Good-Thomas gather of the
+// mean-removed vector into fragments, two passes, and the spectrum stored as
+// fragments (dst) with its exponent (*e_out, lane 0).  The DC bin is stored as
+// S itself.  Removing the mean keeps the FP16 weights from leaking a strong DC
+// component into the other bins: the code spectra are +-1 at DC and about 32
+// elsewhere, so a leak of a few 10^-6 of the DC amplitude into every bin would
+// reach percents of the correlation of a DC-dominated block (a constant
+// offset in the samples).
+__device__ __forceinline__ void fft_x_vector(const int2 *xs, const pfa::FwdB &B, pfa::u4 *dst, int *e_out, int l)
+{
+    const int g = l >> 4, c = l & 15;
+    int2 v[kPolyLen / 64];
+    float sr = 0.f, si = 0.f;
+#pragma unroll
+    for (int i = 0; i < kPolyLen / 64; ++i) {
+        v[i] = xs[l + 64 * i];  // element 1023 is zero
+        sr += (float)v[i].x;
+        si += (float)v[i].y;
+    }
+    const float Sr = wave_sum(sr), Si = wave_sum(si);
+    // IEEE division: a constant vector's mean is its value exactly
+    const float mr = Sr / (float)kCodeLen, mi = Si / (float)kCodeLen;
+    float nrm = 0.f;
+#pragma unroll
+    for (int i = 0; i < kPolyLen / 64; ++i)
+        if (l + 64 * i < kCodeLen) nrm += fabsf((float)v[i].x - mr) + fabsf((float)v[i].y - mi);
+    const int e = l1_exponent(wave_sum(nrm) + fabsf(Sr) + fabsf(Si));
+    const float f = ldexpf(1.f, -e);
+    pfa::u4 a1[3][2];
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            float re[4], im[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int n1 = 16 * s + 4 * g + j, n2 = 16 * t + c;
+                re[j] = 0.f;
+                im[j] = 0.f;
+                if (n1 < pfa::kN1 && n2 < pfa::kN2) {
+                    const int2 x = xs[pfa::time_index(n1, n2)];
+                    re[j] = ((float)x.x - mr) * f;
+                    im[j] = ((float)x.y - mi) * f;
+                }
+            }
+            a1[t][s] = pfa::u4{pfa::pack2(re[0], re[1]), pfa::pack2(re[2], re[3]), pfa::pack2(im[0], im[1]),
+                               pfa::pack2(im[2], im[3])};
+        }
+    pfa::f4 o[2][6];
+    pfa::forward(a1, B, o);
+    if (l == 0) {  // bin 0 (a = 0, b = 0): the vector's sum
+        o[0][0].x = Sr * f;
+        o[0][1].x = Si * f;
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const pfa::f4 re = o[s][2 * t], im = o[s][2 * t + 1];
+            dst[(2 * t + s) * 64 + l] = pfa::u4{pfa::pack2(re.x, re.y), pfa::pack2(re.z, re.w),
+                                                pfa::pack2(im.x, im.y), pfa::pack2(im.z, im.w)};
+        }
+    if (c == 0) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const pfa::f4 re = o[s][4], im = o[s][5];
+            dst[pfa::kTailUnit + 4 * s + g] = pfa::u4{pfa::pack2(re.x, re.y), pfa::pack2(re.z, re.w),
+                                                      pfa::pack2(im.x, im.y), pfa::pack2(im.z, im.w)};
+        }
+    }
+    if (l == 0) *e_out = e;
+}
+
+// Forward transforms of the polyphase vectors in F: one vector per wave,
+// copied into LDS, then fft_x_vector.  (Fusing this with the wipe/fold stage,
+// the spc vectors of a (Doppler, block) item built in LDS and transformed
+// there, was measured slower: one 154 KB workgroup per CU left the wipe's
+// memory latency exposed, 0.63 ms against 0.33 ms for the two kernels.)
 __global__ __launch_bounds__(256) void k_fft_x(const int2 *F, const pfa::u4 *__restrict__ fr, pfa::u4 *Gx, int *E,
                                                const BatchHdr *H)
 {
     __shared__ int2 s_x[4][kPolyLen];
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     pfa::FwdB B;
     pfa::load_fwd(B, fr, l);
     const long long n_vec = H->total[kStVec];
     int2 *xs = s_x[w];
     for (long long vec = (long long)blockIdx.x * 4 + w; vec < n_vec; vec += (long long)gridDim.x * 4) {
         const int2 *src = F + vec * kPolyLen;
-        int2 v[kPolyLen / 64];
-        float sr = 0.f, si = 0.f;
         lds_fence();  // the previous vector's gathers are complete
 #pragma unroll
-        for (int i = 0; i < kPolyLen / 64; ++i) {
-            v[i] = src[l + 64 * i];  // element 1023 is zero
-            xs[l + 64 * i] = v[i];
-            sr += (float)v[i].x;
-            si += (float)v[i].y;
-        }
-        const float Sr = wave_sum(sr), Si = wave_sum(si);
-        // IEEE division: a constant vector's mean is its value exactly
-        const float mr = Sr / (float)kCodeLen, mi = Si / (float)kCodeLen;
-        float nrm = 0.f;
-#pragma unroll
-        for (int i = 0; i < kPolyLen / 64; ++i)
-            if (l + 64 * i < kCodeLen) nrm += fabsf((float)v[i].x - mr) + fabsf((float)v[i].y - mi);
-        const int e = l1_exponent(wave_sum(nrm) + fabsf(Sr) + fabsf(Si));
-        const float f = ldexpf(1.f, -e);
+        for (int i = 0; i < kPolyLen / 64; ++i) xs[l + 64 * i] = src[l + 64 * i];
         lds_fence();
-        pfa::u4 a1[3][2];
-#pragma unroll
-        for (int t = 0; t < 3; ++t)
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                float re[4], im[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int n1 = 16 * s + 4 * g + j, n2 = 16 * t + c;
-                    re[j] = 0.f;
-                    im[j] = 0.f;
-                    if (n1 < pfa::kN1 && n2 < pfa::kN2) {
-                        const int2 x = xs[pfa::time_index(n1, n2)];
-                        re[j] = ((float)x.x - mr) * f;
-                        im[j] = ((float)x.y - mi) * f;
-                    }
-                }
-                a1[t][s] = pfa::u4{pfa::pack2(re[0], re[1]), pfa::pack2(re[2], re[3]), pfa::pack2(im[0], im[1]),
-                                   pfa::pack2(im[2], im[3])};
-            }
-        pfa::f4 o[2][6];
-        pfa::forward(a1, B, o);
-        if (l == 0) {  // bin 0 (a = 0, b = 0): the vector's sum
-            o[0][0].x = Sr * f;
-            o[0][1].x = Si * f;
-        }
-        pfa::u4 *dst = Gx + vec * pfa::kUnits;
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                const pfa::f4 re = o[s][2 * t], im = o[s][2 * t + 1];
-                dst[(2 * t + s) * 64 + l] = pfa::u4{pfa::pack2(re.x, re.y), pfa::pack2(re.z, re.w),
-                                                    pfa::pack2(im.x, im.y), pfa::pack2(im.z, im.w)};
-            }
-        if (c == 0) {
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                const pfa::f4 re = o[s][4], im = o[s][5];
-                dst[pfa::kTailUnit + 4 * s + g] = pfa::u4{pfa::pack2(re.x, re.y), pfa::pack2(re.z, re.w),
-                                                          pfa::pack2(im.x, im.y), pfa::pack2(im.z, im.w)};
-            }
-        }
-        if (l == 0) E[vec] = e;
+        fft_x_vector(xs, B, Gx + vec * pfa::kUnits, E + vec, l);
     }
 }
 
