@@ -97,6 +97,11 @@ def workload(name: str, code_fn):
         snap, srch = synth.weak_complex_int8(code_fn, seed=2)
         desc = ("weak-signal complex int8 baseband, fs 16.368 MHz, 100 ms, 8 planted; "
                 "32 PRN x 121 Doppler (+-7.5 kHz / 125 Hz) x 16368 phases, 4 ms coh x 25 noncoh")
+    elif name == "weak10":
+        snap, srch = synth.weak_complex_int8(code_fn, seed=2, fs=10000000)
+        desc = ("weak-signal complex int8 baseband at a general rate, fs 10.000 MHz, 100 ms, 8 planted; "
+                "32 PRN x 121 Doppler (+-7.5 kHz / 125 Hz) x 10000 phases, 4 ms coh x 25 noncoh "
+                "(zero-padded 32768-point FP32 transforms)")
     elif name == "strong":
         snap, srch = synth.strong_real_2bit(code_fn, seed=1)
         desc = ("strong-signal real 2-bit IF, fs 4.092 MHz, f_IF 1.023 MHz, 10 ms, 4 planted; "
@@ -168,7 +173,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="weak", choices=["weak", "strong", "batch", "serve", "track", "precision"])
+    ap.add_argument("--workload", default="weak",
+                    choices=["weak", "weak10", "strong", "batch", "serve", "track", "precision"])
     ap.add_argument("--batch-n", type=int, default=256, help="snapshots in the batch workload")
     ap.add_argument("--rates", default="50,200,800", help="serve: Poisson arrival rates, req/s")
     ap.add_argument("--serve-n", type=int, default=2000, help="serve: timed requests per rate")
@@ -294,16 +300,30 @@ def main():
     units = n_prn * nd * srch.N_noncoh  # (PRN, Doppler, block) correlations per launch
     flops_unit = 5.0 * N * math.log2(N) + 10.0 * N
     wl = args.workload
-    kern = CORR_KERNEL[args.precision]
-    traffic = read_traffic(kern[2:], wl)
-    roofline = corr_roofline(args.precision, units * flops_unit, corr_ms, traffic, units * (N // 1023))
+    general = snap.fs_hz % 1023000 != 0 or snap.fs_hz // 1023000 > 16
+    if general:
+        # a rate that is not a multiple of the chip rate: the zero-padded FP32
+        # transforms in every precision
+        roofline = corr_roofline("fp32", units * flops_unit, corr_ms, read_traffic("gen_corr", wl), 0)
+        roofline["kernel"] = "k_gen_corr"
+    else:
+        kern = CORR_KERNEL[args.precision]
+        roofline = corr_roofline(args.precision, units * flops_unit, corr_ms, read_traffic(kern[2:], wl),
+                                 units * (N // 1023))
 
     # the FFT pipeline (forward FFT + correlation stages) against the HBM roofline:
     # staged-model bytes, each stage buffer crossing HBM once (F in, G out, G in,
-    # grid out), over the two stages' measured time
-    n_vec = nd * srch.N_noncoh * (N // 1023)
-    g_vec = G_VEC_BYTES[args.precision]
-    staged = n_vec * (8192 + 2 * g_vec) + n_prn * nd * N * 4
+    # grid out; general rates: the folded-block spectra out and in, the grid out),
+    # over the two stages' measured time
+    if general:
+        M = 64
+        while M < 2 * N:
+            M *= 2
+        staged = nd * srch.N_noncoh * M * 8 * 2 + n_prn * nd * N * 4
+    else:
+        n_vec = nd * srch.N_noncoh * (N // 1023)
+        g_vec = G_VEC_BYTES[args.precision]
+        staged = n_vec * (8192 + 2 * g_vec) + n_prn * nd * N * 4
     pipe_ms = stages["fft"][0] / max(1, stages["fft"][1]) + corr_ms
     fft_hbm = {"staged_bytes": staged, "time_ms": round(pipe_ms, 4),
                "achieved_GBs": round(staged / (pipe_ms / 1e3) / 1e9, 1), "peak_GBs": PEAK_HBM_GBS,
@@ -336,7 +356,7 @@ def main():
                        "planted_found": sorted(planted & detected)},
         "source_hash": kernel_source_hash(),
     }
-    if not args.no_other_modes and args.precision == "fp32" and not args.doppler_fd:
+    if not args.no_other_modes and args.precision == "fp32" and not args.doppler_fd and not general:
         out["other_modes"] = other_modes(args, G, torch, d_x, snap, srch, cells, stream)
     if (not args.no_extras and args.workload == "weak" and args.precision == "fp32" and not args.doppler_fd):
         codes = {p: code_fn(p) for p in range(1, 38)}  # the GPU's codes, kept past this context

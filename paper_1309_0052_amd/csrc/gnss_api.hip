@@ -283,6 +283,7 @@ void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, gnss:
     long long tot[gnss::kNumStages] = {};
     long long vec = 0, qk = 0, part = 0, grid_int = 0, fd_f2 = 0, gen_f2 = 0;
     B.gen_first = -1;
+    B.gen_pmask = 0;
     for (int r = 0; r < n; ++r) {
         const gnss::Plan &p = plans[r];
         gnss::ReqDesc &d = B.d[r];
@@ -306,6 +307,7 @@ void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, gnss:
             d.gen = 1;
             d.gen_M = p.gen_M;
             d.gen_P = std::min(p.gen_M, gnss::kGenLds);
+            B.gen_pmask |= (unsigned)d.gen_P;
             d.gen_x_off = gen_f2;
             d.gen_c_off = gen_f2 + (long long)p.n_dopp * p.Nnc * p.gen_M;
             gen_f2 += ((long long)p.n_dopp * p.Nnc + p.n_prn) * p.gen_M;
@@ -499,6 +501,7 @@ int stage_batch(gnss_ctx *c, Workspace &w, BatchHost &B, hipStream_t s, gnss::La
     L.fd = B.fd;
     L.nav_pairs = c->nav_pairs;
     L.gen_off = B.gen_off;
+    L.gen_pmask = B.gen_pmask;
     for (int st = 0; st < gnss::kNumStages; ++st) L.total[st] = B.total[st];
     return GNSS_OK;
 }

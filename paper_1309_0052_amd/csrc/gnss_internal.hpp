@@ -181,6 +181,7 @@ struct Launch {
     int fd;                       // 1: frequency-domain Doppler (exact-length contexts)
     int nav_pairs;                // 1: navigation-bit hypotheses (exact-length contexts)
     size_t gen_off;               // bytes of the spectrum buffer before its general-rate region
+    unsigned gen_pmask;           // general-rate transform lengths P present (bit P)
 };
 
 // Device-resident tables of a context.

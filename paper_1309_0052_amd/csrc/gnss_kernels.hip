@@ -504,7 +504,9 @@ __global__ __launch_bounds__(256) void k_box(const ReqDesc *__restrict__ R, Batc
         if (it < 0) break;
         const int r = find_req(pst, n_req, it);
         const ReqDesc &d = R[r];
-        const int kb = (int)(it - pst[r]);  // (Doppler, block); < 2^31 by the plan checks
+        // (Doppler, block)-major items (dealing them block-major, so that the bins of
+        // a block share its samples in L2, was measured 15% slower)
+        const int kb = (int)(it - pst[r]);  // < 2^31 by the plan checks
         const int k = kb / d.Nnc, b = kb - (kb / d.Nnc) * d.Nnc;
         box_item<256>(d, k, b, s_lut, s_f, F + (d.vec_off + (long long)kb * d.spc) * kPolyLen);
     }
@@ -1915,7 +1917,7 @@ __global__ __launch_bounds__(kSynthThreads) void k_fd_synth(const ReqDesc *__res
 //   R[tau] = sum_n f[n] c[(n - tau) mod N] = IDFT_M(DFT_M(f) conj(DFT_M(cc)))[M - N + tau] / M
 // (no wrap-around because M >= 2N).  FP32 throughout, in every context
 // precision.  A transform of P <= 16384 points runs in one workgroup's LDS
-// (1024 threads, radix-4 passes with one radix-2 pass for odd log2 P); for
+// (1024 threads, in-place radix-8 passes and one radix-2 or 4 pass); for
 // M = 32768 the even and odd bins are two 16384-point transforms:
 //   X[2k] = DFT_P(x[j] + x[j + P])[k],  X[2k + 1] = DFT_P((x[j] - x[j + P]) W_M^j)[k],
 // and the inverse's upper half (the only outputs needed, as N <= M/2) is
@@ -1925,105 +1927,188 @@ __global__ __launch_bounds__(kSynthThreads) void k_fd_synth(const ReqDesc *__res
 // in, natural out), so spectra are multiplied in the order they are stored.
 // ===========================================================================
 
-// W_{4s}^(j m) from the table of W_32768^i (forward sign)
-__device__ __forceinline__ float2 gen_tw(const float2 *tw, int s, int jm)
+// Radix of the LDS passes.  Radix 8 keeps a butterfly's 8 values and their
+// twiddles within about half the registers of a radix-16 one, so the
+// correlation kernel can also hold its per-lag state at 1024 threads.
+constexpr int kGenRad = 8;
+// LDS layout of a transform: element i at i + i/32 (one unused slot per 32),
+// which spreads the strided accesses of the small-span passes over the banks
+constexpr int kGenLdsPad = kGenLds + kGenLds / 32;
+__device__ __forceinline__ int gx(int i) { return i + (i >> 5); }
+
+// The first octant of the P-point twiddles, s_tw[i] = W_P^i for i < P/8,
+// taken from the table of W_32768^i (forward sign).  A pass of span s needs
+// W_{8s}^j = W_P^(j P / 8s) with j < s, always in this octant.
+__device__ __forceinline__ void gen_load_tw(float2 *s_tw, int P, const float2 *tw)
 {
-    return tw[(jm * (kGenTwLen / 4 / s)) & (kGenTwLen - 1)];
+    const int st = kGenTwLen / P;
+    for (int i = threadIdx.x; i < P / kGenRad; i += kGenThreads) s_tw[i] = tw[i * st];
 }
 
-// Forward radix-4 pass, span s: (x0..x3) at i0 + {0, s, 2s, 3s} -> the four
-// outputs of the 4-point DFT times W_{4s}^(j r), r = 0..3, in place.
-__device__ __forceinline__ void gen_fwd4(float2 *x, int P, int s, const float2 *tw)
+// w[r] = W^(j r) for r = 1..7 from w1 = W^j: products of at most three
+// table values, a few ulp from the correctly rounded twiddles
+__device__ __forceinline__ void gen_powers(float2 (&w)[kGenRad], float2 w1)
 {
-    for (int t = threadIdx.x; t < P / 4; t += kGenThreads) {
-        const int j = t & (s - 1), i0 = ((t - j) << 2) + j;
-        const float2 x0 = x[i0], x1 = x[i0 + s], x2 = x[i0 + 2 * s], x3 = x[i0 + 3 * s];
-        const float2 a0 = c_add(x0, x2), a1 = c_sub(x0, x2), b0 = c_add(x1, x3);
-        const float2 d = c_sub(x1, x3), b1 = make_float2(d.y, -d.x);  // -i (x1 - x3)
-        x[i0] = c_add(a0, b0);
-        x[i0 + s] = c_mul(c_add(a1, b1), gen_tw(tw, s, j));
-        x[i0 + 2 * s] = c_mul(c_sub(a0, b0), gen_tw(tw, s, 2 * j));
-        x[i0 + 3 * s] = c_mul(c_sub(a1, b1), gen_tw(tw, s, 3 * j));
+    w[1] = w1;
+    w[2] = c_mul(w1, w1);
+    w[3] = c_mul(w[2], w1);
+    w[4] = c_mul(w[2], w[2]);
+    w[5] = c_mul(w[4], w1);
+    w[6] = c_mul(w[3], w[3]);
+    w[7] = c_mul(w[4], w[3]);
+}
+
+// One radix-8 pass of span S over a P-point transform (both powers of two,
+// compile time), one butterfly per thread-iteration on the 8 values at
+// i0 + r S, i0 = 8 (t - j) + j, j = t mod S, in place.  Forward (decimation
+// in frequency): 8-point DFT, then output r times W_{8S}^(j r).  Inverse:
+// the adjoint, conjugate twiddles first.  In the padded layout
+// gx(i0 + r S) = gx(i0) + r S + floor(r S / 32) for every such i0, so only
+// gx(i0) is computed.
+template <int P, int S, bool INV>
+__device__ __forceinline__ void gen_pass(float2 *x, const float2 *s_tw)
+{
+    constexpr int ts = P / kGenRad / S;
+#pragma unroll 1
+    for (int t = threadIdx.x; t < P / kGenRad; t += kGenThreads) {
+        const int j = t & (S - 1);
+        float2 *base = x + gx((t - j) * kGenRad + j);
+        float2 v[kGenRad], w[kGenRad];
+#pragma unroll
+        for (int r = 0; r < kGenRad; ++r) v[r] = base[r * S + ((r * S) >> 5)];
+        if constexpr (S > 1) gen_powers(w, s_tw[j * ts]);
+        if constexpr (INV) {
+            if constexpr (S > 1) {
+#pragma unroll
+                for (int r = 1; r < kGenRad; ++r) v[r] = c_mulc(v[r], w[r]);
+            }
+            dft8<true, false, false, 0>(v);
+        } else {
+            dft8<false, false, false, 0>(v);
+            if constexpr (S > 1) {
+#pragma unroll
+                for (int r = 1; r < kGenRad; ++r) v[r] = c_mul(v[r], w[r]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kGenRad; ++r) base[r * S + ((r * S) >> 5)] = v[r];
     }
 }
 
-// Adjoint of gen_fwd4 (inverse transform, unnormalised).
-__device__ __forceinline__ void gen_inv4(float2 *x, int P, int s, const float2 *tw)
+// The last pass of span 1 when P is not a power of 8: DFTs of R = 2 or 4
+// consecutive values (no twiddles; gx(i0 + r) = gx(i0) + r, as R <= 4
+// values never cross a 32-slot row).
+template <int P, int R, bool INV>
+__device__ __forceinline__ void gen_tail(float2 *x)
 {
-    for (int t = threadIdx.x; t < P / 4; t += kGenThreads) {
-        const int j = t & (s - 1), i0 = ((t - j) << 2) + j;
-        const float2 u0 = x[i0];
-        const float2 u1 = c_mulc(x[i0 + s], gen_tw(tw, s, j));
-        const float2 u2 = c_mulc(x[i0 + 2 * s], gen_tw(tw, s, 2 * j));
-        const float2 u3 = c_mulc(x[i0 + 3 * s], gen_tw(tw, s, 3 * j));
-        const float2 p0 = c_add(u0, u2), p1 = c_sub(u0, u2), q0 = c_add(u1, u3);
-        const float2 d = c_sub(u1, u3), q1 = make_float2(-d.y, d.x);  // +i (u1 - u3)
-        x[i0] = c_add(p0, q0);
-        x[i0 + s] = c_add(p1, q1);
-        x[i0 + 2 * s] = c_sub(p0, q0);
-        x[i0 + 3 * s] = c_sub(p1, q1);
+    for (int t = threadIdx.x; t < P / R; t += kGenThreads) {
+        float2 *base = x + gx(t * R);
+        if constexpr (R == 2) {
+            const float2 a = base[0], b = base[1];
+            base[0] = c_add(a, b);
+            base[1] = c_sub(a, b);
+        } else {
+            float2 v0 = base[0], v1 = base[1], v2 = base[2], v3 = base[3];
+            dft4<INV>(v0, v1, v2, v3);
+            base[0] = v0;
+            base[1] = v1;
+            base[2] = v2;
+            base[3] = v3;
+        }
     }
 }
 
-// Radix-2 pass of span 1 (its own adjoint).
-__device__ __forceinline__ void gen_pass2(float2 *x, int P)
+// the factor of P left after its radix-8 passes (1, 2 or 4)
+constexpr int gen_tail_radix(int P)
 {
-    for (int t = threadIdx.x; t < P / 2; t += kGenThreads) {
-        const float2 x0 = x[2 * t], x1 = x[2 * t + 1];
-        x[2 * t] = c_add(x0, x1);
-        x[2 * t + 1] = c_sub(x0, x1);
-    }
+    int R = 1;
+    while (R * kGenRad <= P) R *= kGenRad;
+    return P / R;
 }
 
-// P-point forward transform in LDS (natural order in, digit-reversed out).
-// Callers synchronise before (the data are written) and after.
-__device__ void gen_forward(float2 *x, int P, const float2 *tw)
+// forward passes of spans S, S/8, ..., 1 (each followed by a barrier)
+template <int P, int S>
+__device__ __forceinline__ void gen_fwd_passes(float2 *x, const float2 *s_tw)
 {
-    int s = P / 4;
-    for (; s >= 1; s /= 4) {
-        gen_fwd4(x, P, s, tw);
+    if constexpr (S >= 1) {
+        gen_pass<P, S, false>(x, s_tw);
         __syncthreads();
+        gen_fwd_passes<P, S / kGenRad>(x, s_tw);
     }
-    if ((P & 0x55555555) == 0) {  // log2 P odd: the last radix-4 span was 2
-        gen_pass2(x, P);
+}
+
+// inverse passes of spans S, 8S, ..., P/8
+template <int P, int S>
+__device__ __forceinline__ void gen_inv_passes(float2 *x, const float2 *s_tw)
+{
+    if constexpr (S <= P / kGenRad) {
+        gen_pass<P, S, true>(x, s_tw);
+        __syncthreads();
+        gen_inv_passes<P, S * kGenRad>(x, s_tw);
+    }
+}
+
+// P-point forward transform in LDS (natural order in, digit-reversed out):
+// radix-8 passes of spans P/8, P/64, ... and a last radix-2 or 4 pass when
+// P is not a power of 8.  Callers synchronise before (the data and s_tw are
+// written) and after.
+template <int P>
+__device__ __forceinline__ void gen_forward(float2 *x, const float2 *s_tw)
+{
+    gen_fwd_passes<P, P / kGenRad>(x, s_tw);
+    constexpr int R = gen_tail_radix(P);
+    if constexpr (R > 1) {
+        gen_tail<P, R, false>(x);
         __syncthreads();
     }
 }
 
 // Exact adjoint of gen_forward: digit-reversed in, natural order out,
 // unnormalised exp(+2 pi i nk / P).
-__device__ void gen_inverse(float2 *x, int P, const float2 *tw)
+template <int P>
+__device__ __forceinline__ void gen_inverse(float2 *x, const float2 *s_tw)
 {
-    int s;
-    if ((P & 0x55555555) == 0) {
-        gen_pass2(x, P);
-        __syncthreads();
-        s = 2;
-    } else {
-        s = 1;
-    }
-    for (; s <= P / 4; s *= 4) {
-        gen_inv4(x, P, s, tw);
+    constexpr int R = gen_tail_radix(P);
+    if constexpr (R > 1) {
+        gen_tail<P, R, true>(x);
         __syncthreads();
     }
+    gen_inv_passes<P, R>(x, s_tw);
 }
+
+// The thread index through an empty asm statement, so that the compiler
+// does not hoist the per-lag addresses derived from it out of the loops
+// (16 lags x 64-bit addresses, held across the transforms, spill).
+__device__ __forceinline__ int opaque_tid()
+{
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
+// The general-rate kernels are instantiated per transform length P and
+// launched once for each length present in a batch; items of requests with
+// another length are skipped.
 
 // Code spectra of a general-rate request: item = (request, PRN).
 // CC[p][h P + i] = DFT_M(cc)[bin of storage position i of half h].
+template <int P>
 __global__ __launch_bounds__(kGenThreads) void k_gen_code(const ReqDesc *__restrict__ R, const BatchHdr *H,
                                                           const long long *pre, const uint8_t *codes,
                                                           const float2 *tw, float2 *gen)
 {
-    __shared__ float2 x[kGenLds];
+    __shared__ float2 x[kGenLdsPad];
+    __shared__ float2 s_tw[kGenLds / kGenRad];
     const int n_req = H->n_req;
     const long long total = H->total[kStGenC];
     const long long *pst = pre + (long long)kStGenC * (n_req + 1);
     for (long long it = blockIdx.x; it < total; it += gridDim.x) {
         const int r = find_req(pst, n_req, it);
         const ReqDesc &d = R[r];
+        if (d.gen_P != P) continue;
         const int pi = (int)(it - pst[r]);
         const uint8_t *code = codes + (long long)d.prns[pi] * kCodeLen;
-        const int N = d.N, M = d.gen_M, P = d.gen_P;
+        const int N = d.N, M = d.gen_M;
         const long long fs = (long long)N * 1000;
         float2 *dst = gen + d.gen_c_off + (long long)pi * M;
         // c[j mod N] for j < 2N, else 0
@@ -2033,21 +2118,24 @@ __global__ __launch_bounds__(kGenThreads) void k_gen_code(const ReqDesc *__restr
             return code[(n * 1023000LL / fs) % kCodeLen] ? -1.f : 1.f;
         };
         for (int h = 0; h < M / P; ++h) {
-            __syncthreads();
+            __syncthreads();  // the previous transform's outputs are read
+            if (h == 0) gen_load_tw(s_tw, P, tw);
             for (int j = threadIdx.x; j < P; j += kGenThreads) {
+                float2 v;
                 if (M == P) {
-                    x[j] = make_float2(cc(j), 0.f);
+                    v = make_float2(cc(j), 0.f);
                 } else if (h == 0) {
-                    x[j] = make_float2(cc(j) + cc(j + P), 0.f);
+                    v = make_float2(cc(j) + cc(j + P), 0.f);
                 } else {
-                    const float v = cc(j) - cc(j + P);
+                    const float c = cc(j) - cc(j + P);
                     const float2 w = tw[j];  // W_M^j, M = 32768
-                    x[j] = make_float2(v * w.x, v * w.y);
+                    v = make_float2(c * w.x, c * w.y);
                 }
+                x[gx(j)] = v;
             }
             __syncthreads();
-            gen_forward(x, P, tw);
-            for (int j = threadIdx.x; j < P; j += kGenThreads) dst[(long long)h * P + j] = x[j];
+            gen_forward<P>(x, s_tw);
+            for (int j = threadIdx.x; j < P; j += kGenThreads) dst[(long long)h * P + j] = x[gx(j)];
         }
     }
 }
@@ -2056,12 +2144,15 @@ __global__ __launch_bounds__(kGenThreads) void k_gen_code(const ReqDesc *__restr
 // block).  The carrier NCO, first mixing stage and fold of the block (the
 // integer arithmetic of the polyphase path), delayed circularly by the
 // code-Doppler shift if any, then the zero-padded forward transform.
+template <int P>
 __global__ __launch_bounds__(kGenThreads) void k_gen_x(const ReqDesc *__restrict__ R, const BatchHdr *H,
                                                        const long long *pre, const uint32_t *lut, const float2 *tw,
                                                        float2 *gen)
 {
-    __shared__ float2 x[kGenLds];
+    __shared__ float2 x[kGenLdsPad];
+    __shared__ float2 s_tw[kGenLds / kGenRad];
     __shared__ uint32_t s_lut[1024];
+    constexpr int kPer = kGenMaxN / kGenThreads;
     for (int i = threadIdx.x; i < 1024; i += kGenThreads) s_lut[i] = lut[i];
     const int n_req = H->n_req;
     const long long total = H->total[kStGenX];
@@ -2069,16 +2160,20 @@ __global__ __launch_bounds__(kGenThreads) void k_gen_x(const ReqDesc *__restrict
     for (long long it = blockIdx.x; it < total; it += gridDim.x) {
         const int r = find_req(pst, n_req, it);
         const ReqDesc &d = R[r];
+        if (d.gen_P != P) continue;
         const long long local = it - pst[r];
         const int k = (int)(local / d.Nnc), b = (int)(local % d.Nnc);
-        const int N = d.N, M = d.gen_M, P = d.gen_P;
+        const int N = d.N, M = d.gen_M;
         const uint32_t D = d.dk[k];
         const int shift = d.cshift ? d.cshift[(long long)k * d.Nnc + b] : 0;
-        float2 f[kGenMaxN / kGenThreads];  // the folded block, n = tid + 1024 i
-        __syncthreads();  // s_lut staged; the previous item's reads of x are done
+        __syncthreads();  // s_lut staged; the previous item's reads of x and s_tw are done
+        gen_load_tw(s_tw, P, tw);
+        // the folded block, n = tid + 1024 i (zero at n >= N)
+        float2 f[kPer];
+        int tid = opaque_tid();
 #pragma unroll
-        for (int i = 0; i < kGenMaxN / kGenThreads; ++i) {
-            const int n = threadIdx.x + kGenThreads * i;
+        for (int i = 0; i < kPer; ++i) {
+            const int n = tid + kGenThreads * i;
             f[i] = make_float2(0.f, 0.f);
             if (n < N) {
                 int m = n - shift;
@@ -2089,83 +2184,149 @@ __global__ __launch_bounds__(kGenThreads) void k_gen_x(const ReqDesc *__restrict
         }
         float2 *dst = gen + d.gen_x_off + local * M;
         for (int h = 0; h < M / P; ++h) {
+            if (h) __syncthreads();  // the previous half's outputs are read
+            tid = opaque_tid();
 #pragma unroll
-            for (int i = 0; i < kGenMaxN / kGenThreads; ++i) {
-                const int n = threadIdx.x + kGenThreads * i;
+            for (int i = 0; i < kPer; ++i) {
+                const int n = tid + kGenThreads * i;
                 if (n < P) {
-                    // N <= P: the block has no samples at n + P
+                    // N <= P: the block has no samples at n + P; the odd-bin
+                    // half takes it times W_M^n
                     float2 v = f[i];
                     if (h == 1) v = c_mul(v, tw[n]);
-                    x[n] = v;
+                    x[gx(n)] = v;
                 }
             }
             __syncthreads();
-            gen_forward(x, P, tw);
-            for (int j = threadIdx.x; j < P; j += kGenThreads) dst[(long long)h * P + j] = x[j];
-            __syncthreads();
+            gen_forward<P>(x, s_tw);
+            for (int j = threadIdx.x; j < P; j += kGenThreads) dst[(long long)h * P + j] = x[gx(j)];
         }
     }
 }
 
-// Correlation of a general-rate request: item = (request, PRN, Doppler bin);
-// over the blocks, Z = X conj(CC), the inverse transform, |.|^2 of the lags'
-// outputs summed in registers; the grid gets sum |out|^2 2^-24 / M^2.
+// One correlation item of length P (see k_gen_corr).
+template <int P>
+__device__ __forceinline__ void gen_corr_item(const ReqDesc &d, int k, int pi, const float2 *tw, const float2 *gen,
+                                              float2 *x, float2 *s_tw)
+{
+    constexpr int kPer = kGenMaxN / kGenThreads;
+    constexpr int kFill = 8;  // product values loaded per thread before they are stored
+    const int N = d.N, M = d.gen_M;
+    const float2 *C = gen + d.gen_c_off + (long long)pi * M;
+    // 2^-24 (LUT scale) / M^2 (two unnormalised transforms), an exact power of two
+    const float scale = ldexpf(1.f, -24 - 2 * (31 - __clz(M)));
+    GNSS_GLOBAL float *row = gmem(d.grid) + ((long long)pi * d.n_dopp + k) * N;
+    // fill x with the product of the half-h spectra of block b; the first
+    // loads are issued before the barrier that frees x
+    auto product = [&](int b, int h, bool first) {
+        const float2 *X = gen + d.gen_x_off + ((long long)k * d.Nnc + b) * M + (long long)h * P;
+        const float2 *Ch = C + (long long)h * P;
+        const int tid = opaque_tid();
+        for (int j0 = 0; j0 < P; j0 += kFill * kGenThreads) {
+            float2 xv[kFill], cv[kFill];
+#pragma unroll
+            for (int u = 0; u < kFill; ++u) {
+                const int j = j0 + u * kGenThreads + tid;
+                if (j < P) {
+                    xv[u] = X[j];
+                    cv[u] = Ch[j];
+                }
+            }
+            if (j0 == 0) {
+                __syncthreads();  // the previous inverse's outputs are read
+                if (first) gen_load_tw(s_tw, P, tw);
+            }
+#pragma unroll
+            for (int u = 0; u < kFill; ++u) {
+                const int j = j0 + u * kGenThreads + tid;
+                if (j < P) x[gx(j)] = c_mulc(xv[u], cv[u]);
+            }
+        }
+        __syncthreads();
+    };
+    if (M == P) {
+        // lag tau is output M - N + tau
+        float acc[kPer];
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) acc[i] = 0.f;
+        for (int b = 0; b < d.Nnc; ++b) {
+            product(b, 0, b == 0);
+            gen_inverse<P>(x, s_tw);
+            const int tid = opaque_tid();
+#pragma unroll
+            for (int i = 0; i < kPer; ++i) {
+                const int tau = tid + kGenThreads * i;
+                if (tau < N) {
+                    const float2 o = x[gx(P - N + tau)];
+                    acc[i] = fmaf(o.x, o.x, fmaf(o.y, o.y, acc[i]));
+                }
+            }
+        }
+        const int tid = opaque_tid();
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int tau = tid + kGenThreads * i;
+            if (tau < N) row[tau] = acc[i] * scale;
+        }
+    } else if constexpr (P == kGenLds) {
+        // M = 2P: lag tau is output P + kk, kk = P - N + tau
+        for (int b = 0; b < d.Nnc; ++b) {
+            float2 a[kPer];
+            product(b, 0, b == 0);
+            gen_inverse<P>(x, s_tw);
+            // a[] written at every i, so that it is not carried from one
+            // block to the next
+            int tid = opaque_tid();
+#pragma unroll
+            for (int i = 0; i < kPer; ++i) {
+                const int tau = tid + kGenThreads * i;
+                a[i] = tau < N ? x[gx(P - N + tau)] : make_float2(0.f, 0.f);
+            }
+            product(b, 1, false);
+            gen_inverse<P>(x, s_tw);
+            tid = opaque_tid();  // not the first loop's: its lag indices are not kept
+            const bool last = b == d.Nnc - 1;
+#pragma unroll
+            for (int i = 0; i < kPer; ++i) {
+                const int tau = tid + kGenThreads * i;
+                if (tau < N) {
+                    const int kk = P - N + tau;
+                    // A - W_M^-kk B
+                    const float2 v = c_sub(a[i], c_mulc(x[gx(kk)], tw[kk]));
+                    float acc = fmaf(v.x, v.x, fmaf(v.y, v.y, b ? row[tau] : 0.f));
+                    row[tau] = last ? acc * scale : acc;
+                }
+            }
+        }
+    }
+}
+
+// Correlation of a general-rate request: item = (request, Doppler bin, PRN),
+// Doppler-major so that the workgroups running together share the block
+// spectra; over the blocks, Z = X conj(CC), the inverse transform and |.|^2
+// of the lags' outputs, summed in block order; the grid gets
+// sum |out|^2 2^-24 / M^2.  For M = P the sums stay in registers; for M = 2P
+// each lag needs the two half transforms' outputs together (A - W_M^-k B),
+// so A is held in registers and the running sum is kept in the grid row
+// itself (read and written by the same thread, scaled when the last block
+// is added).
+template <int P>
 __global__ __launch_bounds__(kGenThreads) void k_gen_corr(const ReqDesc *__restrict__ R, const BatchHdr *H,
                                                           const long long *pre, const float2 *tw,
                                                           const float2 *gen)
 {
-    __shared__ float2 x[kGenLds];
-    constexpr int kPer = kGenMaxN / kGenThreads;
+    __shared__ float2 x[kGenLdsPad];
+    __shared__ float2 s_tw[kGenLds / kGenRad];
     const int n_req = H->n_req;
     const long long total = H->total[kStGenCorr];
     const long long *pst = pre + (long long)kStGenCorr * (n_req + 1);
     for (long long it = blockIdx.x; it < total; it += gridDim.x) {
         const int r = find_req(pst, n_req, it);
         const ReqDesc &d = R[r];
+        if (d.gen_P != P) continue;
         const long long local = it - pst[r];
-        const int pi = (int)(local / d.n_dopp), k = (int)(local % d.n_dopp);
-        const int N = d.N, M = d.gen_M, P = d.gen_P;
-        const float2 *C = gen + d.gen_c_off + (long long)pi * M;
-        float acc[kPer];
-#pragma unroll
-        for (int i = 0; i < kPer; ++i) acc[i] = 0.f;
-        for (int b = 0; b < d.Nnc; ++b) {
-            const float2 *X = gen + d.gen_x_off + ((long long)k * d.Nnc + b) * M;
-            float2 a[kPer];
-            for (int h = 0; h < M / P; ++h) {
-                __syncthreads();  // the previous inverse's outputs are read
-                for (int j = threadIdx.x; j < P; j += kGenThreads)
-                    x[j] = c_mulc(X[(long long)h * P + j], C[(long long)h * P + j]);
-                __syncthreads();
-                gen_inverse(x, P, tw);
-                // lag tau is output M - N + tau; for M = 2P it is P + kk, kk = P - N + tau
-#pragma unroll
-                for (int i = 0; i < kPer; ++i) {
-                    const int tau = threadIdx.x + kGenThreads * i;
-                    if (tau < N) {
-                        const int kk = P - N + tau;
-                        const float2 o = x[kk];
-                        if (M == P) {
-                            acc[i] = fmaf(o.x, o.x, fmaf(o.y, o.y, acc[i]));
-                        } else if (h == 0) {
-                            a[i] = o;
-                        } else {
-                            // A - W_M^-kk B
-                            const float2 v = c_sub(a[i], c_mulc(o, tw[kk]));
-                            acc[i] = fmaf(v.x, v.x, fmaf(v.y, v.y, acc[i]));
-                        }
-                    }
-                }
-            }
-        }
-        // 2^-24 (LUT scale) / M^2 (two unnormalised transforms), an exact power of two
-        const float scale = ldexpf(1.f, -24 - 2 * (31 - __clz(M)));
-        GNSS_GLOBAL float *row = gmem(d.grid) + ((long long)pi * d.n_dopp + k) * N;
-#pragma unroll
-        for (int i = 0; i < kPer; ++i) {
-            const int tau = threadIdx.x + kGenThreads * i;
-            if (tau < N) row[tau] = acc[i] * scale;
-        }
+        const int k = (int)(local / d.n_prn), pi = (int)(local % d.n_prn);
+        gen_corr_item<P>(d, k, pi, tw, gen, x, s_tw);
     }
 }
 
@@ -2424,6 +2585,23 @@ static hipError_t launch_fd(const Launch &L, const Tables &T, void *d_fd, void *
     return hipSuccess;
 }
 
+// Calls f(std::integral_constant<int, Q>()) for each general-rate transform
+// length Q >= P whose bit is set in mask (bit Q, a power of two), in
+// increasing order; stops at the first error.
+template <int P, typename F>
+static hipError_t gen_lengths(unsigned mask, F &f)
+{
+    if constexpr (P > kGenLds) {
+        return hipSuccess;
+    } else {
+        if (mask & (unsigned)P) {
+            const hipError_t e = f(std::integral_constant<int, P>());
+            if (e != hipSuccess) return e;
+        }
+        return gen_lengths<P * 2>(mask, f);
+    }
+}
+
 hipError_t launch_batch(const Launch &L, const Tables &T, int2 *d_F, void *d_G, float *d_Q, int32_t *d_K,
                         float *d_part, int n_cu, hipStream_t s, hipEvent_t *marks)
 {
@@ -2475,18 +2653,28 @@ hipError_t launch_batch(const Launch &L, const Tables &T, int2 *d_F, void *d_G, 
     }
     if (L.total[kStGenX] > 0) {  // general rates: code spectra and block spectra
         float2 *d_gen = (float2 *)((char *)d_G + L.gen_off);
-        hipLaunchKernelGGL(k_gen_code, dim3(grid_for(L.total[kStGenC], 65535, false)), dim3(kGenThreads), 0, s,
-                           L.reqs, L.hdr, L.pre, T.codes, T.tw_gen, d_gen);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_gen_x, dim3(grid_for(L.total[kStGenX], 65535, false)), dim3(kGenThreads), 0, s,
-                           L.reqs, L.hdr, L.pre, d_lut, T.tw_gen, d_gen);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        auto spectra = [&](auto pc) -> hipError_t {
+            constexpr int P = decltype(pc)::value;
+            hipLaunchKernelGGL(k_gen_code<P>, dim3(grid_for(L.total[kStGenC], 65535, false)), dim3(kGenThreads), 0,
+                               s, L.reqs, L.hdr, L.pre, T.codes, T.tw_gen, d_gen);
+            hipError_t e2 = hipGetLastError();
+            if (e2 != hipSuccess) return e2;
+            hipLaunchKernelGGL(k_gen_x<P>, dim3(grid_for(L.total[kStGenX], 65535, false)), dim3(kGenThreads), 0, s,
+                               L.reqs, L.hdr, L.pre, d_lut, T.tw_gen, d_gen);
+            return hipGetLastError();
+        };
+        if ((e = gen_lengths<64>(L.gen_pmask, spectra)) != hipSuccess) return e;
     }
     if ((e = mark(2)) != hipSuccess) return e;
     if (L.total[kStGenCorr] > 0) {
-        hipLaunchKernelGGL(k_gen_corr, dim3(grid_for(L.total[kStGenCorr], 65535, false)), dim3(kGenThreads), 0,
-                           s, L.reqs, L.hdr, L.pre, T.tw_gen, (const float2 *)((char *)d_G + L.gen_off));
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const float2 *d_gen = (const float2 *)((char *)d_G + L.gen_off);
+        auto corr = [&](auto pc) -> hipError_t {
+            constexpr int P = decltype(pc)::value;
+            hipLaunchKernelGGL(k_gen_corr<P>, dim3(grid_for(L.total[kStGenCorr], 65535, false)), dim3(kGenThreads),
+                               0, s, L.reqs, L.hdr, L.pre, T.tw_gen, d_gen);
+            return hipGetLastError();
+        };
+        if ((e = gen_lengths<64>(L.gen_pmask, corr)) != hipSuccess) return e;
     }
     if (L.total[kStCorr] > 0 && x) {
         // the frequency-domain variant wipes with unit exponentials (no LUT scale 2^12)

@@ -66,6 +66,7 @@ struct BatchHost {
     int fd_bad = -1;     // first request it cannot serve, or -1
     int gen_first = -1;  // first request at a general rate (zero-padded transforms), or -1
     size_t gen_off = 0;  // bytes of the spectrum buffer before the general-rate region
+    unsigned gen_pmask = 0;  // general-rate transform lengths P present (bit P)
     // host-computed tables copied with the descriptors: carrier NCO steps of
     // every (request, Doppler bin) and, with code-Doppler compensation, the
     // lag shift of every (request, bin, block); offsets in elements

@@ -197,11 +197,10 @@ def strong_real_2bit(code_fn, seed: int = 1, fmt: int = REAL_I8):
     return snap, Search(list(range(1, 33)), -5000.0, 5000.0, 500.0, 1, 10)
 
 
-def weak_complex_int8(code_fn, seed: int = 2):
-    """Complex int8 baseband, fs 16.368 MHz, 100 ms; 8 planted PRNs at C/N0 U[28, 40]
-    dB-Hz, Doppler U[-7.5, 7.5] kHz, 20 ms nav-bit flips; search PRN 1-32,
-    +-7.5 kHz step 125 Hz, 4 ms x 25."""
-    fs = 16368000
+def weak_complex_int8(code_fn, seed: int = 2, fs: int = 16368000):
+    """Complex int8 baseband, fs 16.368 MHz (or another rate), 100 ms; 8 planted
+    PRNs at C/N0 U[28, 40] dB-Hz, Doppler U[-7.5, 7.5] kHz, 20 ms nav-bit flips;
+    search PRN 1-32, +-7.5 kHz step 125 Hz, 4 ms x 25."""
     rng = np.random.default_rng([seed, 2])
     planted = _draw_planted(rng, 8, range(1, 33), fs // 1000, 7500.0, 28.0, 40.0, True)
     snap = make_snapshot(seed, CPLX_I8, fs, 0.0, 100.0, planted, code_fn)
