@@ -2086,9 +2086,10 @@ __device__ __forceinline__ int opaque_tid()
     return t;
 }
 
-// The general-rate kernels are instantiated per transform length P and
-// launched once for each length present in a batch; items of requests with
-// another length are skipped.
+// The general-rate kernels are instantiated per transform length P < 16384
+// (LDS sized by P, so smaller transforms share a CU) and launched once for
+// each length present in a batch; items of requests with another length are
+// skipped.  P = 16384 has kernels of its own (below).
 
 // Code spectra of a general-rate request: item = (request, PRN).
 // CC[p][h P + i] = DFT_M(cc)[bin of storage position i of half h].
@@ -2097,8 +2098,8 @@ __global__ __launch_bounds__(kGenThreads) void k_gen_code(const ReqDesc *__restr
                                                           const long long *pre, const uint8_t *codes,
                                                           const float2 *tw, float2 *gen)
 {
-    __shared__ float2 x[kGenLdsPad];
-    __shared__ float2 s_tw[kGenLds / kGenRad];
+    __shared__ float2 x[P + P / 32];
+    __shared__ float2 s_tw[P / kGenRad];
     const int n_req = H->n_req;
     const long long total = H->total[kStGenC];
     const long long *pst = pre + (long long)kStGenC * (n_req + 1);
@@ -2149,8 +2150,8 @@ __global__ __launch_bounds__(kGenThreads) void k_gen_x(const ReqDesc *__restrict
                                                        const long long *pre, const uint32_t *lut, const float2 *tw,
                                                        float2 *gen)
 {
-    __shared__ float2 x[kGenLdsPad];
-    __shared__ float2 s_tw[kGenLds / kGenRad];
+    __shared__ float2 x[P + P / 32];
+    __shared__ float2 s_tw[P / kGenRad];
     __shared__ uint32_t s_lut[1024];
     constexpr int kPer = kGenMaxN / kGenThreads;
     for (int i = threadIdx.x; i < 1024; i += kGenThreads) s_lut[i] = lut[i];
@@ -2315,8 +2316,8 @@ __global__ __launch_bounds__(kGenThreads) void k_gen_corr(const ReqDesc *__restr
                                                           const long long *pre, const float2 *tw,
                                                           const float2 *gen)
 {
-    __shared__ float2 x[kGenLdsPad];
-    __shared__ float2 s_tw[kGenLds / kGenRad];
+    __shared__ float2 x[P + P / 32];
+    __shared__ float2 s_tw[P / kGenRad];
     const int n_req = H->n_req;
     const long long total = H->total[kStGenCorr];
     const long long *pst = pre + (long long)kStGenCorr * (n_req + 1);
@@ -2327,6 +2328,327 @@ __global__ __launch_bounds__(kGenThreads) void k_gen_corr(const ReqDesc *__restr
         const long long local = it - pst[r];
         const int k = (int)(local / d.n_prn), pi = (int)(local % d.n_prn);
         gen_corr_item<P>(d, k, pi, tw, gen, x, s_tw);
+    }
+}
+
+// v W_16^a (forward sign) or v W_16^-a (INV) for a < 8; a is a constant once
+// the callers' loops are unrolled
+__device__ __forceinline__ float2 twiddle16(float2 v, int a, bool inv)
+{
+    switch (a) {
+    case 0: return v;
+    case 1: return inv ? tw<16, 1, true>(v) : tw<16, 1, false>(v);
+    case 2: return inv ? tw<16, 2, true>(v) : tw<16, 2, false>(v);
+    case 3: return inv ? tw<16, 3, true>(v) : tw<16, 3, false>(v);
+    case 4: return inv ? tw<16, 4, true>(v) : tw<16, 4, false>(v);
+    case 5: return inv ? tw<16, 5, true>(v) : tw<16, 5, false>(v);
+    case 6: return inv ? tw<16, 6, true>(v) : tw<16, 6, false>(v);
+    default: return inv ? tw<16, 7, true>(v) : tw<16, 7, false>(v);
+    }
+}
+
+// a copy the compiler cannot see through (keeps per-column products from
+// being hoisted out of loops and held)
+__device__ __forceinline__ float2 opaque(float2 v)
+{
+    asm volatile("" : "+v"(v.x), "+v"(v.y));
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// P = 16384: four-step transforms, 8 x 2048.  With n = 2048 a + b and
+// k = k1 + 8 k2 (a, k1 < 8; b, k2 < 2048)
+//   X[k1 + 8 k2] = DFT_2048 over b of ( W_P^(b k1) DFT_8 over a of x[2048 a + b] )[k2]:
+// a radix-8 stage across the eight 2048-point rows (in LDS, one column b per
+// thread-iteration), then one 2048-point transform per wave (the register
+// FFT of the polyphase path, its transposes in the wave's own LDS row).  The
+// forward transform's rows end in the 2048-point storage order, so a half
+// spectrum is stored as [k1][1024 float4] exactly as that FFT leaves it; the
+// inverse is the adjoint (2048-point inverse per row, then conjugate
+// twiddles and the inverse radix-8 stage).  Two workgroup barriers per
+// transform instead of one per radix pass.
+// ---------------------------------------------------------------------------
+constexpr int kG16Threads = 512;  // eight waves, one 2048-point row each
+constexpr int kG16Cols = kGenLds / 8 / kG16Threads;  // columns b per thread (4)
+static_assert(kGenLds == 8 * 2048, "four-step split of the 16384-point transform");
+
+// Forward radix-8 stage: y[k1][b] = W_P^(b k1) sum_a x(2048 a + b) W_8^(a k1)
+// for this thread's columns b = tid + 512 j; x(j, a, b) supplies the input;
+// wb[j] = W_P^b (g16_bases).
+template <typename Src>
+__device__ __forceinline__ void g16_fwd_stage(float2 *y, const float2 (&wb)[kG16Cols], Src x)
+{
+    const int tid = opaque_tid();
+#pragma unroll
+    for (int j = 0; j < kG16Cols; ++j) {
+        const int b = tid + kG16Threads * j;
+        float2 v[8], w[8];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) v[a] = x(j, a, b);
+        dft8<false, false, false, 0>(v);
+        {
+            // opaque copy: the powers are formed here, not hoisted and held
+            gen_powers(w, opaque(wb[j]));
+        }
+#pragma unroll
+        for (int r = 1; r < 8; ++r) v[r] = c_mul(v[r], w[r]);
+#pragma unroll
+        for (int k1 = 0; k1 < 8; ++k1) y[k1 * 2048 + b] = v[k1];
+        phase_barrier();  // one column at a time (registers)
+    }
+}
+
+// W_P^b of this thread's columns b, from the table of W_32768^i (loaded once
+// per kernel: the stages' column loop would otherwise wait for each); with
+// wm, W_M^b for M = 2P = 32768, which gives W_M^(2048 a + b) = W_M^b W_16^a.
+__device__ __forceinline__ void g16_bases(float2 (&wb)[kG16Cols], float2 (&wm)[kG16Cols], const float2 *twg)
+{
+#pragma unroll
+    for (int j = 0; j < kG16Cols; ++j) {
+        wb[j] = twg[2 * (threadIdx.x + kG16Threads * j)];
+        wm[j] = twg[threadIdx.x + kG16Threads * j];
+    }
+}
+
+
+// Wave k1 transforms row k1 of y (natural order) and stores the storage-order
+// result at dst[k1][1024 float4].  The row is the wave's transpose buffer.
+__device__ __forceinline__ void g16_fwd_rows(float2 *y, const float2 *s_tw, float4 *dst)
+{
+    const int tid = opaque_tid(), w = tid >> 6, l = tid & 63;
+    float2 *row = y + w * 2048;
+    float2 v[32];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int k2b = 0; k2b < 8; ++k2b) v[8 * u + k2b] = row[l + 64 * u + 256 * k2b];
+    fft2048<false, true>(v, row, s_tw, s_tw + kT1Elems, l);
+    float4 *d = dst + w * 1024;
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj)
+        d[jj * 64 + l] = make_float4(v[2 * jj].x, v[2 * jj].y, v[2 * jj + 1].x, v[2 * jj + 1].y);
+}
+
+// Wave k1 forms row k1 of X conj(C) (half spectra in the stored layout),
+// transforms it back and leaves the natural-order row in y.  The barrier
+// that frees y (the previous stage's reads) is taken inside, after the
+// spectra are loaded, so their latency overlaps the wait.
+__device__ __forceinline__ void g16_inv_rows(float2 *y, const float2 *s_tw, const float4 *X, const float4 *C)
+{
+    // an opaque index, so that no address is hoisted out of the callers' loops
+    const int tid = opaque_tid(), w = tid >> 6, l = tid & 63;
+    float2 *row = y + w * 2048;
+    const float4 *xq = X + w * 1024, *cq = C + w * 1024;
+    float2 z[32];
+    phase_barrier();
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) {
+        const float4 t = xq[jj * 64 + l], c = cq[jj * 64 + l];
+        z[2 * jj] = c_mulc(make_float2(t.x, t.y), make_float2(c.x, c.y));
+        z[2 * jj + 1] = c_mulc(make_float2(t.z, t.w), make_float2(c.z, c.w));
+    }
+    __syncthreads();
+    ifft2048<false, true>(z, row, s_tw, s_tw + kT1Elems, l);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int k2b = 0; k2b < 8; ++k2b) row[l + 64 * u + 256 * k2b] = z[8 * u + k2b];
+}
+
+// Inverse radix-8 stage: out(2048 a + b) = sum_k1 W_8^(-a k1) W_P^(-b k1) y[k1][b]
+// for this thread's columns; f(j, a, b, value) receives each output.
+template <typename Sink>
+__device__ __forceinline__ void g16_inv_stage(const float2 *y, const float2 (&wb)[kG16Cols], Sink f)
+{
+    const int tid = opaque_tid();
+#pragma unroll
+    for (int j = 0; j < kG16Cols; ++j) {
+        const int b = tid + kG16Threads * j;
+        float2 v[8], w[8];
+#pragma unroll
+        for (int k1 = 0; k1 < 8; ++k1) v[k1] = y[k1 * 2048 + b];
+        {
+            // opaque copy: the powers are formed here, not hoisted and held
+            gen_powers(w, opaque(wb[j]));
+        }
+#pragma unroll
+        for (int r = 1; r < 8; ++r) v[r] = c_mulc(v[r], w[r]);
+        dft8<true, false, false, 0>(v);
+#pragma unroll
+        for (int a = 0; a < 8; ++a) f(j, a, b, v[a]);
+        phase_barrier();  // one column at a time (registers)
+    }
+}
+
+// Code spectra, P = 16384 (see k_gen_code).
+__global__ __launch_bounds__(kG16Threads) void k_gen_code16(const ReqDesc *__restrict__ R, const BatchHdr *H,
+                                                            const long long *pre, const uint8_t *codes,
+                                                            const float2 *tw, const float2 *twg, float2 *gen)
+{
+    constexpr int P = kGenLds;
+    __shared__ float2 y[P];
+    __shared__ float2 s_tw[kTwElems];
+    stage_twiddles(s_tw, tw, threadIdx.x, kG16Threads);
+    float2 wb[kG16Cols], wm[kG16Cols];
+    g16_bases(wb, wm, twg);
+    const int n_req = H->n_req;
+    const long long total = H->total[kStGenC];
+    const long long *pst = pre + (long long)kStGenC * (n_req + 1);
+    for (long long it = blockIdx.x; it < total; it += gridDim.x) {
+        const int r = find_req(pst, n_req, it);
+        const ReqDesc &d = R[r];
+        if (d.gen_P != P) continue;
+        const int pi = (int)(it - pst[r]);
+        const uint8_t *code = codes + (long long)d.prns[pi] * kCodeLen;
+        const int N = d.N, M = d.gen_M;
+        const long long fs = (long long)N * 1000;
+        float2 *dst = gen + d.gen_c_off + (long long)pi * M;
+        // c[j mod N] for j < 2N, else 0
+        auto cc = [&](int j) -> float {
+            if (j >= 2 * N) return 0.f;
+            const long long n = j >= N ? j - N : j;
+            return code[(n * 1023000LL / fs) % kCodeLen] ? -1.f : 1.f;
+        };
+        for (int h = 0; h < M / P; ++h) {
+            __syncthreads();  // the twiddles are staged; the previous rows are read
+            g16_fwd_stage(y, wb, [&](int j, int a, int b) -> float2 {
+                const int n = 2048 * a + b;
+                if (M == P) return make_float2(cc(n), 0.f);
+                if (h == 0) return make_float2(cc(n) + cc(n + P), 0.f);
+                const float c = cc(n) - cc(n + P);
+                const float2 w = twg[n];  // W_M^n, M = 32768
+                return make_float2(c * w.x, c * w.y);
+            });
+            __syncthreads();
+            g16_fwd_rows(y, s_tw, (float4 *)(dst + (long long)h * P));
+        }
+    }
+}
+
+// Block spectra, P = 16384 (see k_gen_x).
+__global__ __launch_bounds__(kG16Threads) void k_gen_x16(const ReqDesc *__restrict__ R, const BatchHdr *H,
+                                                         const long long *pre, const uint32_t *lut,
+                                                         const float2 *tw, const float2 *twg, float2 *gen)
+{
+    constexpr int P = kGenLds;
+    __shared__ float2 y[P];
+    __shared__ float2 s_tw[kTwElems];
+    __shared__ uint32_t s_lut[1024];
+    for (int i = threadIdx.x; i < 1024; i += kG16Threads) s_lut[i] = lut[i];
+    stage_twiddles(s_tw, tw, threadIdx.x, kG16Threads);
+    float2 wb[kG16Cols], wm[kG16Cols];
+    g16_bases(wb, wm, twg);
+    const int n_req = H->n_req;
+    const long long total = H->total[kStGenX];
+    const long long *pst = pre + (long long)kStGenX * (n_req + 1);
+    for (long long it = blockIdx.x; it < total; it += gridDim.x) {
+        const int r = find_req(pst, n_req, it);
+        const ReqDesc &d = R[r];
+        if (d.gen_P != P) continue;
+        const long long local = it - pst[r];
+        const int k = (int)(local / d.Nnc), b = (int)(local % d.Nnc);
+        const int N = d.N, M = d.gen_M;
+        const uint32_t D = d.dk[k];
+        const int shift = d.cshift ? d.cshift[(long long)k * d.Nnc + b] : 0;
+        __syncthreads();  // s_lut staged
+        // the folded block at n = 2048 a + tid + 512 j (zero at n >= N)
+        float2 f[kG16Cols][8];
+        const int tid = opaque_tid();
+#pragma unroll
+        for (int j = 0; j < kG16Cols; ++j)
+#pragma unroll
+            for (int a = 0; a < 8; ++a) {
+                const int n = 2048 * a + tid + kG16Threads * j;
+                f[j][a] = make_float2(0.f, 0.f);
+                if (n < N) {
+                    int m = n - shift;
+                    if (m < 0) m += N;
+                    const int2 v = wipe_fold_one(d.samples, d.fmt, N, d.Tc, s_lut, D, b, m);
+                    f[j][a] = make_float2((float)v.x, (float)v.y);
+                }
+            }
+        float2 *dst = gen + d.gen_x_off + local * M;
+        for (int h = 0; h < M / P; ++h) {
+            if (h) __syncthreads();  // the previous half's rows are read
+            // N <= P: no samples at n + P; the odd-bin half takes x[n] W_M^n
+            g16_fwd_stage(y, wb, [&](int j, int a, int) -> float2 {
+                if (h == 0) return f[j][a];
+                // f W_M^n, n = 2048 a + b: W_M^b W_16^a
+                return twiddle16(c_mul(f[j][a], opaque(wm[j])), a, false);
+            });
+            __syncthreads();
+            g16_fwd_rows(y, s_tw, (float4 *)(dst + (long long)h * P));
+        }
+    }
+}
+
+// Correlation, P = 16384 (see k_gen_corr): item = (request, Doppler bin,
+// PRN), Doppler-major; this thread's lags are the outputs n = 2048 a + b_j
+// at or above P - N, their sums in registers (for M = 2P with the first
+// half's outputs A beside them).
+__global__ __launch_bounds__(kG16Threads) void k_gen_corr16(const ReqDesc *__restrict__ R, const BatchHdr *H,
+                                                            const long long *pre, const float2 *tw,
+                                                            const float2 *twg, const float2 *gen)
+{
+    constexpr int P = kGenLds;
+    __shared__ float2 y[P];
+    __shared__ float2 s_tw[kTwElems];
+    stage_twiddles(s_tw, tw, threadIdx.x, kG16Threads);
+    float2 wb[kG16Cols], wm[kG16Cols];
+    g16_bases(wb, wm, twg);
+    const int n_req = H->n_req;
+    const long long total = H->total[kStGenCorr];
+    const long long *pst = pre + (long long)kStGenCorr * (n_req + 1);
+    for (long long it = blockIdx.x; it < total; it += gridDim.x) {
+        const int r = find_req(pst, n_req, it);
+        const ReqDesc &d = R[r];
+        if (d.gen_P != P) continue;
+        const long long local = it - pst[r];
+        const int k = (int)(local / d.n_prn), pi = (int)(local % d.n_prn);
+        const int N = d.N, M = d.gen_M;
+        const float4 *C = (const float4 *)(gen + d.gen_c_off + (long long)pi * M);
+        const float scale = ldexpf(1.f, -24 - 2 * (31 - __clz(M)));
+        GNSS_GLOBAL float *row = gmem(d.grid) + ((long long)pi * d.n_dopp + k) * N;
+        float acc[kG16Cols][8];
+#pragma unroll
+        for (int j = 0; j < kG16Cols; ++j)
+#pragma unroll
+            for (int a = 0; a < 8; ++a) acc[j][a] = 0.f;
+        for (int b = 0; b < d.Nnc; ++b) {
+            const float4 *X = (const float4 *)(gen + d.gen_x_off + ((long long)k * d.Nnc + b) * M);
+            // (the barrier inside: the twiddles are staged, the previous stage's reads of y done)
+            g16_inv_rows(y, s_tw, X, C);
+            __syncthreads();
+            if (M == P) {
+                // lag tau = n - (P - N)
+                g16_inv_stage(y, wb, [&](int j, int a, int bb, float2 o) {
+                    const int n = 2048 * a + bb;
+                    if (n >= P - N) acc[j][a] = fmaf(o.x, o.x, fmaf(o.y, o.y, acc[j][a]));
+                });
+            } else {
+                // lag tau is output P + kk, kk = n - (P - N): A - W_M^-kk B
+                float2 A[kG16Cols][8];
+                g16_inv_stage(y, wb, [&](int j, int a, int, float2 o) { A[j][a] = o; });
+                g16_inv_rows(y, s_tw, X + P / 2, C + P / 2);
+                __syncthreads();
+                g16_inv_stage(y, wb, [&](int j, int a, int bb, float2 o) {
+                    const int n = 2048 * a + bb;
+                    if (n >= P - N) {
+                        // W_M^-n = conj(W_M^b) W_16^-a
+                        const float2 v = c_sub(A[j][a], twiddle16(c_mulc(o, opaque(wm[j])), a, true));
+                        acc[j][a] = fmaf(v.x, v.x, fmaf(v.y, v.y, acc[j][a]));
+                    }
+                });
+            }
+        }
+        const int tid = opaque_tid();
+#pragma unroll
+        for (int j = 0; j < kG16Cols; ++j)
+#pragma unroll
+            for (int a = 0; a < 8; ++a) {
+                const int n = 2048 * a + tid + kG16Threads * j;
+                if (n >= P - N) row[n - (P - N)] = acc[j][a] * scale;
+            }
     }
 }
 
@@ -2655,13 +2977,23 @@ hipError_t launch_batch(const Launch &L, const Tables &T, int2 *d_F, void *d_G, 
         float2 *d_gen = (float2 *)((char *)d_G + L.gen_off);
         auto spectra = [&](auto pc) -> hipError_t {
             constexpr int P = decltype(pc)::value;
-            hipLaunchKernelGGL(k_gen_code<P>, dim3(grid_for(L.total[kStGenC], 65535, false)), dim3(kGenThreads), 0,
-                               s, L.reqs, L.hdr, L.pre, T.codes, T.tw_gen, d_gen);
-            hipError_t e2 = hipGetLastError();
-            if (e2 != hipSuccess) return e2;
-            hipLaunchKernelGGL(k_gen_x<P>, dim3(grid_for(L.total[kStGenX], 65535, false)), dim3(kGenThreads), 0, s,
-                               L.reqs, L.hdr, L.pre, d_lut, T.tw_gen, d_gen);
-            return hipGetLastError();
+            if constexpr (P == kGenLds) {
+                hipLaunchKernelGGL(k_gen_code16, dim3(grid_for(L.total[kStGenC], 65535, false)), dim3(kG16Threads),
+                                   0, s, L.reqs, L.hdr, L.pre, T.codes, T.tw, T.tw_gen, d_gen);
+                hipError_t e2 = hipGetLastError();
+                if (e2 != hipSuccess) return e2;
+                hipLaunchKernelGGL(k_gen_x16, dim3(grid_for(L.total[kStGenX], 65535, false)), dim3(kG16Threads), 0,
+                                   s, L.reqs, L.hdr, L.pre, d_lut, T.tw, T.tw_gen, d_gen);
+                return hipGetLastError();
+            } else {
+                hipLaunchKernelGGL(k_gen_code<P>, dim3(grid_for(L.total[kStGenC], 65535, false)), dim3(kGenThreads),
+                                   0, s, L.reqs, L.hdr, L.pre, T.codes, T.tw_gen, d_gen);
+                hipError_t e2 = hipGetLastError();
+                if (e2 != hipSuccess) return e2;
+                hipLaunchKernelGGL(k_gen_x<P>, dim3(grid_for(L.total[kStGenX], 65535, false)), dim3(kGenThreads), 0,
+                                   s, L.reqs, L.hdr, L.pre, d_lut, T.tw_gen, d_gen);
+                return hipGetLastError();
+            }
         };
         if ((e = gen_lengths<64>(L.gen_pmask, spectra)) != hipSuccess) return e;
     }
@@ -2670,8 +3002,12 @@ hipError_t launch_batch(const Launch &L, const Tables &T, int2 *d_F, void *d_G, 
         const float2 *d_gen = (const float2 *)((char *)d_G + L.gen_off);
         auto corr = [&](auto pc) -> hipError_t {
             constexpr int P = decltype(pc)::value;
-            hipLaunchKernelGGL(k_gen_corr<P>, dim3(grid_for(L.total[kStGenCorr], 65535, false)), dim3(kGenThreads),
-                               0, s, L.reqs, L.hdr, L.pre, T.tw_gen, d_gen);
+            if constexpr (P == kGenLds)
+                hipLaunchKernelGGL(k_gen_corr16, dim3(grid_for(L.total[kStGenCorr], 65535, false)),
+                                   dim3(kG16Threads), 0, s, L.reqs, L.hdr, L.pre, T.tw, T.tw_gen, d_gen);
+            else
+                hipLaunchKernelGGL(k_gen_corr<P>, dim3(grid_for(L.total[kStGenCorr], 65535, false)),
+                                   dim3(kGenThreads), 0, s, L.reqs, L.hdr, L.pre, T.tw_gen, d_gen);
             return hipGetLastError();
         };
         if ((e = gen_lengths<64>(L.gen_pmask, corr)) != hipSuccess) return e;
