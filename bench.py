@@ -305,7 +305,8 @@ def main():
         # a rate that is not a multiple of the chip rate: the zero-padded FP32
         # transforms in every precision
         roofline = corr_roofline("fp32", units * flops_unit, corr_ms, read_traffic("gen_corr", wl), 0)
-        roofline["kernel"] = "k_gen_corr"
+        # N > 4096: the 16384-point (four-step) kernel; else the radix-8 one of its length
+        roofline["kernel"] = "k_gen_corr16" if N > 4096 else "k_gen_corr"
     else:
         kern = CORR_KERNEL[args.precision]
         roofline = corr_roofline(args.precision, units * flops_unit, corr_ms, read_traffic(kern[2:], wl),

@@ -119,10 +119,15 @@ def test_general_rate_same_in_every_precision_and_in_a_mixed_batch():
     """The general-rate kernels are FP32 in every context: FP16 and
     exact-length contexts give the FP32 context's grid bit for bit.  In a
     batch beside chip-rate requests (which take the polyphase kernels) each
-    request's results equal its results alone, bit for bit."""
+    request's results equal its results alone, bit for bit, also beside
+    general-rate requests of another transform length."""
     snaps = []
+    # 5 and 10 MHz take the 16384-point kernels (one and two halves), 2.5 MHz
+    # the 8192-point ones: one batch launches both lengths, each skipping the
+    # other's items
     for i, (fs, fmt, f_if) in enumerate([(5000000, O.CPLX_I8, 0.0), (4092000, O.REAL_I8, 1023000.0),
-                                         (10000000, O.REAL_2BIT_PACKED, 2500000.0), (2046000, O.CPLX_I8, 0.0)]):
+                                         (10000000, O.REAL_2BIT_PACKED, 2500000.0), (2046000, O.CPLX_I8, 0.0),
+                                         (2500000, O.CPLX_I8, 0.0)]):
         pl = [synth.Planted(prn=3 + i, code_phase=100 * i + 7, doppler_hz=500.0, cn0_dbhz=50.0)]
         snaps.append((synth.make_snapshot(40 + i, fmt, fs, f_if, 3.2, pl, O.ca_code),
                       synth.Search([3 + i, 20], 0.0, 1000.0, 500.0, 1, 3)))
@@ -152,7 +157,7 @@ def test_general_rate_same_in_every_precision_and_in_a_mixed_batch():
             assert pb.tobytes() == alone[j][1].tobytes(), j
     for prec in (G.GNSS_FP16, G.GNSS_FP16_PFA):
         with G.Context(0, precision=prec) as ch:
-            for j in (0, 2):  # the general-rate requests
+            for j in (0, 2, 4):  # the general-rate requests
                 grid, pk = _search(ch, *snaps[j])
                 assert np.array_equal(grid, alone[j][0]), (prec, j)
                 assert pk.tobytes() == alone[j][1].tobytes(), (prec, j)
