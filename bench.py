@@ -330,6 +330,20 @@ def main():
                "achieved_GBs": round(staged / (pipe_ms / 1e3) / 1e9, 1), "peak_GBs": PEAK_HBM_GBS,
                "frac": round(staged / (pipe_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
 
+    # end to end: the method's algorithmic work (per (PRN, bin, block) an N-point
+    # inverse transform, the spectrum product, |.|^2 and the sum; per (bin, block) an
+    # N-point forward transform; the wipe-off of every sample in every bin) and its
+    # bytes (the record once, the grid once, the code spectra once) against the
+    # chip's FP32 and HBM peaks: max(bytes / BW, flops / peak) / measured time
+    n_samples = srch.T_coh * srch.N_noncoh * N
+    e2e_flops = (n_prn * nd * srch.N_noncoh * flops_unit + nd * srch.N_noncoh * 5.0 * N * math.log2(N)
+                 + nd * n_samples * (6.0 if snap.fmt == G.GNSS_CPLX_I8 else 2.0))
+    e2e_bytes = snap.samples.nbytes + n_prn * nd * N * 4 + n_prn * N * 8
+    t_min = max(e2e_bytes / (PEAK_HBM_GBS * 1e9), e2e_flops / 157.3e12)
+    end_to_end = {"flops": e2e_flops, "bytes": e2e_bytes,
+                  "bound": "alu" if e2e_flops / 157.3e12 >= e2e_bytes / (PEAK_HBM_GBS * 1e9) else "hbm",
+                  "t_min_ms": round(t_min * 1e3, 4), "frac": round(t_min / (ms_step / 1e3), 4)}
+
     out = {
         "metric": "search cells/s (PRNxDopplerxphasexms) + p50/p99 latency/snapshot",
         "value": value,
@@ -353,6 +367,7 @@ def main():
         "stages_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in stages.items()},
         "roofline": roofline,
         "fft_pipeline_hbm": fft_hbm,
+        "end_to_end": end_to_end,
         "detections": {"planted": sorted(planted), "detected": sorted(detected),
                        "planted_found": sorted(planted & detected)},
         "source_hash": kernel_source_hash(),

@@ -143,7 +143,7 @@ void gnss_ctx_destroy(gnss_ctx *ctx);
  * 2 otherwise), "corr_waves" (waves, i.e. (Doppler, phase) items, per
  * correlation workgroup: GNSS_FP32 tile 1 runs 12, 6 or 4 at three waves per
  * SIMD, tiles 2 and 4 run 8; the FP16 kernels have one width each; 0 =
- * autotuned, by default 12 for tile 1; a width the tile does not have falls
+ * autotuned, by default 4 for tile 1; a width the tile does not have falls
  * back to its default),
  * "persistent" (grid of the correlation kernel, the dominant one: 1 an
  * occupancy-sized grid whose workgroups take items from per-XCD work counters

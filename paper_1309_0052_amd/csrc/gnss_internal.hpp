@@ -17,7 +17,7 @@ constexpr int kMaxN = kCodeLen * kMaxSpc;
 constexpr int kVec = 1024;             // float4 per storage-order spectrum (2048 complex)
 constexpr int kPolyLen = 1024;         // int2 per polyphase component (1023 + 1 zero)
 constexpr int kCorrWaves = 8;          // waves per FP32 correlation workgroup (PRN tiles 2, 4)
-constexpr int kCorrWaves1 = 12;        // ... PRN tile 1 (three waves per SIMD)
+constexpr int kCorrWaves1 = 4;         // ... PRN tile 1 (three 4-wave workgroups per CU: three waves per SIMD)
 constexpr int kCorrWavesH = 4;         // waves per FP16 correlation workgroup
 constexpr int kCorrWavesX = 4;         // waves per exact-length correlation workgroup
 

@@ -418,9 +418,9 @@ std::string rate_signature(const gnss::Plan *plans, int n)
 
 gnss::CorrShape corr_shape_for(gnss_ctx *c, const gnss::Plan *plans, int n)
 {
-    // untuned: FP32 tile 1 with 12 waves (three waves per SIMD; 6% faster than
-    // tile 2 on the weak workload), FP16 tile 2 (PRNs go in pairs), exact-length
-    // tile 2; forced options override tile and waves
+    // untuned: FP32 tile 1 with 4 waves (three workgroups, i.e. three waves per
+    // SIMD; the fastest shape on the weak workload), FP16 tile 2 (PRNs go in
+    // pairs), exact-length tile 2; forced options override tile and waves
     gnss::CorrShape s{c->precision == GNSS_FP32 ? 1 : 2, 0};
     {
         std::lock_guard<std::mutex> lk(c->tuned_mu);

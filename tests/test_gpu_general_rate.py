@@ -94,6 +94,41 @@ def test_general_rate_search_matches_direct_oracle(ctx, case):
     log("  max mixed error %.3e, exemptions %d, refinements checked %d" % (worst, exempt, checked))
 
 
+@pytest.mark.timeout(600)
+def test_weak_workload_at_10mhz_full_size(ctx):
+    """The benchmark's 10 MHz weak-signal workload at full size (N = 10000,
+    M = 32768: the four-step 16384-point kernels with both halves; 32 PRNs x
+    121 bins x 25 blocks of 4 ms) in the launch configuration bench.py times:
+    the FP32 grid against the oracle's FP64 FFT route everywhere, detections
+    and refinements, and sampled cells (every detected peak and random cells)
+    against the direct correlation."""
+    snap, srch = synth.weak_complex_int8(O.ca_code, seed=2, fs=10000000)
+    nd = O.n_doppler(srch.lo, srch.hi, srch.step)
+    N = snap.fs_hz // 1000
+    log("weak workload at 10 MHz: complex int8, 32 PRN x %d bins x %d phases x 25 x 4 ms" % (nd, N))
+    grid, pk = _search(ctx, snap, srch)
+    log("  oracle grid (FP64 FFT route) ...")
+    P = O.grid_fft(snap.samples, snap.fmt, snap.fs_hz, snap.f_if_hz, srch.prns, srch.lo, srch.step,
+                   nd, srch.T_coh, srch.N_noncoh)
+    worst = assert_grid_close(grid, P)
+    ref = O.peaks(P, srch.prns, O.chip_exclusion(snap.fs_hz), 2.5, srch.lo, srch.step)
+    exempt = compare_detections(pk, ref, P)
+    checked = compare_refinement(pk, ref, P, grid, srch.lo, srch.step)
+    assert checked >= len(srch.prns) - exempt
+    log("  max mixed error %.3e, exemptions %d, refinements checked %d" % (worst, exempt, checked))
+    rng = np.random.default_rng(3)
+    cells = [(srch.prns.index(int(r["prn"])), int(r["doppler_bin"]), int(r["code_phase"]))
+             for r in pk if r["detected"]]
+    assert cells  # the strongest planted satellites are found
+    cells += list(zip(rng.integers(0, len(srch.prns), 40), rng.integers(0, nd, 40), rng.integers(0, N, 40)))
+    cells = np.array(cells, np.int64)
+    vals = O.cells_direct(snap.samples, snap.fmt, snap.fs_hz, snap.f_if_hz, srch.prns, srch.lo,
+                          srch.step, nd, srch.T_coh, srch.N_noncoh, cells)
+    got = grid[cells[:, 0], cells[:, 1], cells[:, 2]].astype(np.float64)
+    means = P.mean(axis=(1, 2))[cells[:, 0]]
+    assert np.all(np.abs(got - vals) <= 1e-4 * (vals + means))
+
+
 def test_general_rate_code_doppler_matches_oracle():
     """Code-Doppler compensation at a general rate: the folded block delayed
     by llround(b Tc N f_k / f_L1) samples, as in the oracle."""
