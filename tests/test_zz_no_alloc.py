@@ -95,6 +95,32 @@ def test_noalloc_equals_acquire_device_twice_second_smaller(prec, strong_case):
         assert_grid_close(ref["small"][0], Ps)
 
 
+def test_noalloc_general_rate_equals_acquire_device():
+    """General rates: the zero-padded FP32 transforms keep their block and
+    code spectra in the same workspace.  A 10 MHz request (two 16384-point
+    halves), then a smaller 2.5 MHz one (8192 points): bit for bit what
+    gnss_acquire_device gives."""
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    cases = []
+    for seed, fs, prns, planted in ((81, 10000000, [6, 21, 30], (21, -500.0)), (82, 2500000, [9, 12], (12, 500.0))):
+        pl = [synth.Planted(prn=planted[0], code_phase=1234, doppler_hz=planted[1], cn0_dbhz=50.0)]
+        snap = synth.make_snapshot(seed, synth.CPLX_I8, fs, 0.0, 4.3, pl, O.ca_code)
+        cases.append((snap, synth.Search(prns, -500.0, 500.0, 500.0, 2, 2)))
+    with G.Context(0) as ctx:
+        devs = [Dev(snap, srch) for snap, srch in cases]
+        ref = []
+        for d in devs:
+            ctx.acquire_device(d.req)
+            ref.append(d.result())
+            d.clear()
+        for i, d in enumerate(devs):
+            print("noalloc general rate, request %d (fs %d)" % (i, d.snap.fs_hz), flush=True)
+            ctx.acquire_device_noalloc(d.req)
+            g, pk = d.result()
+            assert np.array_equal(g, ref[i][0]), i
+            _same_peaks(pk, ref[i][1])
+
+
 def test_noalloc_refuses_oversize_request_and_allocates_nothing(strong_case):
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     snap, srch, nd, P = strong_case
