@@ -236,8 +236,8 @@ int gnss_acquire_batch_device(gnss_ctx *ctx, const gnss_request *reqs, int32_t n
 typedef struct gnss_graph gnss_graph;
 int gnss_graph_create(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, gnss_graph **out);
 int gnss_graph_launch(gnss_graph *graph, void *stream);
-/* Waits for the device, then frees the graph and its workspace; NULL is a
- * no-op. */
+/* Waits for the graph's last launch (not for the rest of the device), then
+ * frees the graph and its workspace; NULL is a no-op. */
 void gnss_graph_destroy(gnss_graph *graph);
 
 /* Picks the correlation kernel's launch for batches with the sample rates of

@@ -1108,10 +1108,18 @@ int gnss_graph_create(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, gn
             e = hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0);
             if (e != hipSuccess) rc = set_err(GNSS_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
         }
+        if (!rc) {
+            e = hipEventCreateWithFlags(&gr->done, hipEventDisableTiming);
+            if (e != hipSuccess) {
+                gr->done = nullptr;
+                rc = set_err(GNSS_EDEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+            }
+        }
         if (graph) (void)hipGraphDestroy(graph);
     }
     (void)hipStreamDestroy(cs);
     if (rc) {
+        if (gr->done) (void)hipEventDestroy(gr->done);
         if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
         release_ws(ctx, gr->ws);
         delete gr;
@@ -1127,6 +1135,7 @@ int gnss_graph_launch(gnss_graph *graph, void *stream)
     DeviceGuard g(graph->ctx->device);
     if (g.rc) return g.rc;
     HIP_TRY(hipGraphLaunch(graph->exec, (hipStream_t)stream));
+    HIP_TRY(hipEventRecord(graph->done, (hipStream_t)stream));
     return GNSS_OK;
 }
 
@@ -1134,7 +1143,11 @@ void gnss_graph_destroy(gnss_graph *graph)
 {
     if (!graph) return;
     DeviceGuard g(graph->ctx->device);
-    (void)hipDeviceSynchronize();
+    // the last launch (replays do not overlap), not the rest of the device
+    if (graph->done) {
+        (void)hipEventSynchronize(graph->done);
+        (void)hipEventDestroy(graph->done);
+    }
     if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
     release_ws(graph->ctx, graph->ws);
     delete graph;

@@ -144,6 +144,7 @@ struct gnss_graph {
     gnss_ctx *ctx = nullptr;
     gnss_rt::Workspace ws;
     hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;  // recorded after every launch (replays do not overlap)
     int corr_pt = 2;
     int corr_w = 8;
 };
