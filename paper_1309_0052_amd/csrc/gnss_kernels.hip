@@ -1916,24 +1916,26 @@ __global__ __launch_bounds__(kSynthThreads) void k_fd_synth(const ReqDesc *__res
 // c[j mod N] at [0, 2N), and
 //   R[tau] = sum_n f[n] c[(n - tau) mod N] = IDFT_M(DFT_M(f) conj(DFT_M(cc)))[M - N + tau] / M
 // (no wrap-around because M >= 2N).  FP32 throughout, in every context
-// precision.  A transform of P <= 16384 points runs in one workgroup's LDS
-// (1024 threads, in-place radix-8 passes and one radix-2 or 4 pass); for
-// M = 32768 the even and odd bins are two 16384-point transforms:
+// precision.  Each transform of P = min(M, 16384) points runs in one
+// workgroup's LDS; for M = 32768 the even and odd bins are two 16384-point
+// transforms:
 //   X[2k] = DFT_P(x[j] + x[j + P])[k],  X[2k + 1] = DFT_P((x[j] - x[j + P]) W_M^j)[k],
 // and the inverse's upper half (the only outputs needed, as N <= M/2) is
 //   out[P + k] = A[k] - W_M^-k B[k],  A = IDFT_P(Z even bins), B = IDFT_P(Z odd bins).
-// The forward transforms are decimation in frequency (natural order in,
-// digit-reversed out) and the inverse is their exact adjoint (digit-reversed
-// in, natural out), so spectra are multiplied in the order they are stored.
+// P <= 8192: in-place radix-8 passes and one radix-2 or 4 pass in a
+// 1024-thread workgroup, decimation in frequency forward (natural order in,
+// digit-reversed out) and the exact adjoint inverse (digit-reversed in,
+// natural out), so spectra are multiplied in the order they are stored.
+// P = 16384: four-step 8 x 2048 transforms (below).
 // ===========================================================================
 
-// Radix of the LDS passes.  Radix 8 keeps a butterfly's 8 values and their
-// twiddles within about half the registers of a radix-16 one, so the
-// correlation kernel can also hold its per-lag state at 1024 threads.
+// Radix of the LDS passes (a radix-16 butterfly with its twiddles needs about
+// twice the registers, too many beside the correlation's per-lag sums at
+// 1024 threads).
 constexpr int kGenRad = 8;
-// LDS layout of a transform: element i at i + i/32 (one unused slot per 32),
-// which spreads the strided accesses of the small-span passes over the banks
-constexpr int kGenLdsPad = kGenLds + kGenLds / 32;
+// LDS layout of a transform: element i at i + i/32 (one unused slot per 32,
+// P + P/32 slots), which spreads the strided accesses of the small-span
+// passes over the banks
 __device__ __forceinline__ int gx(int i) { return i + (i >> 5); }
 
 // The first octant of the P-point twiddles, s_tw[i] = W_P^i for i < P/8,
@@ -2386,10 +2388,7 @@ __device__ __forceinline__ void g16_fwd_stage(float2 *y, const float2 (&wb)[kG16
 #pragma unroll
         for (int a = 0; a < 8; ++a) v[a] = x(j, a, b);
         dft8<false, false, false, 0>(v);
-        {
-            // opaque copy: the powers are formed here, not hoisted and held
-            gen_powers(w, opaque(wb[j]));
-        }
+        gen_powers(w, opaque(wb[j]));  // formed here, not hoisted and held
 #pragma unroll
         for (int r = 1; r < 8; ++r) v[r] = c_mul(v[r], w[r]);
 #pragma unroll
@@ -2409,7 +2408,6 @@ __device__ __forceinline__ void g16_bases(float2 (&wb)[kG16Cols], float2 (&wm)[k
         wm[j] = twg[threadIdx.x + kG16Threads * j];
     }
 }
-
 
 // Wave k1 transforms row k1 of y (natural order) and stores the storage-order
 // result at dst[k1][1024 float4].  The row is the wave's transpose buffer.
@@ -2467,10 +2465,7 @@ __device__ __forceinline__ void g16_inv_stage(const float2 *y, const float2 (&wb
         float2 v[8], w[8];
 #pragma unroll
         for (int k1 = 0; k1 < 8; ++k1) v[k1] = y[k1 * 2048 + b];
-        {
-            // opaque copy: the powers are formed here, not hoisted and held
-            gen_powers(w, opaque(wb[j]));
-        }
+        gen_powers(w, opaque(wb[j]));  // formed here, not hoisted and held
 #pragma unroll
         for (int r = 1; r < 8; ++r) v[r] = c_mulc(v[r], w[r]);
         dft8<true, false, false, 0>(v);
@@ -2515,9 +2510,10 @@ __global__ __launch_bounds__(kG16Threads) void k_gen_code16(const ReqDesc *__res
                 const int n = 2048 * a + b;
                 if (M == P) return make_float2(cc(n), 0.f);
                 if (h == 0) return make_float2(cc(n) + cc(n + P), 0.f);
+                // (cc[n] - cc[n + P]) W_M^n, M = 32768: W_M^b W_16^a
                 const float c = cc(n) - cc(n + P);
-                const float2 w = twg[n];  // W_M^n, M = 32768
-                return make_float2(c * w.x, c * w.y);
+                const float2 w = opaque(wm[j]);
+                return twiddle16(make_float2(c * w.x, c * w.y), a, false);
             });
             __syncthreads();
             g16_fwd_rows(y, s_tw, (float4 *)(dst + (long long)h * P));
