@@ -837,7 +837,7 @@ __device__ __forceinline__ void stage_twiddles_h(hc2 *s_tw, const hc2 *tw, int t
 // the result, and the FP16 roundings of those values would dominate it.)
 // Output: Gh[vec] in the packed storage order, the vector's exponent E[vec]
 // and its scaled sum Dc[vec] = S * 2^-e.
-// three waves per SIMD (167 VGPRs with a 20-byte spill): 15% faster than two
+// three waves per SIMD (168 VGPRs with a 44-byte spill): faster than two
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_fft_poly_h(const int2 *F, const hc2 *tw, uint4 *Gh, int *E,
                                                     float2 *Dc, const BatchHdr *H)
 {
@@ -1570,7 +1570,7 @@ __global__ __launch_bounds__(64 * kCorrWavesX) void k_corr_x(const ReqDesc *__re
 // ===========================================================================
 // Frequency-domain Doppler (exact-length contexts, option doppler_fd).  The
 // carrier is removed once per block at the base frequency f_if + lo by an
-// exact exponential (FP64 phase, FP32 sin/cos; phase zero at the block start,
+// exact exponential (64-bit integer phase, FP32 sin/cos; phase zero at the block start,
 // which leaves |R|^2 unchanged), and one zero-padded DFT of length
 // M = P T_coh N = A * 1023 serves every Doppler bin: bin k's folded block has
 // the N-point spectrum F^[q] = Y_M[P T_coh q + k kappa] (folding T_coh
