@@ -198,6 +198,38 @@ def test_general_rate_same_in_every_precision_and_in_a_mixed_batch():
                 assert pk.tobytes() == alone[j][1].tobytes(), (prec, j)
 
 
+def test_general_rate_served_equals_alone():
+    """Served (continuous batching) general-rate requests, submitted beside a
+    chip-rate one: results bit for bit those of the requests alone."""
+    import time
+    specs = [(91, 5000000, O.CPLX_I8, 0.0), (92, 4092000, O.REAL_I8, 1023000.0),
+             (93, 10000000, O.CPLX_I8, 0.0), (94, 2500000, O.REAL_2BIT_PACKED, 625000.0)]
+    items = []
+    for seed, fs, fmt, f_if in specs:
+        pl = [synth.Planted(prn=11, code_phase=777, doppler_hz=500.0, cn0_dbhz=50.0)]
+        snap = synth.make_snapshot(seed, fmt, fs, f_if, 4.4, pl, O.ca_code)
+        items.append((snap, synth.Search([11, 25], 0.0, 1000.0, 500.0, 2, 2)))
+    with G.Context(0) as c:
+        alone = [_search(c, snap, srch) for snap, srch in items]
+    with G.Context(0) as sctx:
+        subs = []
+        for i, (snap, srch) in enumerate(items):
+            nd = O.n_doppler(srch.lo, srch.hi, srch.step)
+            N = snap.fs_hz // 1000
+            grid = np.zeros((len(srch.prns), nd, N), np.float32)
+            pk = np.zeros(len(srch.prns), G.PEAK_DTYPE)
+            x = np.ascontiguousarray(snap.samples)
+            req = G.make_request(x.ctypes.data, snap.fmt, snap.n, snap.fs_hz, snap.f_if_hz, srch.prns, srch.lo,
+                                 srch.hi, srch.step, srch.T_coh, srch.N_noncoh, grid.ctypes.data, pk.ctypes.data)
+            subs.append((sctx.submit(req), grid, pk, x))
+            time.sleep(0.001)
+        for i, (t, grid, pk, x) in enumerate(subs):
+            info = sctx.wait(t, 60.0)
+            assert info.status == 0, i
+            assert np.array_equal(grid, alone[i][0]), i
+            assert pk.tobytes() == alone[i][1].tobytes(), i
+
+
 def test_general_rate_unsupported_options():
     snap = synth.make_snapshot(9, O.CPLX_I8, 5000000, 0.0, 2.2, [], O.ca_code)
     srch = synth.Search([1], 0.0, 0.0, 1.0, 1, 2)
