@@ -853,8 +853,9 @@ def precision_measure(G, torch, code_fn, steps: int, warmup: int) -> dict:
 
 def run_precision(args, G, torch, ctx, code_fn):
     """The strong-signal snapshot on the three precisions of the same GPU."""
+    codes = {p: code_fn(p) for p in range(1, 38)}  # the GPU's codes, kept past this context
     ctx.close()
-    m = precision_measure(G, torch, code_fn, args.steps, args.warmup)
+    m = precision_measure(G, torch, codes.__getitem__, args.steps, args.warmup)
     head = args.precision if args.precision != "fp32" else "fp16"
     out = {
         "metric": "search cells/s (PRNxDopplerxphasexms) + p50/p99 latency/snapshot",
