@@ -2521,6 +2521,50 @@ __global__ __launch_bounds__(kG16Threads) void k_gen_code16(const ReqDesc *__res
     }
 }
 
+// The wipe-off and fold of this thread's 32 samples n = 2048 a + tid + 512 j
+// of block b (zero at n >= N), delayed circularly by shift: the arithmetic
+// of wipe_fold_one with the milliseconds outermost, so that the 32 samples'
+// loads of one millisecond are in flight together.
+template <int FMT>
+__device__ __forceinline__ void g16_fold(const ReqDesc &d, int b, uint32_t D, int shift, const uint32_t *s_lut,
+                                         int tid, float2 (&f)[kG16Cols][8])
+{
+    const int N = d.N, Tc = d.Tc;
+    int yr[kG16Cols][8], yi[kG16Cols][8], m[kG16Cols][8];
+#pragma unroll
+    for (int j = 0; j < kG16Cols; ++j)
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const int n = 2048 * a + tid + kG16Threads * j;
+            int mm = n - shift;
+            if (mm < 0) mm += N;
+            m[j][a] = n < N ? mm : -1;
+            yr[j][a] = 0;
+            yi[j][a] = 0;
+        }
+    for (int c = 0; c < Tc; ++c) {
+        const long long base = (long long)(b * Tc + c) * N;
+#pragma unroll
+        for (int j = 0; j < kG16Cols; ++j)
+#pragma unroll
+            for (int a = 0; a < 8; ++a) {
+                if (m[j][a] < 0) continue;
+                const long long ng = base + m[j][a];
+                int xr, xi;
+                load_sample(d.samples, FMT, ng, xr, xi);
+                const uint32_t ph = (uint32_t)(unsigned long long)ng * D;
+                const uint32_t e = s_lut[ph >> 22];
+                const int cs = (int)(int16_t)(e & 0xFFFFu), sn = (int)(int16_t)(e >> 16);
+                yr[j][a] += xr * cs + xi * sn;
+                yi[j][a] += xi * cs - xr * sn;
+            }
+    }
+#pragma unroll
+    for (int j = 0; j < kG16Cols; ++j)
+#pragma unroll
+        for (int a = 0; a < 8; ++a) f[j][a] = make_float2((float)yr[j][a], (float)yi[j][a]);
+}
+
 // Block spectra, P = 16384 (see k_gen_x).
 __global__ __launch_bounds__(kG16Threads) void k_gen_x16(const ReqDesc *__restrict__ R, const BatchHdr *H,
                                                          const long long *pre, const uint32_t *lut,
@@ -2550,19 +2594,12 @@ __global__ __launch_bounds__(kG16Threads) void k_gen_x16(const ReqDesc *__restri
         // the folded block at n = 2048 a + tid + 512 j (zero at n >= N)
         float2 f[kG16Cols][8];
         const int tid = opaque_tid();
-#pragma unroll
-        for (int j = 0; j < kG16Cols; ++j)
-#pragma unroll
-            for (int a = 0; a < 8; ++a) {
-                const int n = 2048 * a + tid + kG16Threads * j;
-                f[j][a] = make_float2(0.f, 0.f);
-                if (n < N) {
-                    int m = n - shift;
-                    if (m < 0) m += N;
-                    const int2 v = wipe_fold_one(d.samples, d.fmt, N, d.Tc, s_lut, D, b, m);
-                    f[j][a] = make_float2((float)v.x, (float)v.y);
-                }
-            }
+        if (d.fmt == GNSS_CPLX_I8)
+            g16_fold<GNSS_CPLX_I8>(d, b, D, shift, s_lut, tid, f);
+        else if (d.fmt == GNSS_REAL_I8)
+            g16_fold<GNSS_REAL_I8>(d, b, D, shift, s_lut, tid, f);
+        else
+            g16_fold<GNSS_REAL_2BIT_PACKED>(d, b, D, shift, s_lut, tid, f);
         float2 *dst = gen + d.gen_x_off + local * M;
         for (int h = 0; h < M / P; ++h) {
             if (h) __syncthreads();  // the previous half's rows are read
