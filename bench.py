@@ -320,6 +320,8 @@ def main():
         M = 64
         while M < 2 * N:
             M *= 2
+        if N >= 64 and N & (N - 1) == 0:
+            M = N  # a power of two: no padding
         staged = nd * srch.N_noncoh * M * 8 * 2 + n_prn * nd * N * 4
     else:
         n_vec = nd * srch.N_noncoh * (N // 1023)

@@ -46,15 +46,18 @@ struct Plan {
 };
 
 // General rates: N <= kGenMaxN samples per ms, transforms of length
-// M = 2^ceil(log2(2N)) <= 2 kGenLds done as one (M <= kGenLds) or two
-// (M = 2 kGenLds, even and odd bins) transforms of at most kGenLds points in
-// a workgroup's LDS.
+// M = 2^ceil(log2(2N)) <= 2 kGenLds (M = N when N is a power of two) done as
+// one (M <= kGenLds) or two (M = 2 kGenLds, even and odd bins) transforms of
+// at most kGenLds points in a workgroup's LDS.
 constexpr int kGenMaxN = 16384;
 constexpr int kGenLds = 16384;
 constexpr int kGenTwLen = 2 * kGenLds;  // twiddle table W_32768^j, j < 32768
 constexpr int kGenThreads = 1024;
 inline int gen_transform_len(int N)
 {
+    // N a power of two (>= 64): the length-N circular correlation is the
+    // N-point one, no padding needed
+    if (N >= 64 && (N & (N - 1)) == 0) return N;
     int M = 64;
     while (M < 2 * N) M *= 2;
     return M;

@@ -1915,7 +1915,9 @@ __global__ __launch_bounds__(kSynthThreads) void k_fd_synth(const ReqDesc *__res
 // 2N): the block f at [0, N), the replica over two code periods cc[j] =
 // c[j mod N] at [0, 2N), and
 //   R[tau] = sum_n f[n] c[(n - tau) mod N] = IDFT_M(DFT_M(f) conj(DFT_M(cc)))[M - N + tau] / M
-// (no wrap-around because M >= 2N).  FP32 throughout, in every context
+// (no wrap-around because M >= 2N).  When N is a power of two, M = N: the
+// same formula is then the N-point circular correlation itself (cc is one
+// period on [0, M)).  FP32 throughout, in every context
 // precision.  Each transform of P = min(M, 16384) points runs in one
 // workgroup's LDS; for M = 32768 the even and odd bins are two 16384-point
 // transforms:

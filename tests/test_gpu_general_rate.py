@@ -58,10 +58,13 @@ CASES = [
     ("5M_real", O.REAL_I8, 5000000, 1250000.0, 1, 2, [3, 13], [(3, -250.0)], -750.0, 250.0, 500.0),
     ("2M5_cplx", O.CPLX_I8, 2500000, 0.0, 3, 2, [20, 31], [(31, 400.0)], -400.0, 400.0, 400.0),
     # M = 2P: N > 8192 takes the even/odd split of the 32768-point transforms
-    ("16M384_cplx", O.CPLX_I8, 16384000, 0.0, 1, 2, [7, 24], [(24, 0.0)], -500.0, 500.0, 500.0),
     ("8M193_real", O.REAL_I8, 8193000, 2048250.0, 1, 2, [14], [(14, -500.0)], -500.0, 0.0, 500.0),
-    # M = P = 16384 at the largest single transform; a tiny N
+    ("12M_cplx", O.CPLX_I8, 12000000, 0.0, 1, 2, [7, 24], [(24, 0.0)], -500.0, 500.0, 500.0),
+    # N a power of two: M = N, no padding (16384, the largest; 8192; 1024)
+    ("16M384_cplx", O.CPLX_I8, 16384000, 0.0, 1, 2, [7, 24], [(24, 0.0)], -500.0, 500.0, 500.0),
     ("8M192_cplx", O.CPLX_I8, 8192000, 0.0, 1, 2, [2, 29], [(29, 500.0)], 0.0, 500.0, 500.0),
+    ("1M024_packed", O.REAL_2BIT_PACKED, 1024000, 256000.0, 2, 2, [5, 30], [(30, -500.0)], -500.0, 0.0, 500.0),
+    # a tiny N
     ("100k_cplx", O.CPLX_I8, 100000, 0.0, 4, 3, [1, 2], [(2, 0.0)], -250.0, 250.0, 250.0),
 ]
 
@@ -79,6 +82,8 @@ def test_general_rate_search_matches_direct_oracle(ctx, case):
     M = 64
     while M < 2 * N:
         M *= 2
+    if N >= 64 and N & (N - 1) == 0:
+        M = N  # a power of two: the N-point correlation, no padding
     log("general rate %s: fs=%d N=%d M=%d fmt=%d bins=%d Tc=%d Nnc=%d" % (name, fs, N, M, fmt, nd, Tc, Nnc))
     grid, pk = _search(ctx, snap, srch)
     P = O.grid_direct(snap.samples, fmt, fs, f_if, prns, lo, step, nd, Tc, Nnc)
