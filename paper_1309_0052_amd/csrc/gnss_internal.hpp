@@ -20,6 +20,14 @@ constexpr int kCorrWaves = 8;          // waves per FP32 correlation workgroup (
 constexpr int kCorrWaves1 = 4;         // ... PRN tile 1 (three 4-wave workgroups per CU: three waves per SIMD)
 constexpr int kCorrWavesH = 4;         // waves per FP16 correlation workgroup
 constexpr int kCorrWavesX = 4;         // waves per exact-length correlation workgroup
+// FP32 non-coherent sums are cascaded: each group of kSumGroup blocks is
+// summed in registers, then added to the sum so far kept in the grid.  A
+// sequential FP32 sum of Nnc positive terms has relative error up to
+// (Nnc - 1) 2^-24, and a biased one in practice once the sum dwarfs the
+// terms (terms below half its ulp are dropped); in groups the bound is
+// (kSumGroup + Nnc / kSumGroup) 2^-24, and requests of at most kSumGroup
+// blocks take one group, exactly as a plain sum.
+constexpr int kSumGroup = 256;
 
 struct PrnList {
     int32_t v[kMaxList];

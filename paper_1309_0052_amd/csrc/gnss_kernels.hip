@@ -556,9 +556,11 @@ __global__ __launch_bounds__(256) void k_fft_poly(const int2 *F, const float2 *t
 // PRN: both the per-wave writes and the per-row reads are free of bank
 // conflicts) and written as contiguous runs of consecutive tau.
 // write_rows writes one PRN's staged sums (column w = wave w's (Doppler,
-// phase) item; consecutive items of a bin are consecutive lags).
+// phase) item; consecutive items of a bin are consecutive lags), or adds
+// them to the grid (add): the element-to-thread map depends only on the
+// request, chunk and thread, so each thread reads back its own earlier store.
 template <int W>
-__device__ __forceinline__ void write_rows(const float *st, const ReqDesc &d, int pi, int chunk, int tid)
+__device__ __forceinline__ void write_rows(const float *st, const ReqDesc &d, int pi, int chunk, int tid, bool add = false)
 {
     constexpr int kPad = W + 1;
     const int spc = d.spc;
@@ -572,7 +574,8 @@ __device__ __forceinline__ void write_rows(const float *st, const ReqDesc &d, in
         GNSS_GLOBAL float *row = gmem(d.grid) + ((long long)pi * d.n_dopp + ka) * d.N + sa;
         for (int idx = tid; idx < cnt; idx += 64 * W) {
             const int q = idx / ns, j = idx - q * ns;
-            row[(long long)spc * q + j] = st[q * kPad + wa + j];
+            GNSS_GLOBAL float *o = row + (long long)spc * q + j;
+            *o = add ? *o + st[q * kPad + wa + j] : st[q * kPad + wa + j];
         }
         wa += ns;
     }
@@ -580,10 +583,12 @@ __device__ __forceinline__ void write_rows(const float *st, const ReqDesc &d, in
 
 // Stages and writes a tile's sums, P = |IFFT|^2 * scale (2^-22 for the
 // unnormalised 2048-point IFFT and 2^-24 for the LUT scale, times the FP16
-// path's code-spectrum scaling).
+// path's code-spectrum scaling); add: adds them to the grid's sums instead
+// (every wave of the workgroup passes the same flag).
 template <int PT, int W>
 __device__ __forceinline__ void store_tile(const float (&acc)[PT][16], float *s_stage, const ReqDesc &d,
-                                           int ptile, int chunk, int w, int l, int tid, float scale)
+                                           int ptile, int chunk, int w, int l, int tid, float scale,
+                                           bool add = false)
 {
     constexpr int kPad = W + 1;
     __syncthreads();
@@ -600,7 +605,39 @@ __device__ __forceinline__ void store_tile(const float (&acc)[PT][16], float *s_
     for (int p = 0; p < PT; ++p) {
         const int pi = ptile * PT + p;
         if (pi >= d.n_prn) break;
-        write_rows<W>(s_stage + p * 1024 * kPad, d, pi, chunk, tid);
+        write_rows<W>(s_stage + p * 1024 * kPad, d, pi, chunk, tid, add);
+    }
+}
+
+// Cascaded non-coherent sums: a wave adds its lanes' sums of the group of
+// blocks just done to the grid (add) or stores them there (the first group),
+// then clears them; each lane reads back only its own stores, and the final
+// write (store_tile with add, another thread per element) comes after its
+// workgroup barriers.  Lane l holds the lags q = l + 64 u + 256 k2b of the
+// item (bin k, phase s): grid column s + spc q.
+template <int PT>
+__device__ __forceinline__ void add_group(float (&acc)[PT][16], const ReqDesc &d, int ptile, int k, int s, int l,
+                                          float scale, bool add)
+{
+#pragma unroll
+    for (int p = 0; p < PT; ++p) {
+        const int pi = ptile * PT + p;
+        if (pi < d.n_prn) {
+            GNSS_GLOBAL float *row = gmem(d.grid) + ((long long)pi * d.n_dopp + k) * d.N + s;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int k2b = 0; k2b < 4; ++k2b) {
+                    const int q = l + 64 * u + 256 * k2b;
+                    if (q < kCodeLen) {
+                        GNSS_GLOBAL float *o = row + (long long)d.spc * q;
+                        const float v = acc[p][4 * u + k2b] * scale;
+                        *o = add ? *o + v : v;
+                    }
+                }
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[p][i] = 0.f;
     }
 }
 
@@ -608,7 +645,9 @@ __device__ __forceinline__ void store_tile(const float (&acc)[PT][16], float *s_
 // items); one wave per (Doppler, phase) item, looping over the blocks and the
 // tile's PT PRNs with the sums in registers.
 // W waves per workgroup, WPE the waves per SIMD the registers are budgeted for
-// (PRN tile 1 at three waves per SIMD: 164 VGPRs; tiles 2 and 4 at two).
+// (PRN tile 1 at three waves per SIMD: 164 VGPRs; tiles 2 and 4 at two;
+// tile 4, at the 256-register limit, keeps 12 bytes of its set-up in
+// scratch, stored once per item and reloaded for the final write).
 template <int PT, int W, int WPE>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE))) void k_corr(const ReqDesc *__restrict__ R, BatchHdr *H,
                                                           const long long *pre, const float4 *G,
@@ -631,7 +670,9 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE))) v
     float *s_stage = (float *)smem;  // reused after the transforms
 
     const int tid = threadIdx.x;
-    const int w = tid >> 6, l = tid & 63;
+    // the wave index as a wave-uniform (scalar) value: the item's bin and
+    // phase derived from it stay out of the vector registers
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
     const int n_req = H->n_req;
     const long long total = H->total[kStCorr];
     const long long *pst = pre + (long long)kStCorr * (n_req + 1);
@@ -643,6 +684,11 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE))) v
         const ReqDesc &d = R[r];
         const long long local = it - pst[r];
         const int ptile = (int)(local % d.n_ptiles), chunk = (int)(local / d.n_ptiles);
+        const int item = chunk * W + w;
+        const bool active = item < d.n_items;
+        const int spc = d.spc;
+        const int k = item / spc, s = item - k * spc;
+
         // code spectra of the tile's PRNs and the twiddles (in a persistent
         // launch this overwrites the staging area of the previous item's
         // write: the barrier inside next_item separates them)
@@ -655,11 +701,6 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE))) v
         stage_twiddles(s_tw, tw, tid, 64 * W);
         __syncthreads();
 
-        const int item = chunk * W + w;
-        const bool active = item < d.n_items;
-        const int spc = d.spc;
-        const int k = item / spc, s = item - k * spc;
-
         float acc[PT][16];
 #pragma unroll
         for (int p = 0; p < PT; ++p)
@@ -667,42 +708,47 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE))) v
             for (int i = 0; i < 16; ++i) acc[p][i] = 0.f;
 
         if (active) {
-            const float4 *gk = G + (d.vec_off + (long long)k * d.Nnc * spc + s) * kVec;
             float2 *xb = s_xb + w * kXbufElemsQ;
-            for (int b = 0; b < d.Nnc; ++b) {
-                const float4 *gp = gk + (long long)b * spc * kVec;
-                // PRN slots past n_prn hold the all-zero spectrum of row 0; they are
-                // computed (no branch in the loop) but never written.
+            // groups of kSumGroup blocks (one for most requests)
+            for (int b0 = 0; b0 < d.Nnc; b0 += kSumGroup) {
+                if (b0) add_group<PT>(acc, d, ptile, k, s, l, 0x1p-46f, b0 > kSumGroup);
+                const float4 *gk = G + (d.vec_off + ((long long)k * d.Nnc + b0) * spc + s) * kVec;
+                const int nb = min(d.Nnc - b0, kSumGroup);
+                for (int b = 0; b < nb; ++b) {
+                    const float4 *gp = gk + (long long)b * spc * kVec;
+                    // PRN slots past n_prn hold the all-zero spectrum of row 0; they are
+                    // computed (no branch in the loop) but never written.
 #pragma unroll
-                for (int p = 0; p < PT; ++p) {
-                    // the block spectrum is re-read for every PRN of the tile (L1/L2
-                    // hits after the first) rather than pinned in registers
-                    float2 z[32];
-                    const float4 *gq = gp;
-                    asm volatile("" : "+v"(gq));
-                    phase_barrier();
+                    for (int p = 0; p < PT; ++p) {
+                        // the block spectrum is re-read for every PRN of the tile (L1/L2
+                        // hits after the first) rather than pinned in registers
+                        float2 z[32];
+                        const float4 *gq = gp;
+                        asm volatile("" : "+v"(gq));
+                        phase_barrier();
 #pragma unroll
-                    for (int jj = 0; jj < 16; ++jj) {
-                        float4 t = gq[jj * 64 + l];
-                        float4 c = s_cc[p * kVec + jj * 64 + l];
-                        z[2 * jj] = c_mul(make_float2(t.x, t.y), make_float2(c.x, c.y));
-                        z[2 * jj + 1] = c_mul(make_float2(t.z, t.w), make_float2(c.z, c.w));
-                    }
-                    phase_barrier();
-                    ifft2048<true, true>(z, xb, s_tw, s_tw + kT1Elems, l);
-                    phase_barrier();
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-#pragma unroll
-                        for (int k2b = 0; k2b < 4; ++k2b) {
-                            float2 rv = z[8 * u + k2b];
-                            acc[p][4 * u + k2b] = fmaf(rv.x, rv.x, fmaf(rv.y, rv.y, acc[p][4 * u + k2b]));
+                        for (int jj = 0; jj < 16; ++jj) {
+                            float4 t = gq[jj * 64 + l];
+                            float4 c = s_cc[p * kVec + jj * 64 + l];
+                            z[2 * jj] = c_mul(make_float2(t.x, t.y), make_float2(c.x, c.y));
+                            z[2 * jj + 1] = c_mul(make_float2(t.z, t.w), make_float2(c.z, c.w));
                         }
+                        phase_barrier();
+                        ifft2048<true, true>(z, xb, s_tw, s_tw + kT1Elems, l);
+                        phase_barrier();
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+#pragma unroll
+                            for (int k2b = 0; k2b < 4; ++k2b) {
+                                float2 rv = z[8 * u + k2b];
+                                acc[p][4 * u + k2b] = fmaf(rv.x, rv.x, fmaf(rv.y, rv.y, acc[p][4 * u + k2b]));
+                            }
+                    }
                 }
             }
         }
 
-        store_tile<PT, W>(acc, s_stage, d, ptile, chunk, w, l, tid, 0x1p-46f);
+        store_tile<PT, W>(acc, s_stage, d, ptile, chunk, w, l, tid, 0x1p-46f, d.Nnc > kSumGroup);
     }
 }
 
@@ -2209,23 +2255,23 @@ __global__ __launch_bounds__(kGenThreads) void k_gen_x(const ReqDesc *__restrict
     }
 }
 
-// One correlation item of length P (see k_gen_corr).
+// One correlation item of length P = M (see k_gen_corr).
 template <int P>
 __device__ __forceinline__ void gen_corr_item(const ReqDesc &d, int k, int pi, const float2 *tw, const float2 *gen,
                                               float2 *x, float2 *s_tw)
 {
+    static_assert(P < kGenLds, "the 16384-point transforms have kernels of their own");
     constexpr int kPer = kGenMaxN / kGenThreads;
     constexpr int kFill = 8;  // product values loaded per thread before they are stored
-    const int N = d.N, M = d.gen_M;
-    const float2 *C = gen + d.gen_c_off + (long long)pi * M;
-    // 2^-24 (LUT scale) / M^2 (two unnormalised transforms), an exact power of two
-    const float scale = ldexpf(1.f, -24 - 2 * (31 - __clz(M)));
+    const int N = d.N;
+    const float2 *C = gen + d.gen_c_off + (long long)pi * P;
+    // 2^-24 (LUT scale) / P^2 (two unnormalised transforms), an exact power of two
+    const float scale = ldexpf(1.f, -24 - 2 * (31 - __clz(P)));
     GNSS_GLOBAL float *row = gmem(d.grid) + ((long long)pi * d.n_dopp + k) * N;
-    // fill x with the product of the half-h spectra of block b; the first
+    // fill x with the product of block b's spectrum and the code's; the first
     // loads are issued before the barrier that frees x
-    auto product = [&](int b, int h, bool first) {
-        const float2 *X = gen + d.gen_x_off + ((long long)k * d.Nnc + b) * M + (long long)h * P;
-        const float2 *Ch = C + (long long)h * P;
+    auto product = [&](int b, bool first) {
+        const float2 *X = gen + d.gen_x_off + ((long long)k * d.Nnc + b) * P;
         const int tid = opaque_tid();
         for (int j0 = 0; j0 < P; j0 += kFill * kGenThreads) {
             float2 xv[kFill], cv[kFill];
@@ -2234,7 +2280,7 @@ __device__ __forceinline__ void gen_corr_item(const ReqDesc &d, int k, int pi, c
                 const int j = j0 + u * kGenThreads + tid;
                 if (j < P) {
                     xv[u] = X[j];
-                    cv[u] = Ch[j];
+                    cv[u] = C[j];
                 }
             }
             if (j0 == 0) {
@@ -2249,13 +2295,15 @@ __device__ __forceinline__ void gen_corr_item(const ReqDesc &d, int k, int pi, c
         }
         __syncthreads();
     };
-    if (M == P) {
-        // lag tau is output M - N + tau
+    // lag tau is output P - N + tau; the sums in groups of kSumGroup blocks,
+    // each group's added to the row by the thread that holds it
+    for (int b0 = 0; b0 < d.Nnc; b0 += kSumGroup) {
         float acc[kPer];
 #pragma unroll
         for (int i = 0; i < kPer; ++i) acc[i] = 0.f;
-        for (int b = 0; b < d.Nnc; ++b) {
-            product(b, 0, b == 0);
+        const int b1 = min(d.Nnc, b0 + kSumGroup);
+        for (int b = b0; b < b1; ++b) {
+            product(b, b == 0);
             gen_inverse<P>(x, s_tw);
             const int tid = opaque_tid();
 #pragma unroll
@@ -2271,50 +2319,16 @@ __device__ __forceinline__ void gen_corr_item(const ReqDesc &d, int k, int pi, c
 #pragma unroll
         for (int i = 0; i < kPer; ++i) {
             const int tau = tid + kGenThreads * i;
-            if (tau < N) row[tau] = acc[i] * scale;
-        }
-    } else if constexpr (P == kGenLds) {
-        // M = 2P: lag tau is output P + kk, kk = P - N + tau
-        for (int b = 0; b < d.Nnc; ++b) {
-            float2 a[kPer];
-            product(b, 0, b == 0);
-            gen_inverse<P>(x, s_tw);
-            // a[] written at every i, so that it is not carried from one
-            // block to the next
-            int tid = opaque_tid();
-#pragma unroll
-            for (int i = 0; i < kPer; ++i) {
-                const int tau = tid + kGenThreads * i;
-                a[i] = tau < N ? x[gx(P - N + tau)] : make_float2(0.f, 0.f);
-            }
-            product(b, 1, false);
-            gen_inverse<P>(x, s_tw);
-            tid = opaque_tid();  // not the first loop's: its lag indices are not kept
-            const bool last = b == d.Nnc - 1;
-#pragma unroll
-            for (int i = 0; i < kPer; ++i) {
-                const int tau = tid + kGenThreads * i;
-                if (tau < N) {
-                    const int kk = P - N + tau;
-                    // A - W_M^-kk B
-                    const float2 v = c_sub(a[i], c_mulc(x[gx(kk)], tw[kk]));
-                    float acc = fmaf(v.x, v.x, fmaf(v.y, v.y, b ? row[tau] : 0.f));
-                    row[tau] = last ? acc * scale : acc;
-                }
-            }
+            if (tau < N) row[tau] = b0 ? row[tau] + acc[i] * scale : acc[i] * scale;
         }
     }
 }
 
-// Correlation of a general-rate request: item = (request, Doppler bin, PRN),
-// Doppler-major so that the workgroups running together share the block
-// spectra; over the blocks, Z = X conj(CC), the inverse transform and |.|^2
-// of the lags' outputs, summed in block order; the grid gets
-// sum |out|^2 2^-24 / M^2.  For M = P the sums stay in registers; for M = 2P
-// each lag needs the two half transforms' outputs together (A - W_M^-k B),
-// so A is held in registers and the running sum is kept in the grid row
-// itself (read and written by the same thread, scaled when the last block
-// is added).
+// Correlation of a general-rate request with M = P <= 8192: item =
+// (request, Doppler bin, PRN), Doppler-major so that the workgroups running
+// together share the block spectra; over the blocks, Z = X conj(CC), the
+// inverse transform and |.|^2 of the lags' outputs, summed in block order
+// in registers; the grid gets sum |out|^2 2^-24 / M^2.
 template <int P>
 __global__ __launch_bounds__(kGenThreads) void k_gen_corr(const ReqDesc *__restrict__ R, const BatchHdr *H,
                                                           const long long *pre, const float2 *tw,
@@ -2619,8 +2633,8 @@ __global__ __launch_bounds__(kG16Threads) void k_gen_x16(const ReqDesc *__restri
 
 // Correlation, P = 16384 (see k_gen_corr): item = (request, Doppler bin,
 // PRN), Doppler-major; this thread's lags are the outputs n = 2048 a + b_j
-// at or above P - N, their sums in registers (for M = 2P with the first
-// half's outputs A beside them).
+// at or above P - N, their sums in registers in groups of kSumGroup blocks
+// (for M = 2P with the first half's outputs A beside them).
 __global__ __launch_bounds__(kG16Threads) void k_gen_corr16(const ReqDesc *__restrict__ R, const BatchHdr *H,
                                                             const long long *pre, const float2 *tw,
                                                             const float2 *twg, const float2 *gen)
@@ -2644,46 +2658,54 @@ __global__ __launch_bounds__(kG16Threads) void k_gen_corr16(const ReqDesc *__res
         const float4 *C = (const float4 *)(gen + d.gen_c_off + (long long)pi * M);
         const float scale = ldexpf(1.f, -24 - 2 * (31 - __clz(M)));
         GNSS_GLOBAL float *row = gmem(d.grid) + ((long long)pi * d.n_dopp + k) * N;
-        float acc[kG16Cols][8];
+        // the sums in groups of kSumGroup blocks, each group's added to the
+        // row by the thread that holds it
+        for (int b0 = 0; b0 < d.Nnc; b0 += kSumGroup) {
+            float acc[kG16Cols][8];
 #pragma unroll
-        for (int j = 0; j < kG16Cols; ++j)
+            for (int j = 0; j < kG16Cols; ++j)
 #pragma unroll
-            for (int a = 0; a < 8; ++a) acc[j][a] = 0.f;
-        for (int b = 0; b < d.Nnc; ++b) {
-            const float4 *X = (const float4 *)(gen + d.gen_x_off + ((long long)k * d.Nnc + b) * M);
-            // (the barrier inside: the twiddles are staged, the previous stage's reads of y done)
-            g16_inv_rows(y, s_tw, X, C);
-            __syncthreads();
-            if (M == P) {
-                // lag tau = n - (P - N)
-                g16_inv_stage(y, wb, [&](int j, int a, int bb, float2 o) {
-                    const int n = 2048 * a + bb;
-                    if (n >= P - N) acc[j][a] = fmaf(o.x, o.x, fmaf(o.y, o.y, acc[j][a]));
-                });
-            } else {
-                // lag tau is output P + kk, kk = n - (P - N): A - W_M^-kk B
-                float2 A[kG16Cols][8];
-                g16_inv_stage(y, wb, [&](int j, int a, int, float2 o) { A[j][a] = o; });
-                g16_inv_rows(y, s_tw, X + P / 2, C + P / 2);
+                for (int a = 0; a < 8; ++a) acc[j][a] = 0.f;
+            const int b1 = min(d.Nnc, b0 + kSumGroup);
+            for (int b = b0; b < b1; ++b) {
+                const float4 *X = (const float4 *)(gen + d.gen_x_off + ((long long)k * d.Nnc + b) * M);
+                // (the barrier inside: the twiddles are staged, the previous stage's reads of y done)
+                g16_inv_rows(y, s_tw, X, C);
                 __syncthreads();
-                g16_inv_stage(y, wb, [&](int j, int a, int bb, float2 o) {
-                    const int n = 2048 * a + bb;
+                if (M == P) {
+                    // lag tau = n - (P - N)
+                    g16_inv_stage(y, wb, [&](int j, int a, int bb, float2 o) {
+                        const int n = 2048 * a + bb;
+                        if (n >= P - N) acc[j][a] = fmaf(o.x, o.x, fmaf(o.y, o.y, acc[j][a]));
+                    });
+                } else {
+                    // lag tau is output P + kk, kk = n - (P - N): A - W_M^-kk B
+                    float2 A[kG16Cols][8];
+                    g16_inv_stage(y, wb, [&](int j, int a, int, float2 o) { A[j][a] = o; });
+                    g16_inv_rows(y, s_tw, X + P / 2, C + P / 2);
+                    __syncthreads();
+                    g16_inv_stage(y, wb, [&](int j, int a, int bb, float2 o) {
+                        const int n = 2048 * a + bb;
+                        if (n >= P - N) {
+                            // W_M^-n = conj(W_M^b) W_16^-a
+                            const float2 v = c_sub(A[j][a], twiddle16(c_mulc(o, opaque(wm[j])), a, true));
+                            acc[j][a] = fmaf(v.x, v.x, fmaf(v.y, v.y, acc[j][a]));
+                        }
+                    });
+                }
+            }
+            const int tid = opaque_tid();
+#pragma unroll
+            for (int j = 0; j < kG16Cols; ++j)
+#pragma unroll
+                for (int a = 0; a < 8; ++a) {
+                    const int n = 2048 * a + tid + kG16Threads * j;
                     if (n >= P - N) {
-                        // W_M^-n = conj(W_M^b) W_16^-a
-                        const float2 v = c_sub(A[j][a], twiddle16(c_mulc(o, opaque(wm[j])), a, true));
-                        acc[j][a] = fmaf(v.x, v.x, fmaf(v.y, v.y, acc[j][a]));
+                        GNSS_GLOBAL float *o = row + (n - (P - N));
+                        *o = b0 ? *o + acc[j][a] * scale : acc[j][a] * scale;
                     }
-                });
-            }
+                }
         }
-        const int tid = opaque_tid();
-#pragma unroll
-        for (int j = 0; j < kG16Cols; ++j)
-#pragma unroll
-            for (int a = 0; a < 8; ++a) {
-                const int n = 2048 * a + tid + kG16Threads * j;
-                if (n >= P - N) row[n - (P - N)] = acc[j][a] * scale;
-            }
     }
 }
 

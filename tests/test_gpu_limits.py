@@ -1,0 +1,107 @@
+"""GPU parity at the request limits of the boundary: the largest Doppler
+window (65536 bins) and the largest non-coherent sum (100000 blocks).
+
+At 65536 bins the whole FP32 grid is compared with the oracle's FP64 FFT
+route, with detections and refinements (the usual bar, tests/parity.py).
+At 100000 blocks a power check alone could not see one block lost or summed
+twice (1e-5 of the sum), so the record is low-level noise everywhere except
+one millisecond holding a strong satellite -- the first block in one case,
+the last in the other: the detection at the planted cell shows that block
+was summed, and sampled cells (the peak and random ones) match the oracle's
+direct correlation within 1e-5 (mixed).  That bound is ten times tighter
+than the usual one, on purpose: a plain running FP32 sum over the 100000
+blocks is off by up to 2.2e-4 here (with the strong block first the sum's
+ulp is 512, and the noise blocks' smaller terms are rounded away, a bias
+rather than a random walk), while the kernels' grouped sums stay near 1e-6.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from parity import assert_grid_close, compare_detections, compare_refinement, log
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+G = pytest.importorskip("paper_1309_0052_amd")
+
+FS = 1023000  # one sample per chip: the smallest transforms, so the limits dominate
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = G.Context(0)
+    yield c
+    c.close()
+
+
+def _search(c, samples, fmt, n, fs, prns, lo, hi, step, T_coh, N_noncoh):
+    nd = O.n_doppler(lo, hi, step)
+    N = fs // 1000
+    d_x = torch.from_numpy(np.ascontiguousarray(samples)).cuda()
+    d_grid = torch.zeros(len(prns) * nd * N, dtype=torch.float32, device="cuda")
+    d_pk = torch.zeros(len(prns) * 48, dtype=torch.uint8, device="cuda")
+    req = G.make_request(d_x.data_ptr(), fmt, n, fs, 0.0, prns, lo, hi, step, T_coh, N_noncoh,
+                         d_grid.data_ptr(), d_pk.data_ptr())
+    c.acquire_device(req, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    return (d_grid.cpu().numpy().reshape(len(prns), nd, N), d_pk.cpu().numpy().view(G.PEAK_DTYPE).copy())
+
+
+@pytest.mark.timeout(600)
+def test_largest_doppler_window(ctx):
+    """65536 bins of 1 Hz (the limit), one PRN, one block."""
+    lo, hi, step = -32768.0, 32767.0, 1.0
+    nd = O.n_doppler(lo, hi, step)
+    assert nd == 65536
+    pl = [synth.Planted(prn=7, code_phase=321, doppler_hz=-1234.0, cn0_dbhz=55.0)]
+    snap = synth.make_snapshot(5, O.CPLX_I8, FS, 0.0, 1.2, pl, O.ca_code)
+    log("largest Doppler window: %d bins x 1023 phases" % nd)
+    grid, pk = _search(ctx, snap.samples, snap.fmt, snap.n, FS, [7], lo, hi, step, 1, 1)
+    P = O.grid_fft(snap.samples, snap.fmt, FS, 0.0, [7], lo, step, nd, 1, 1)
+    worst = assert_grid_close(grid, P)
+    ref = O.peaks(P, [7], 1, 2.5, lo, step)
+    exempt = compare_detections(pk, ref, P)
+    checked = compare_refinement(pk, ref, P, grid, lo, step)
+    assert checked + exempt >= 1
+    assert pk[0]["detected"] and pk[0]["code_phase"] == 321
+    # 1 ms coherent: the Doppler peak is ~1 kHz wide, noise moves its maximum
+    # by a few 1 Hz bins (the oracle's by the same: compare_detections above)
+    assert abs(lo + step * int(pk[0]["doppler_bin"]) - (-1234.0)) <= 100.0
+    log("  max mixed error %.3e" % worst)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("where", ["first", "last"])
+def test_largest_noncoherent_sum(ctx, where):
+    """100000 blocks of 1 ms (the limit), three bins; the satellite is present
+    in one block only."""
+    N_noncoh, T_coh = 100000, 1
+    n = FS // 1000 * T_coh * N_noncoh
+    rng = np.random.default_rng(17)
+    samples = rng.integers(-2, 3, size=2 * n, dtype=np.int8)  # I, Q interleaved, small noise
+    pl = [synth.Planted(prn=19, code_phase=600, doppler_hz=0.0, cn0_dbhz=71.0)]
+    sig = synth.make_snapshot(3, O.CPLX_I8, FS, 0.0, 1.0, pl, O.ca_code, noise=False)
+    b = 0 if where == "first" else N_noncoh - 1
+    seg = samples[2 * b * 1023: 2 * (b + 1) * 1023].astype(np.int16) + sig.samples[:2 * 1023].astype(np.int16)
+    samples[2 * b * 1023: 2 * (b + 1) * 1023] = np.clip(seg, -127, 127).astype(np.int8)
+    prns, lo, hi, step = [19, 4], -500.0, 500.0, 500.0
+    log("largest non-coherent sum: %d blocks, satellite in the %s block only" % (N_noncoh, where))
+    grid, pk = _search(ctx, samples, O.CPLX_I8, n, FS, prns, lo, hi, step, T_coh, N_noncoh)
+    assert np.all(np.isfinite(grid)) and np.all(grid >= 0)
+    # the satellite's block was summed: its cell is the peak, far above the noise
+    assert pk[0]["detected"] and pk[0]["code_phase"] == 600 and pk[0]["doppler_bin"] == 1, pk[0]
+    cells = [(0, 1, 600)]
+    cells += list(zip(rng.integers(0, 2, 6), rng.integers(0, 3, 6), rng.integers(0, 1023, 6)))
+    cells = np.array(cells, np.int64)
+    vals = O.cells_direct(samples, O.CPLX_I8, FS, 0.0, prns, lo, step, 3, T_coh, N_noncoh, cells)
+    got = grid[cells[:, 0], cells[:, 1], cells[:, 2]].astype(np.float64)
+    means = grid.astype(np.float64).mean(axis=(1, 2))[cells[:, 0]]
+    err = np.abs(got - vals) / (vals + means)
+    log("  peak %.4e (oracle %.4e), max mixed error %.3e" % (got[0], vals[0], err.max()))
+    assert np.all(err <= 1e-5), err
+    # one block of the satellite (about 6.5e9 at this amplitude) against the
+    # 100000 noise blocks summed at every cell (about 4.1e8): some 16 times the mean
+    assert got[0] > 10 * means[0]
