@@ -9,7 +9,10 @@ summed in the same block order and grouped at the same blocks), the group
 boundaries (256, 257 and 512 blocks), and the general-rate kernels at a
 4096-point transform and at both 16384-point cases (M = 32768 in two halves,
 M = N = 16384).  The whole FP32 grid against the oracle's FP64 FFT route
-within the mixed tolerance, with identical detections.
+within the mixed tolerance, with identical detections.  Long and short
+requests batched together and in replayed graphs equal their own searches
+bit for bit; the FP16 modes, which keep plain running sums, stay within
+their bounds over 600 blocks.
 """
 import numpy as np
 import pytest
@@ -130,3 +133,93 @@ def test_long_sum_matches_oracle(ctx, case):
         i = srch.prns.index(p.prn)
         assert pk[i]["detected"] and pk[i]["code_phase"] == p.code_phase, (p.prn, pk[i])
     log("  max mixed error %.3e, exemptions %d" % (worst, exempt))
+
+
+class _DevReq:
+    """Device buffers of one request; the grid is pre-filled with -1 so that
+    a cell the first group's store missed would show."""
+
+    def __init__(self, snap, srch):
+        self.snap, self.srch = snap, srch
+        self.shape = (len(srch.prns), O.n_doppler(srch.lo, srch.hi, srch.step), snap.fs_hz // 1000)
+        self.x = torch.from_numpy(np.ascontiguousarray(snap.samples)).cuda()
+        self.grid = torch.full((int(np.prod(self.shape)),), -1.0, dtype=torch.float32, device="cuda")
+        self.pk = torch.zeros(len(srch.prns) * 48, dtype=torch.uint8, device="cuda")
+        self.req = G.make_request(self.x.data_ptr(), snap.fmt, snap.n, snap.fs_hz, snap.f_if_hz,
+                                  srch.prns, srch.lo, srch.hi, srch.step, srch.T_coh,
+                                  srch.N_noncoh, self.grid.data_ptr(), self.pk.data_ptr())
+
+    def clear(self):
+        self.grid.fill_(-1.0)
+        self.pk.zero_()
+
+    def result(self):
+        torch.cuda.synchronize()
+        return (self.grid.cpu().numpy().reshape(self.shape).copy(),
+                self.pk.cpu().numpy().view(G.PEAK_DTYPE).copy())
+
+
+def test_long_and_short_requests_batched_and_captured(ctx):
+    """Long (several groups) and short (one group) requests, chip-rate and
+    general-rate, in one batch and in a graph replayed three times with
+    eager work between: each equals its own search alone bit for bit."""
+    items = [
+        _case("1M023_600", O.CPLX_I8, 1023000, 0.0, 1, 600, [3, 11, 19], [(11, 500.0)], -500.0, 500.0, 500.0),
+        _case("4M092_short", O.REAL_I8, 4092000, 1023000.0, 1, 4, [6, 25], [(25, -500.0)], -500.0, 500.0, 500.0),
+        _case("2M_cplx_300", O.CPLX_I8, 2000000, 0.0, 1, 300, [4, 17], [(17, 500.0)], 0.0, 500.0, 500.0),
+        _case("5M_short", O.CPLX_I8, 5000000, 0.0, 1, 3, [8], [(8, 0.0)], -500.0, 500.0, 500.0),
+    ]
+    reqs = [_DevReq(snap, srch) for snap, srch, _ in items]
+    alone = []
+    for r in reqs:
+        ctx.acquire_device(r.req)
+        alone.append(r.result())
+    for r in reqs:
+        r.clear()
+    ctx.acquire_batch_device([r.req for r in reqs])
+    for i, r in enumerate(reqs):
+        g, p = r.result()
+        assert np.array_equal(g, alone[i][0]) and np.array_equal(p, alone[i][1]), ("batch", i)
+    graph = ctx.graph([r.req for r in reqs])
+    try:
+        stream = torch.cuda.current_stream()
+        for rep in range(3):
+            for r in reqs:
+                r.clear()
+            junk = torch.randn(1 << 20, device="cuda")
+            (junk * 2.0).sum().item()
+            log("long/short graph replay %d" % rep)
+            graph.launch(stream)
+            for i, r in enumerate(reqs):
+                g, p = r.result()
+                assert np.array_equal(g, alone[i][0]) and np.array_equal(p, alone[i][1]), (rep, i)
+    finally:
+        graph.close()
+    snap, srch, _ = items[0]
+    _check(snap, srch, alone[0][0], alone[0][1])
+
+
+# the FP16 modes' derived bounds against the FP64 oracle (tests/test_gpu_fp16.py)
+TOL16 = {"fp16": 3.4e-2, "fp16pfa": 2.0e-2}
+
+
+@pytest.mark.parametrize("prec", ["fp16", "fp16pfa"])
+def test_fp16_modes_long_sum(prec):
+    """The FP16 modes keep plain running FP32 sums (their bounds are two
+    orders above the summation error), over 600 blocks rescaled between
+    block exponents: within the mode's bound, identical detections."""
+    p = G.GNSS_FP16 if prec == "fp16" else G.GNSS_FP16_PFA
+    snap, srch, pl = _case("1M023_600", O.CPLX_I8, 1023000, 0.0, 1, 600, [3, 11, 19], [(11, 500.0)],
+                           -500.0, 500.0, 500.0)
+    with G.Context(0, precision=p) as c:
+        grid, pk = _search(c, snap, srch)
+    nd = O.n_doppler(srch.lo, srch.hi, srch.step)
+    P = O.grid_fft(snap.samples, snap.fmt, snap.fs_hz, snap.f_if_hz, srch.prns, srch.lo, srch.step,
+                   nd, srch.T_coh, srch.N_noncoh)
+    tol = TOL16[prec]
+    worst = assert_grid_close(grid, P, tol)
+    ref = O.peaks(P, srch.prns, O.chip_exclusion(snap.fs_hz), 2.5, srch.lo, srch.step)
+    compare_detections(pk, ref, P, tie_rel=tol, value_rel=tol)
+    i = srch.prns.index(11)
+    assert pk[i]["detected"] and pk[i]["code_phase"] == pl[0].code_phase, pk[i]
+    log("%s, 600 blocks: max mixed error %.3e" % (prec, worst))
