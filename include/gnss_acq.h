@@ -111,8 +111,10 @@ typedef struct gnss_request {
 /* Synchronous acquisition on host buffers (Sec. 3, Fig. 2).  Uses an
  * internally locked default context on device 0; thread-safe.  samples,
  * prn_list, out_grid (nullable) and out_peaks are host memory owned by the
- * caller; outputs are written before the call returns.  Errors: GNSS_EINVAL
- * (arguments), GNSS_ENOTSUP (fs), GNSS_ENOMEM, GNSS_EDEVICE. */
+ * caller; outputs are written before the call returns.  A long request whose
+ * workspace does not fit runs in passes over its blocks (see
+ * gnss_acquire_device).  Errors: GNSS_EINVAL (arguments), GNSS_ENOTSUP (fs),
+ * GNSS_ENOMEM, GNSS_EDEVICE. */
 int gnss_acquire(const void *samples, int32_t fmt, size_t n, double fs, double f_if,
                  const int32_t *prn_list, int32_t n_prn, double doppler_lo,
                  double doppler_hi, double doppler_step, int32_t T_coh_ms,
@@ -170,6 +172,9 @@ void gnss_ctx_destroy(gnss_ctx *ctx);
  * that a data-bit flip between them does not cancel the signal; needs an even
  * N_noncoh and fs = k * 1.023 MHz, else GNSS_ENOTSUP at search time; 0,
  * the default: plain sum),
+ * "block_window" (blocks per pass of a request run alone, see
+ * gnss_acquire_device: a multiple of 256; 0, the default: all the blocks
+ * that fit),
  * "max_slots" (requests per
  * served batch, 1..4096), "fault_alloc" / "fault_copy" / "fault_launch" (n >= 1:
  * the n-th following device allocation, host/device copy or batch launch of
@@ -180,10 +185,11 @@ void gnss_ctx_destroy(gnss_ctx *ctx);
 int gnss_ctx_set(gnss_ctx *ctx, const char *key, double value);
 
 /* Device bytes the context's workspace needs for a request in FP32 (an
- * upper bound for FP16, whose spectra take half the space): the block and
- * spectrum buffers of the device-resident pipeline (Sec. 5 keeps
- * intermediates on the GPU); does not allocate.  Errors: as gnss_acquire's
- * argument checks. */
+ * upper bound for FP16, whose spectra take half the space) searched in one
+ * pass: the block and spectrum buffers of the device-resident pipeline
+ * (Sec. 5 keeps intermediates on the GPU); does not allocate.  A request run
+ * alone that needs more than the context can hold runs in passes in less.
+ * Errors: as gnss_acquire's argument checks. */
 int gnss_workspace_bytes(const gnss_request *req, size_t *bytes);
 
 /* Acquisition on device buffers (Sec. 3, Fig. 2; the whole coherent
@@ -193,8 +199,18 @@ int gnss_workspace_bytes(const gnss_request *req, size_t *bytes);
  * stream, which is PyTorch's default stream) and the call returns without waiting; outputs are valid once
  * the stream reaches that point.  The context's workspace is reused, so calls
  * on one context must not overlap on different streams.  May allocate
- * workspace on first use or growth.  Errors: GNSS_EINVAL, GNSS_ENOTSUP,
- * GNSS_ENOMEM, GNSS_EDEVICE. */
+ * workspace on first use or growth.
+ * Long requests (the non-coherent sum of Sec. 3 over many blocks): when the
+ * one-pass workspace does not fit (the HBM budget, or without one three
+ * quarters of the device's memory, beside what the context holds
+ * elsewhere), or under option "block_window", the request runs in passes of
+ * a multiple of 256 blocks, enqueued one after another on the stream; each
+ * pass wipes, folds and transforms only its own blocks at their places in
+ * the record, adds its sums to the grid (out_grid, or an internal one) and
+ * only the last detects.  In GNSS_FP32 the results equal a one-pass search
+ * bit for bit; the FP16 precisions stay within their bounds.  A request that
+ * does not fit even in 256-block passes gets GNSS_ENOMEM.
+ * Errors: GNSS_EINVAL, GNSS_ENOTSUP, GNSS_ENOMEM, GNSS_EDEVICE. */
 int gnss_acquire_device(gnss_ctx *ctx, const gnss_request *req, void *stream);
 
 /* Allocation-free form of gnss_acquire_device, for callers that cannot
@@ -214,8 +230,12 @@ int gnss_acquire_device(gnss_ctx *ctx, const gnss_request *req, void *stream);
  * device), which keeps the last call's contents; calls that overlap on one
  * GPU, on any streams or contexts, race and give undefined results.  The
  * host waits for the previous call's metadata copy before staging the next.
+ * A long request whose one pass does not fit the array runs in passes over
+ * its blocks as in gnss_acquire_device, all in the array (laid out for the
+ * first, longest pass).
  * Errors: as gnss_acquire_device; GNSS_ENOMEM (with the bytes needed in
- * gnss_last_error) when the workspace or metadata exceeds those sizes. */
+ * gnss_last_error) when the workspace or metadata exceeds those sizes even
+ * in 256-block passes. */
 #define GNSS_NOALLOC_SCRATCH_BYTES 67108864
 #define GNSS_NOALLOC_META_BYTES 1048576
 int gnss_acquire_device_noalloc(gnss_ctx *ctx, const gnss_request *req, void *stream);

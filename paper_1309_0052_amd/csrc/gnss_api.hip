@@ -302,6 +302,8 @@ void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, gnss:
         d.Tc = p.Tc;
         d.Nnc = p.Nnc;
         d.n_prn = p.n_prn;
+        d.b0 = p.b0;
+        d.acc = p.acc;
         d.n_items = p.gen ? 0 : p.n_dopp * p.spc;
         if (p.gen) {
             d.gen = 1;
@@ -325,7 +327,8 @@ void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, gnss:
             } else {
                 B.cshift_off[r] = (long long)B.cshift.size();
                 for (int k = 0; k < p.n_dopp; ++k)
-                    for (int b = 0; b < p.Nnc; ++b) B.cshift.push_back(code_shift(b, p.Tc, p.N, p.lo, p.step, k));
+                    for (int b = 0; b < p.Nnc; ++b)
+                        B.cshift.push_back(code_shift(p.b0 + b, p.Tc, p.N, p.lo, p.step, k));
             }
         }
         if (!d.grid) {
@@ -365,7 +368,8 @@ void build_batch(const gnss::Plan *plans, const gnss_request *reqs, int n, gnss:
         }
         const long long cnt[gnss::kNumStages] = {
             p.gen ? 0 : (long long)p.n_dopp * p.Nnc, p.n_vec(),
-            (long long)d.n_ptiles * cdiv(d.n_items, corr_w), (long long)p.n_prn * d.n_tau_blk, (long long)p.n_prn,
+            (long long)d.n_ptiles * cdiv(d.n_items, corr_w), p.detect ? (long long)p.n_prn * d.n_tau_blk : 0,
+            p.detect ? (long long)p.n_prn : 0,
             fd_a, fd_b,
             p.gen ? (long long)p.n_dopp * p.Nnc : 0, p.gen ? (long long)p.n_prn : 0,
             p.gen ? (long long)p.n_prn * p.n_dopp : 0};
@@ -606,15 +610,30 @@ int scratch_address(int device, void **out)
 
 // Lays the device buffers of a one-request batch out in the scratch array as
 // 256-byte-aligned views.  Fails if they do not fit.
+static void scratch_offsets(const BatchHost &B, size_t (&sizes)[7], size_t (&off)[7], size_t &end)
+{
+    const size_t sz[7] = {B.F_bytes, B.G_bytes, B.Q_bytes, B.K_bytes, B.part_bytes, B.grid_bytes, meta_bytes(B)};
+    end = 0;
+    for (int i = 0; i < 7; ++i) {
+        sizes[i] = sz[i];
+        off[i] = end;
+        end += align256(std::max<size_t>(sz[i], 1));
+    }
+}
+
+// Whether a laid-out batch fits the allocation-free scratch and staging.
+static bool scratch_fits(const BatchHost &B, const Workspace &w)
+{
+    size_t sizes[7], off[7], end;
+    scratch_offsets(B, sizes, off, end);
+    return end <= GNSS_NOALLOC_SCRATCH_BYTES && sizes[6] <= w.h_stage_cap;
+}
+
 static int scratch_layout(gnss_ctx *c, const BatchHost &B, Workspace &w)
 {
-    const size_t sizes[7] = {B.F_bytes, B.G_bytes, B.Q_bytes, B.K_bytes, B.part_bytes, B.grid_bytes, meta_bytes(B)};
     DevBuf *bufs[7] = {&w.F, &w.G, &w.Q, &w.K, &w.part, &w.grid, &w.meta};
-    size_t off[7], end = 0;
-    for (int i = 0; i < 7; ++i) {
-        off[i] = end;
-        end += align256(std::max<size_t>(sizes[i], 1));
-    }
+    size_t sizes[7], off[7], end;
+    scratch_offsets(B, sizes, off, end);
     if (end > GNSS_NOALLOC_SCRATCH_BYTES)
         return set_err(GNSS_ENOMEM, "the request needs %zu bytes of workspace, more than the %zu of the "
                        "allocation-free scratch", end, (size_t)GNSS_NOALLOC_SCRATCH_BYTES);
@@ -711,6 +730,7 @@ int ctx_init_tables(gnss_ctx *c)
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, c->device));
     c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+    c->dev_total = prop.totalGlobalMem;
     // set-up of the allocation-free entry point: the device address of the
     // static scratch array, the pinned metadata staging and the events it uses
     int rc = scratch_address(c->device, &c->d_scratch);
@@ -786,6 +806,92 @@ int default_ctx(gnss_ctx **out)
 }  // namespace gnss_rt
 
 using namespace gnss_rt;
+
+// ---- long requests: passes over the blocks ---------------------------------
+// A request run alone whose workspace does not fit (or option block_window)
+// runs in passes of a multiple of kSumGroup blocks: the FP32 kernels then
+// group their sums at the same blocks as in one pass, so the results are
+// the same bit for bit.  Each pass after the first adds its sums to the
+// grid's, and only the last one detects.
+
+static void lay_out_pass(gnss_ctx *c, const gnss::Plan &p, const gnss_request &r, int b0, int nb, BatchHost &B)
+{
+    gnss::Plan q = p;
+    q.b0 = b0;
+    q.Nnc = nb;
+    q.acc = b0 > 0;
+    q.detect = b0 + nb == p.Nnc;
+    build_batch(&q, &r, 1, corr_shape_for(c, &q, 1), c->threshold, c->precision, c->doppler_fd, c->code_doppler, B);
+}
+
+// Whether request r needs passes, given the layout B of its one pass.
+template <typename Fits>
+static bool needs_passes(gnss_ctx *c, const gnss::Plan &p, const BatchHost &B, Fits fits)
+{
+    if (p.Nnc <= gnss::kSumGroup) return false;
+    if (c->block_window > 0) return c->block_window < p.Nnc;
+    return B.cshift_bad >= 0 || !fits(B);
+}
+
+// Blocks per pass: option block_window, else the largest multiple of
+// kSumGroup whose pass layout fits; all of them (one pass, which then
+// reports the shortage) when not even kSumGroup blocks fit.
+template <typename Fits>
+static int pass_blocks(gnss_ctx *c, const gnss::Plan &p, const gnss_request &r, Fits fits)
+{
+    if (c->block_window > 0) return std::min(c->block_window, p.Nnc);
+    auto ok = [&](int nb) {
+        BatchHost B;
+        lay_out_pass(c, p, r, 0, nb, B);
+        return B.cshift_bad < 0 && fits(B);
+    };
+    if (!ok(gnss::kSumGroup)) return p.Nnc;
+    int lo = 1, hi = (p.Nnc - 1) / gnss::kSumGroup;  // groups per pass; ok(lo groups)
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (ok(mid * gnss::kSumGroup))
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo * gnss::kSumGroup;
+}
+
+// Whether a layout fits the context's HBM budget (without one, three
+// quarters of the device's memory) beside the device memory the context
+// holds outside workspace w; extra: what the call needs besides the batch.
+static bool fits_hbm(gnss_ctx *c, const Workspace &w, const BatchHost &B, size_t extra)
+{
+    const DevBuf *bufs[] = {&w.F, &w.G, &w.Q, &w.K, &w.part, &w.grid, &w.meta, &w.samples, &w.peaks};
+    size_t held = 0;
+    for (const DevBuf *b : bufs)
+        if (b->owned) held += b->cap;
+    size_t dev;
+    {
+        std::lock_guard<std::mutex> lk(c->mem_mu);
+        dev = c->dev_bytes;
+    }
+    const size_t other = dev > held ? dev - held : 0;
+    const size_t limit = c->budget ? c->budget : c->dev_total / 4 * 3;
+    return other + batch_device_bytes(B) + extra <= limit;
+}
+
+// Runs request r alone on stream s in passes of nb blocks; B gets the last
+// pass's layout.  Allocation-free (scratch): the first pass, the longest,
+// lays out the static scratch and the others run in that layout, so the
+// grid keeps its place.
+static int run_passes(gnss_ctx *c, Workspace &w, const gnss::Plan &p, const gnss_request &r, int nb,
+                      hipStream_t s, bool prof, bool scratch, BatchHost &B)
+{
+    int rc;
+    for (int b0 = 0; b0 < p.Nnc; b0 += nb) {
+        lay_out_pass(c, p, r, b0, std::min(nb, p.Nnc - b0), B);
+        if (scratch && b0 == 0 && (rc = scratch_layout(c, B, w))) return rc;
+        gnss::Launch L;
+        if ((rc = stage_batch(c, w, B, s, L)) || (rc = launch(c, w, L, s, prof))) return rc;
+    }
+    return GNSS_OK;
+}
 
 extern "C" {
 
@@ -914,6 +1020,12 @@ int gnss_ctx_set(gnss_ctx *ctx, const char *key, double value)
         a.store((int)value);
         return GNSS_OK;
     }
+    if (!strcmp(key, "block_window")) {
+        if (!(value >= 0.0) || value > 1e9 || value != std::floor(value) || (long long)value % gnss::kSumGroup)
+            return set_err(GNSS_EINVAL, "block_window must be 0 or a multiple of %d", gnss::kSumGroup);
+        ctx->block_window = (int)value;
+        return GNSS_OK;
+    }
     if (!strcmp(key, "max_slots")) {
         if (!(value >= 1.0) || value > 4096.0) return set_err(GNSS_EINVAL, "max_slots outside [1, 4096]");
         ctx->max_slots = (int)value;
@@ -967,6 +1079,13 @@ int gnss_acquire_batch_device(gnss_ctx *ctx, const gnss_request *reqs, int32_t n
     hipStream_t s = (hipStream_t)stream;
     BatchHost B;
     build_batch(plans.data(), reqs, n_req, corr_shape_for(ctx, plans.data(), n_req), ctx->threshold, ctx->precision, ctx->doppler_fd, ctx->code_doppler, B);
+    if (n_req == 1) {
+        auto fits = [&](const BatchHost &Bx) { return fits_hbm(ctx, ctx->ws, Bx, 0); };
+        if (needs_passes(ctx, plans[0], B, fits)) {
+            const int nb = pass_blocks(ctx, plans[0], reqs[0], fits);
+            if (nb < plans[0].Nnc) return run_passes(ctx, ctx->ws, plans[0], reqs[0], nb, s, true, false, B);
+        }
+    }
     gnss::Launch L;
     if ((rc = stage_batch(ctx, ctx->ws, B, s, L))) return rc;
     return launch(ctx, ctx->ws, L, s, true);
@@ -992,9 +1111,14 @@ int gnss_acquire_device_noalloc(gnss_ctx *ctx, const gnss_request *req, void *st
     build_batch(&p, req, 1, corr_shape_for(ctx, &p, 1), ctx->threshold, ctx->precision, ctx->doppler_fd,
                 ctx->code_doppler, B);
     Workspace &w = ctx->ws_na;
+    // every buffer gets the capacity the batch needs in the scratch, and the
+    // staging and its events exist: staging and launch allocate nothing
+    auto fits = [&](const BatchHost &Bx) { return scratch_fits(Bx, w); };
+    if (needs_passes(ctx, p, B, fits)) {
+        const int nb = pass_blocks(ctx, p, *req, fits);
+        if (nb < p.Nnc) return run_passes(ctx, w, p, *req, nb, s, false, true, B);
+    }
     if ((rc = scratch_layout(ctx, B, w))) return rc;
-    // every buffer now has the capacity the batch needs, and the staging and
-    // its events exist: staging and launch allocate nothing
     gnss::Launch L;
     if ((rc = stage_batch(ctx, w, B, s, L))) return rc;
     return launch(ctx, w, L, s, false);
@@ -1043,8 +1167,12 @@ int gnss_acquire(const void *samples, int32_t fmt, size_t n, double fs, double f
     dr.out_peaks = (gnss_peak *)w.peaks.p;
     BatchHost B;
     build_batch(&p, &dr, 1, corr_shape_for(c, &p, 1), c->threshold, c->precision, c->doppler_fd, c->code_doppler, B);
+    auto fits = [&](const BatchHost &Bx) { return fits_hbm(c, w, Bx, sb + pb); };
+    int nb = p.Nnc;
+    if (needs_passes(c, p, B, fits)) nb = pass_blocks(c, p, dr, fits);
     gnss::Launch L;
-    if ((rc = stage_batch(c, w, B, c->stream, L)) || (rc = launch(c, w, L, c->stream, true))) {
+    if (nb < p.Nnc ? (rc = run_passes(c, w, p, dr, nb, c->stream, true, false, B))
+                   : ((rc = stage_batch(c, w, B, c->stream, L)) || (rc = launch(c, w, L, c->stream, true)))) {
         (void)hipStreamSynchronize(c->stream);
         return rc;
     }

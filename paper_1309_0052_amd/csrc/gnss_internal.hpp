@@ -49,6 +49,9 @@ struct Plan {
     // length-N correlations run on zero-padded transforms of length gen_M
     int gen;
     int gen_M;      // power of two >= 2N
+    // a pass over part of the blocks (see ReqDesc): the first block, whether
+    // the grid already holds earlier passes' sums, whether detection runs
+    int b0 = 0, acc = 0, detect = 1;
     int64_t grid_elems() const { return (int64_t)n_prn * n_dopp * N; }
     int64_t n_vec() const { return gen ? 0 : (int64_t)n_dopp * Nnc * spc; }
 };
@@ -167,6 +170,12 @@ struct ReqDesc {
     // (float2 offsets in the general-rate region of the spectrum buffer)
     int gen, gen_M, gen_P;
     long long gen_x_off, gen_c_off;
+    // A long request may run in passes over its blocks: this pass's blocks
+    // are the record's blocks b0 .. b0 + Nnc - 1 (sample positions and
+    // carrier phases are the record's; F, G and the shift table hold the
+    // pass's blocks only), and with acc the correlation adds its sums to the
+    // grid's, those of the earlier passes
+    int b0, acc;
     int prns[kMaxList];
 };
 

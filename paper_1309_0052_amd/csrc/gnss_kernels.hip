@@ -282,7 +282,7 @@ __global__ __launch_bounds__(256) void k_wipe_fold(const ReqDesc *__restrict__ R
     __syncthreads();
     int2 *dst = out + (long long)blockIdx.x * d.N;
     for (int m = threadIdx.x; m < d.N; m += 256)
-        dst[m] = wipe_fold_one(d.samples, d.fmt, d.N, d.Tc, s_lut, D, b, m);
+        dst[m] = wipe_fold_one(d.samples, d.fmt, d.N, d.Tc, s_lut, D, d.b0 + b, m);
 }
 
 hipError_t launch_wipe_fold(const Launch &L, const Plan &p, const uint32_t *d_lut, int32_t *d_out, hipStream_t s)
@@ -451,11 +451,11 @@ __device__ __forceinline__ void box_item(const ReqDesc &d, int k, int b, const u
         const int len = cnt + spc - 1;
         __syncthreads();  // LUT staged / previous chunk's boxcar done
         if (d.fmt == GNSS_CPLX_I8)
-            box_wipe<GNSS_CPLX_I8, NT>(d.samples, N, d.Tc, s_lut, D, b, n0, len, shift, s_f);
+            box_wipe<GNSS_CPLX_I8, NT>(d.samples, N, d.Tc, s_lut, D, d.b0 + b, n0, len, shift, s_f);
         else if (d.fmt == GNSS_REAL_I8)
-            box_wipe<GNSS_REAL_I8, NT>(d.samples, N, d.Tc, s_lut, D, b, n0, len, shift, s_f);
+            box_wipe<GNSS_REAL_I8, NT>(d.samples, N, d.Tc, s_lut, D, d.b0 + b, n0, len, shift, s_f);
         else
-            box_wipe<GNSS_REAL_2BIT_PACKED, NT>(d.samples, N, d.Tc, s_lut, D, b, n0, len, shift, s_f);
+            box_wipe<GNSS_REAL_2BIT_PACKED, NT>(d.samples, N, d.Tc, s_lut, D, d.b0 + b, n0, len, shift, s_f);
         __syncthreads();
         const int n_runs = (cnt + kBoxRun - 1) / kBoxRun;
         for (int rr = threadIdx.x; rr < n_runs; rr += NT) {
@@ -711,7 +711,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE))) v
             float2 *xb = s_xb + w * kXbufElemsQ;
             // groups of kSumGroup blocks (one for most requests)
             for (int b0 = 0; b0 < d.Nnc; b0 += kSumGroup) {
-                if (b0) add_group<PT>(acc, d, ptile, k, s, l, 0x1p-46f, b0 > kSumGroup);
+                if (b0) add_group<PT>(acc, d, ptile, k, s, l, 0x1p-46f, d.acc || b0 > kSumGroup);
                 const float4 *gk = G + (d.vec_off + ((long long)k * d.Nnc + b0) * spc + s) * kVec;
                 const int nb = min(d.Nnc - b0, kSumGroup);
                 for (int b = 0; b < nb; ++b) {
@@ -748,7 +748,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE))) v
             }
         }
 
-        store_tile<PT, W>(acc, s_stage, d, ptile, chunk, w, l, tid, 0x1p-46f, d.Nnc > kSumGroup);
+        store_tile<PT, W>(acc, s_stage, d, ptile, chunk, w, l, tid, 0x1p-46f, d.acc || d.Nnc > kSumGroup);
     }
 }
 
@@ -1090,7 +1090,7 @@ __global__ __launch_bounds__(64 * kCorrWavesH) __attribute__((amdgpu_waves_per_e
             }
         }
 
-        store_tile<PT, W>(acc, s_stage, d, ptile, chunk, w, l, tid, out_scale);
+        store_tile<PT, W>(acc, s_stage, d, ptile, chunk, w, l, tid, out_scale, d.acc != 0);
     }
 }
 
@@ -1608,7 +1608,7 @@ __global__ __launch_bounds__(64 * kCorrWavesX) void k_corr_x(const ReqDesc *__re
                         }
             }
             __syncthreads();
-            write_rows<W>(s_stage, d, pi, chunk, tid);
+            write_rows<W>(s_stage, d, pi, chunk, tid, d.acc != 0);
         }
     }
 }
@@ -1658,7 +1658,7 @@ __global__ __launch_bounds__(256) void k_fd_pass1(const ReqDesc *__restrict__ R,
         const long long local = it - pst[r];
         const int A = d.fd_A, b = (int)(local / A), n1 = (int)(local % A);
         const long long M = (long long)A * kCodeLen, L = (long long)d.Tc * d.N;
-        const long long base = (long long)b * L;
+        const long long base = (long long)(d.b0 + b) * L;
         if (n1 < d.fd_PTc && l == 0) fd_rowmax(FD, d)[b * d.fd_PTc + n1] = 0u;  // for the second pass
         float vr[3][2][4], vi[3][2][4];
         float nrm = 0.f;
@@ -2229,7 +2229,7 @@ __global__ __launch_bounds__(kGenThreads) void k_gen_x(const ReqDesc *__restrict
             if (n < N) {
                 int m = n - shift;
                 if (m < 0) m += N;
-                const int2 v = wipe_fold_one(d.samples, d.fmt, N, d.Tc, s_lut, D, b, m);
+                const int2 v = wipe_fold_one(d.samples, d.fmt, N, d.Tc, s_lut, D, d.b0 + b, m);
                 f[i] = make_float2((float)v.x, (float)v.y);
             }
         }
@@ -2319,7 +2319,7 @@ __device__ __forceinline__ void gen_corr_item(const ReqDesc &d, int k, int pi, c
 #pragma unroll
         for (int i = 0; i < kPer; ++i) {
             const int tau = tid + kGenThreads * i;
-            if (tau < N) row[tau] = b0 ? row[tau] + acc[i] * scale : acc[i] * scale;
+            if (tau < N) row[tau] = (b0 || d.acc) ? row[tau] + acc[i] * scale : acc[i] * scale;
         }
     }
 }
@@ -2559,7 +2559,7 @@ __device__ __forceinline__ void g16_fold(const ReqDesc &d, int b, uint32_t D, in
             yi[j][a] = 0;
         }
     for (int c = 0; c < Tc; ++c) {
-        const long long base = (long long)(b * Tc + c) * N;
+        const long long base = (long long)((d.b0 + b) * Tc + c) * N;
 #pragma unroll
         for (int j = 0; j < kG16Cols; ++j)
 #pragma unroll
@@ -2702,7 +2702,7 @@ __global__ __launch_bounds__(kG16Threads) void k_gen_corr16(const ReqDesc *__res
                     const int n = 2048 * a + tid + kG16Threads * j;
                     if (n >= P - N) {
                         GNSS_GLOBAL float *o = row + (n - (P - N));
-                        *o = b0 ? *o + acc[j][a] * scale : acc[j][a] * scale;
+                        *o = (b0 || d.acc) ? *o + acc[j][a] * scale : acc[j][a] * scale;
                     }
                 }
         }

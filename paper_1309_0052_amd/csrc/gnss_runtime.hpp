@@ -91,6 +91,7 @@ struct gnss_ctx {
     int device = 0;
     int n_cu = 1;
     size_t budget = 0;      // 0: unlimited
+    size_t dev_total = 0;   // the device's memory (bytes)
     size_t dev_bytes = 0;   // device bytes held by this context (tables + workspaces)
     size_t table_bytes = 0; // of which the constant tables
     int precision = GNSS_FP32;
@@ -103,6 +104,7 @@ struct gnss_ctx {
     int doppler_fd = 0;     // 1: frequency-domain Doppler (exact-length contexts)
     int nav_pairs = 0;      // 1: blocks in pairs, max over the navigation-bit sign (exact-length contexts)
     int max_slots = 64;     // requests per served batch
+    int block_window = 0;   // blocks per pass of a request run alone; 0: all that fit
     hipStream_t stream = nullptr;
     // tables
     uint32_t *d_lut = nullptr;  // [1024] packed cos16 | sin16 << 16

@@ -3,8 +3,10 @@ the same search as gnss_acquire_device with its workspace in the library's
 static scratch array.  Its results must equal gnss_acquire_device's bit for
 bit (same kernels, same arithmetic, same order), on consecutive calls whose
 second is smaller than the first (the scratch keeps the previous call's
-contents), in every precision; a request too large for the scratch is
-refused with GNSS_ENOMEM and leaves the context usable."""
+contents), in every precision; a long request whose one pass the scratch
+cannot hold runs in passes over its blocks through the scratch; a request
+too large for the scratch even so is refused with GNSS_ENOMEM and leaves
+the context usable."""
 import numpy as np
 import pytest
 
@@ -145,5 +147,38 @@ def test_noalloc_refuses_oversize_request_and_allocates_nothing(strong_case):
             assert np.array_equal(g, ref[0])
             _same_peaks(pk, ref[1])
             d.clear()
+        torch.cuda.synchronize()
+        assert torch.cuda.mem_get_info()[0] == free0
+
+
+def test_noalloc_runs_a_long_request_in_passes():
+    """A request whose one pass the scratch cannot hold (2000 blocks: about
+    150 MB of workspace) but whose 256-block passes it can runs in passes
+    through the scratch, equal to gnss_acquire_device bit for bit, with no
+    new device memory; then a small request on the same scratch."""
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    pl = [synth.Planted(prn=11, code_phase=345, doppler_hz=-500.0, cn0_dbhz=38.0)]
+    snap = synth.make_snapshot(61, synth.CPLX_I8, 1023000, 0.0, 2000.25, pl, O.ca_code)
+    srch = synth.Search([3, 11, 19], -500.0, 500.0, 500.0, 1, 2000)
+    small_snap, small_srch = _small_case()
+    with G.Context(0) as ctx:
+        long_, small = Dev(snap, srch), Dev(small_snap, small_srch)
+        ctx.acquire_device(long_.req)
+        ref = long_.result()
+        ctx.acquire_device(small.req)
+        ref_small = small.result()
+        long_.clear()
+        small.clear()
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        ctx.acquire_device_noalloc(long_.req)
+        g, pk = long_.result()
+        assert np.array_equal(g, ref[0])
+        _same_peaks(pk, ref[1])
+        assert pk[1]["detected"] and pk[1]["code_phase"] == 345
+        ctx.acquire_device_noalloc(small.req)
+        g, pk = small.result()
+        assert np.array_equal(g, ref_small[0])
+        _same_peaks(pk, ref_small[1])
         torch.cuda.synchronize()
         assert torch.cuda.mem_get_info()[0] == free0
