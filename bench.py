@@ -102,6 +102,11 @@ def workload(name: str, code_fn):
         desc = ("weak-signal complex int8 baseband at a general rate, fs 10.000 MHz, 100 ms, 8 planted; "
                 "32 PRN x 121 Doppler (+-7.5 kHz / 125 Hz) x 10000 phases, 4 ms coh x 25 noncoh "
                 "(zero-padded 32768-point FP32 transforms)")
+    elif name == "long":
+        snap, srch = synth.long_complex_int8(code_fn, seed=3)
+        desc = ("long weak-signal integration, complex int8 baseband, fs 16.368 MHz, 2.048 s, 8 planted at "
+                "22-30 dB-Hz; 32 PRN x 121 Doppler (+-7.5 kHz / 125 Hz) x 16368 phases, 4 ms coh x 512 "
+                "noncoh, under an HBM budget that makes it run in passes over its blocks")
     elif name == "strong":
         snap, srch = synth.strong_real_2bit(code_fn, seed=1)
         desc = ("strong-signal real 2-bit IF, fs 4.092 MHz, f_IF 1.023 MHz, 10 ms, 4 planted; "
@@ -174,7 +179,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="weak",
-                    choices=["weak", "weak10", "strong", "batch", "serve", "track", "precision"])
+                    choices=["weak", "weak10", "long", "strong", "batch", "serve", "track", "precision"])
     ap.add_argument("--batch-n", type=int, default=256, help="snapshots in the batch workload")
     ap.add_argument("--rates", default="50,200,800", help="serve: Poisson arrival rates, req/s")
     ap.add_argument("--serve-n", type=int, default=2000, help="serve: timed requests per rate")
@@ -182,6 +187,8 @@ def main():
     ap.add_argument("--serve-kind", default="mixed", choices=["mixed", "strong"],
                     help="serve: heterogeneous batch-style requests or strong-signal snapshots")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget")
+    ap.add_argument("--long-budget-gb", type=float, default=16.0,
+                    help="long: the context's HBM budget (one pass of the request needs ~24 GB)")
     ap.add_argument("--corr-ptile", type=int, default=0, choices=[0, 1, 2, 4, 8],
                     help="PRN tile of the correlation kernel; 0: autotuned for the workload")
     ap.add_argument("--corr-waves", type=int, default=0, choices=[0, 4, 6, 8, 12],
@@ -221,7 +228,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     prec = precision_const(G, args.precision)
-    ctx = G.Context(0, precision=prec)
+    budget = int(args.long_budget_gb * (1 << 30)) if args.workload == "long" else 0
+    ctx = G.Context(0, hbm_budget_bytes=budget, precision=prec)
     if args.corr_ptile:
         ctx.set("corr_ptile", args.corr_ptile)
     if args.corr_waves:
@@ -266,7 +274,12 @@ def main():
                          d_grid.data_ptr(), d_pk.data_ptr())
     pt, sched = args.corr_ptile, args.persistent
     if not pt or sched < 0:  # explicit tile and schedule options skip the autotuner
-        t_pt, t_sched = ctx.autotune([req], os.path.join("/tmp", "gnss_autotune.txt"))
+        # the tuner times one-pass batches; its choice is kept per rate mix, so a
+        # request run in passes is tuned on its first 256 blocks
+        tune = req if args.workload != "long" else G.make_request(
+            d_x.data_ptr(), snap.fmt, snap.n, snap.fs_hz, snap.f_if_hz, srch.prns, srch.lo, srch.hi,
+            srch.step, srch.T_coh, 256, d_grid.data_ptr(), d_pk.data_ptr())
+        t_pt, t_sched = ctx.autotune([tune], os.path.join("/tmp", "gnss_autotune.txt"))
         pt, sched = pt or t_pt, sched if sched >= 0 else t_sched
     ctx.set("profile", 1)
     for _ in range(args.warmup):
@@ -295,9 +308,11 @@ def main():
     cells = n_prn * nd * N * srch.T_coh * srch.N_noncoh
     value = cells / (ms_step / 1e3)
 
-    # dominant kernel: spectrum product -> IFFT -> |.|^2 -> block sum
+    # dominant kernel: spectrum product -> IFFT -> |.|^2 -> block sum; a request
+    # run in passes over its blocks launches it once per pass
     corr_ms = stages["corr"][0] / max(1, stages["corr"][1])
-    units = n_prn * nd * srch.N_noncoh  # (PRN, Doppler, block) correlations per launch
+    lps = max(1, stages["corr"][1]) / args.steps  # correlation launches per step
+    units = n_prn * nd * srch.N_noncoh / lps  # (PRN, Doppler, block) correlations per launch
     flops_unit = 5.0 * N * math.log2(N) + 10.0 * N
     wl = args.workload
     general = snap.fs_hz % 1023000 != 0 or snap.fs_hz // 1023000 > 16
@@ -327,7 +342,7 @@ def main():
         n_vec = nd * srch.N_noncoh * (N // 1023)
         g_vec = G_VEC_BYTES[args.precision]
         staged = n_vec * (8192 + 2 * g_vec) + n_prn * nd * N * 4
-    pipe_ms = stages["fft"][0] / max(1, stages["fft"][1]) + corr_ms
+    pipe_ms = (stages["fft"][0] + stages["corr"][0]) / args.steps
     fft_hbm = {"staged_bytes": staged, "time_ms": round(pipe_ms, 4),
                "achieved_GBs": round(staged / (pipe_ms / 1e3) / 1e9, 1), "peak_GBs": PEAK_HBM_GBS,
                "frac": round(staged / (pipe_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
@@ -374,7 +389,9 @@ def main():
                        "planted_found": sorted(planted & detected)},
         "source_hash": kernel_source_hash(),
     }
-    if not args.no_other_modes and args.precision == "fp32" and not args.doppler_fd and not general:
+    if args.workload == "long":
+        out["passes"] = long_passes(args, G, torch, d_x, d_grid, snap, srch, stream, lps, ms_step, budget)
+    elif not args.no_other_modes and args.precision == "fp32" and not args.doppler_fd and not general:
         out["other_modes"] = other_modes(args, G, torch, d_x, snap, srch, cells, stream)
     if (not args.no_extras and args.workload == "weak" and args.precision == "fp32" and not args.doppler_fd):
         codes = {p: code_fn(p) for p in range(1, 38)}  # the GPU's codes, kept past this context
@@ -389,6 +406,39 @@ def main():
             out["cpu_baseline"] = {"error": "%s: %s" % (type(e).__name__, e), "kind": "oracle"}
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def long_passes(args, G, torch, d_x, d_grid, snap, srch, stream, lps, ms_step, budget):
+    """The long request in passes (under the context's budget) against the same
+    request in one pass on an unlimited context: ms per step of each, and
+    whether the grids are the same bit for bit (they must be in FP32)."""
+    nd = G.n_doppler(srch.lo, srch.hi, srch.step)
+    N = snap.fs_hz // 1000
+    n_prn = len(srch.prns)
+    probe = G.make_request(d_x.data_ptr(), snap.fmt, snap.n, snap.fs_hz, snap.f_if_hz, srch.prns, srch.lo,
+                           srch.hi, srch.step, srch.T_coh, srch.N_noncoh, None, 1)
+    res = {"budget_gb": budget / (1 << 30), "one_pass_workspace_gb": G.gnss_workspace_bytes(probe) / (1 << 30),
+           "passes_per_step": lps, "ms_per_step_in_passes": ms_step}
+    c = G.Context(0, precision=precision_const(G, args.precision))
+    try:
+        g = torch.empty(n_prn * nd * N, dtype=torch.float32, device="cuda")
+        pk = torch.zeros(n_prn * 48, dtype=torch.uint8, device="cuda")
+        req = G.make_request(d_x.data_ptr(), snap.fmt, snap.n, snap.fs_hz, snap.f_if_hz, srch.prns, srch.lo,
+                             srch.hi, srch.step, srch.T_coh, srch.N_noncoh, g.data_ptr(), pk.data_ptr())
+        c.acquire_device(req, stream)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        steps = max(1, min(args.steps, 5))
+        ev[0].record(stream)
+        for _ in range(steps):
+            c.acquire_device(req, stream)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        res["ms_per_step_one_pass"] = ev[0].elapsed_time(ev[1]) / steps
+        res["grid_equal_one_pass"] = bool(torch.equal(g, d_grid))
+    finally:
+        c.close()
+    return res
 
 
 def other_modes(args, G, torch, d_x, snap, srch, cells, stream):

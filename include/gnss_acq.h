@@ -270,7 +270,9 @@ void gnss_graph_destroy(gnss_graph *graph);
  * the text cache file `cache_path` (nullable) keyed by device, precision and
  * rate signature; writes the cache and sets the context to use the choice
  * (options "corr_ptile", "corr_waves" and "persistent" override it); the
- * cache file holds "key tile schedule waves" lines.
+ * cache file holds "key tile schedule waves" lines.  The timed runs are
+ * one-pass batches: a request that only fits in passes over its blocks gets
+ * GNSS_ENOMEM here, and a shorter request at the same rates tunes it.
  * *chosen_tile and *chosen_persistent (nullable) get it. */
 int gnss_autotune(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, const char *cache_path,
                   int32_t *chosen_tile, int32_t *chosen_persistent);

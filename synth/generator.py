@@ -207,6 +207,17 @@ def weak_complex_int8(code_fn, seed: int = 2, fs: int = 16368000):
     return snap, Search(list(range(1, 33)), -7500.0, 7500.0, 125.0, 4, 25)
 
 
+def long_complex_int8(code_fn, seed: int = 3, fs: int = 16368000, blocks: int = 512):
+    """Complex int8 baseband, fs 16.368 MHz, 4 ms x `blocks` (2.048 s by
+    default); 8 planted PRNs at C/N0 U[22, 30] dB-Hz, weaker than a 100 ms
+    record can show, Doppler U[-7.5, 7.5] kHz, 20 ms nav-bit flips; search
+    PRN 1-32, +-7.5 kHz step 125 Hz, 4 ms x `blocks`."""
+    rng = np.random.default_rng([seed, 5])
+    planted = _draw_planted(rng, 8, range(1, 33), fs // 1000, 7500.0, 22.0, 30.0, True)
+    snap = make_snapshot(seed, CPLX_I8, fs, 0.0, 4.0 * blocks + 0.5, planted, code_fn)
+    return snap, Search(list(range(1, 33)), -7500.0, 7500.0, 125.0, 4, blocks)
+
+
 def batch_workload(code_fn, seed: int = 4, n: int = 256, ms_range=(20, 200), rates=None,
                    prn_range=(8, 32), window_khz=(2.0, 10.0), planted_range=(1, 6),
                    cn0_range=(30.0, 45.0), workers: int = 1):
