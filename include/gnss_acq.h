@@ -292,9 +292,11 @@ typedef struct gnss_ticket_info {
  * the call returns; prn_list is copied; out_peaks (and out_grid if not
  * null) must stay valid until the ticket is reported done.  A context
  * thread batches queued requests as batch slots and the HBM budget allow
- * (two batches in flight, overlapping on the device).  Errors: argument
- * errors as gnss_acquire; GNSS_ENOMEM if the request alone exceeds a batch
- * slot's share of the budget. */
+ * (two batches in flight, overlapping on the device).  A request whose
+ * one pass exceeds a batch slot's share of the budget runs alone in passes
+ * over its blocks (see gnss_acquire_device), each within the share.
+ * Errors: argument errors as gnss_acquire; GNSS_ENOMEM if the request
+ * exceeds a slot's share even in 256-block passes. */
 int gnss_submit(gnss_ctx *ctx, const gnss_request *req, uint64_t *ticket);
 
 /* Non-blocking completion check of a submitted request (the cloud client's

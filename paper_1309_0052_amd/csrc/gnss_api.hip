@@ -803,18 +803,10 @@ int default_ctx(gnss_ctx **out)
     return GNSS_OK;
 }
 
-}  // namespace gnss_rt
 
-using namespace gnss_rt;
+// ---- long requests: passes over the blocks (gnss_runtime.hpp) -------------
 
-// ---- long requests: passes over the blocks ---------------------------------
-// A request run alone whose workspace does not fit (or option block_window)
-// runs in passes of a multiple of kSumGroup blocks: the FP32 kernels then
-// group their sums at the same blocks as in one pass, so the results are
-// the same bit for bit.  Each pass after the first adds its sums to the
-// grid's, and only the last one detects.
-
-static void lay_out_pass(gnss_ctx *c, const gnss::Plan &p, const gnss_request &r, int b0, int nb, BatchHost &B)
+void lay_out_pass(gnss_ctx *c, const gnss::Plan &p, const gnss_request &r, int b0, int nb, BatchHost &B)
 {
     gnss::Plan q = p;
     q.b0 = b0;
@@ -822,39 +814,6 @@ static void lay_out_pass(gnss_ctx *c, const gnss::Plan &p, const gnss_request &r
     q.acc = b0 > 0;
     q.detect = b0 + nb == p.Nnc;
     build_batch(&q, &r, 1, corr_shape_for(c, &q, 1), c->threshold, c->precision, c->doppler_fd, c->code_doppler, B);
-}
-
-// Whether request r needs passes, given the layout B of its one pass.
-template <typename Fits>
-static bool needs_passes(gnss_ctx *c, const gnss::Plan &p, const BatchHost &B, Fits fits)
-{
-    if (p.Nnc <= gnss::kSumGroup) return false;
-    if (c->block_window > 0) return c->block_window < p.Nnc;
-    return B.cshift_bad >= 0 || !fits(B);
-}
-
-// Blocks per pass: option block_window, else the largest multiple of
-// kSumGroup whose pass layout fits; all of them (one pass, which then
-// reports the shortage) when not even kSumGroup blocks fit.
-template <typename Fits>
-static int pass_blocks(gnss_ctx *c, const gnss::Plan &p, const gnss_request &r, Fits fits)
-{
-    if (c->block_window > 0) return std::min(c->block_window, p.Nnc);
-    auto ok = [&](int nb) {
-        BatchHost B;
-        lay_out_pass(c, p, r, 0, nb, B);
-        return B.cshift_bad < 0 && fits(B);
-    };
-    if (!ok(gnss::kSumGroup)) return p.Nnc;
-    int lo = 1, hi = (p.Nnc - 1) / gnss::kSumGroup;  // groups per pass; ok(lo groups)
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) / 2;
-        if (ok(mid * gnss::kSumGroup))
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo * gnss::kSumGroup;
 }
 
 // Whether a layout fits the context's HBM budget (without one, three
@@ -876,11 +835,7 @@ static bool fits_hbm(gnss_ctx *c, const Workspace &w, const BatchHost &B, size_t
     return other + batch_device_bytes(B) + extra <= limit;
 }
 
-// Runs request r alone on stream s in passes of nb blocks; B gets the last
-// pass's layout.  Allocation-free (scratch): the first pass, the longest,
-// lays out the static scratch and the others run in that layout, so the
-// grid keeps its place.
-static int run_passes(gnss_ctx *c, Workspace &w, const gnss::Plan &p, const gnss_request &r, int nb,
+int run_passes(gnss_ctx *c, Workspace &w, const gnss::Plan &p, const gnss_request &r, int nb,
                       hipStream_t s, bool prof, bool scratch, BatchHost &B)
 {
     int rc;
@@ -892,6 +847,10 @@ static int run_passes(gnss_ctx *c, Workspace &w, const gnss::Plan &p, const gnss
     }
     return GNSS_OK;
 }
+
+}  // namespace gnss_rt
+
+using namespace gnss_rt;
 
 extern "C" {
 

@@ -192,6 +192,52 @@ size_t batch_device_bytes(const BatchHost &B);
 int stage_batch(gnss_ctx *c, Workspace &w, BatchHost &B, hipStream_t s, gnss::Launch &L, bool meta_only = false);
 int launch(gnss_ctx *c, Workspace &w, const gnss::Launch &L, hipStream_t s, bool allow_profile);
 
+// Long requests run alone in passes over their blocks: each pass a multiple
+// of kSumGroup blocks, so that the FP32 kernels group their block sums at
+// the same blocks as in one pass (the results are the same bit for bit);
+// each pass after the first adds its sums to the grid's and only the last
+// detects.  lay_out_pass lays out the pass of blocks b0 .. b0 + nb - 1 of
+// request r (plan p); run_passes runs r in passes of nb blocks on stream s
+// (scratch: the first pass, the longest, lays out the allocation-free
+// scratch and the others run in that layout); B gets the last pass's layout.
+void lay_out_pass(gnss_ctx *c, const gnss::Plan &p, const gnss_request &r, int b0, int nb, BatchHost &B);
+int run_passes(gnss_ctx *c, Workspace &w, const gnss::Plan &p, const gnss_request &r, int nb, hipStream_t s,
+               bool prof, bool scratch, BatchHost &B);
+
+// Whether request r (plan p, one-pass layout B) runs in passes: option
+// block_window below its blocks, or a one-pass layout that does not fit.
+template <typename Fits>
+bool needs_passes(gnss_ctx *c, const gnss::Plan &p, const BatchHost &B, Fits fits)
+{
+    if (p.Nnc <= gnss::kSumGroup) return false;
+    if (c->block_window > 0) return c->block_window < p.Nnc;
+    return B.cshift_bad >= 0 || !fits(B);
+}
+
+// Blocks per pass: option block_window, else the largest multiple of
+// kSumGroup whose pass layout fits (fits(B)); all of them (one pass, which
+// then reports the shortage) when not even kSumGroup blocks fit.
+template <typename Fits>
+int pass_blocks(gnss_ctx *c, const gnss::Plan &p, const gnss_request &r, Fits fits)
+{
+    if (c->block_window > 0) return std::min(c->block_window, p.Nnc);
+    auto ok = [&](int nb) {
+        BatchHost B;
+        lay_out_pass(c, p, r, 0, nb, B);
+        return B.cshift_bad < 0 && fits(B);
+    };
+    if (p.Nnc <= gnss::kSumGroup || !ok(gnss::kSumGroup)) return p.Nnc;
+    int lo = 1, hi = (p.Nnc - 1) / gnss::kSumGroup;  // groups per pass; ok(lo groups)
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (ok(mid * gnss::kSumGroup))
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo * gnss::kSumGroup;
+}
+
 // autotuner lookup: the PRN tile for a batch of these plans
 gnss::CorrShape corr_shape_for(gnss_ctx *c, const gnss::Plan *plans, int n);
 int persistent_for(gnss_ctx *c, const BatchHost &B);

@@ -9,8 +9,9 @@
 // workspace: while one batch runs, the requests that arrived meanwhile are
 // admitted into the other slot as far as the slot's share of the HBM budget
 // allows, uploaded and launched, so consecutive batches overlap on the
-// device.  A request larger than a slot's share fails with GNSS_ENOMEM; the
-// others wait in arrival order.
+// device.  A request larger than a slot's share runs alone in passes over
+// its blocks, each within the share, when it has more than 256 blocks, and
+// otherwise fails with GNSS_ENOMEM; the others wait in arrival order.
 #include "gnss_runtime.hpp"
 
 #include <math.h>
@@ -41,7 +42,8 @@ struct Ticket {
     void *h_samples = nullptr;      // pinned copy of the record
     size_t h_samples_cap = 0;
     size_t sample_bytes = 0;
-    size_t need_bytes = 0;          // device bytes of this request alone
+    size_t need_bytes = 0;          // device bytes of this request alone (one pass of it)
+    int pass_blocks = 0;            // > 0: runs alone in passes of this many blocks
     int state = kQueued;
     int status = GNSS_OK;
     std::string error;
@@ -212,6 +214,8 @@ static int run_slot_once(gnss_ctx *c, Slot &sl)
         if (t->req.out_grid) gb += (size_t)t->plan.grid_elems() * sizeof(float);
     }
     int rc;
+    // a request in passes runs alone, its arena laid out for the first pass
+    const int nb = n == 1 ? sl.members[0]->pass_blocks : 0;
     {
         // the batch's layout in the slot's arena: workspace buffers, then the
         // samples, peaks and grids of its requests
@@ -221,6 +225,7 @@ static int run_slot_once(gnss_ctx *c, Slot &sl)
             rq[i] = sl.members[i]->req;
             pl[i] = sl.members[i]->plan;
         }
+        if (nb) pl[0].Nnc = nb;
         BatchHost P;
         build_batch(pl.data(), rq.data(), n, gnss::CorrShape{2, gnss::corr_waves(c->precision, 2)}, c->threshold, c->precision, c->doppler_fd, c->code_doppler, P);
         const size_t sizes[10] = {P.F_bytes, P.G_bytes, P.Q_bytes, P.K_bytes, P.part_bytes, P.grid_bytes,
@@ -258,9 +263,13 @@ static int run_slot_once(gnss_ctx *c, Slot &sl)
         plans[i] = t->plan;
     }
     BatchHost B;
-    build_batch(plans.data(), reqs.data(), n, corr_shape_for(c, plans.data(), n), c->threshold, c->precision, c->doppler_fd, c->code_doppler, B);
-    gnss::Launch L;
-    if ((rc = stage_batch(c, sl.ws, B, sl.stream, L)) || (rc = launch(c, sl.ws, L, sl.stream, false))) return rc;
+    if (nb) {
+        if ((rc = run_passes(c, sl.ws, plans[0], reqs[0], nb, sl.stream, false, false, B))) return rc;
+    } else {
+        build_batch(plans.data(), reqs.data(), n, corr_shape_for(c, plans.data(), n), c->threshold, c->precision, c->doppler_fd, c->code_doppler, B);
+        gnss::Launch L;
+        if ((rc = stage_batch(c, sl.ws, B, sl.stream, L)) || (rc = launch(c, sl.ws, L, sl.stream, false))) return rc;
+    }
     if ((rc = copy_async(c, sl.h_peaks, sl.peaks.p, pb, hipMemcpyDeviceToHost, sl.stream))) return rc;
     for (int i = 0; i < n; ++i) {
         Ticket *t = sl.members[i];
@@ -323,12 +332,14 @@ static void server_loop(gnss_ctx *c)
                 size_t used = 0;
                 while (!S.queue.empty() && (int)take.size() < c->max_slots) {
                     Ticket *t = S.queue.front();
-                    if (!take.empty() && used + t->need_bytes > cap) break;
+                    // a request in passes over its blocks runs alone
+                    if (!take.empty() && (t->pass_blocks || used + t->need_bytes > cap)) break;
                     S.queue.pop_front();
                     used += t->need_bytes;
                     t->state = kRunning;
                     t->t_start = Clock::now();
                     take.push_back(t);
+                    if (t->pass_blocks) break;
                 }
                 for (Ticket *t : take) t->batch_size = (int)take.size();
             }
@@ -504,11 +515,21 @@ int gnss_submit(gnss_ctx *ctx, const gnss_request *req, uint64_t *ticket)
     BatchHost B;
     gnss_request r1 = *req;
     build_batch(&p, &r1, 1, corr_shape_for(ctx, &p, 1), ctx->threshold, ctx->precision, ctx->doppler_fd, ctx->code_doppler, B);
-    t->need_bytes = batch_device_bytes(B) + t->sample_bytes + (size_t)p.n_prn * sizeof(gnss_peak) +
-                    (req->out_grid ? (size_t)p.grid_elems() * sizeof(float) : 0);
-    if (t->need_bytes > admit_budget(ctx))
-        return set_err(GNSS_ENOMEM, "request needs %zu device bytes, more than a batch slot's %zu", t->need_bytes,
-                       admit_budget(ctx));
+    const size_t fixed = t->sample_bytes + (size_t)p.n_prn * sizeof(gnss_peak) +
+                         (req->out_grid ? (size_t)p.grid_elems() * sizeof(float) : 0);
+    t->need_bytes = batch_device_bytes(B) + fixed;
+    if (t->need_bytes > admit_budget(ctx)) {
+        // a long request runs alone in passes over its blocks, each within a slot's share
+        auto fits = [&](const BatchHost &Bx) { return batch_device_bytes(Bx) + fixed <= admit_budget(ctx); };
+        const int nb = p.Nnc > gnss::kSumGroup ? pass_blocks(ctx, p, r1, fits) : p.Nnc;
+        BatchHost Bp;
+        if (nb < p.Nnc) lay_out_pass(ctx, p, r1, 0, nb, Bp);
+        if (nb >= p.Nnc || !fits(Bp))
+            return set_err(GNSS_ENOMEM, "request needs %zu device bytes, more than a batch slot's %zu, even in "
+                           "passes of %d blocks", t->need_bytes, admit_budget(ctx), gnss::kSumGroup);
+        t->pass_blocks = nb;
+        t->need_bytes = batch_device_bytes(Bp) + fixed;
+    }
     Server &S = *ctx->server;
     t->h_samples = S.pinned.take(std::max<size_t>(t->sample_bytes, 1), &t->h_samples_cap);
     if (!t->h_samples) return set_err(GNSS_ENOMEM, "pinned allocation of %zu bytes failed", t->sample_bytes);

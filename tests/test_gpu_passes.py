@@ -202,3 +202,44 @@ def test_block_window_option_is_checked(ctx):
         assert ei.value.code == G.GNSS_EINVAL
     for good in (0, GROUP, 4 * GROUP, 0):
         ctx.set("block_window", good)
+
+
+def _host_request(snap, srch):
+    nd = O.n_doppler(srch.lo, srch.hi, srch.step)
+    grid = np.full((len(srch.prns), nd, snap.fs_hz // 1000), -1.0, np.float32)
+    pk = np.zeros(len(srch.prns), G.PEAK_DTYPE)
+    x = np.ascontiguousarray(snap.samples)
+    req = G.make_request(x.ctypes.data, snap.fmt, snap.n, snap.fs_hz, snap.f_if_hz, srch.prns, srch.lo,
+                         srch.hi, srch.step, srch.T_coh, srch.N_noncoh, grid.ctypes.data, pk.ctypes.data)
+    return req, x, grid, pk
+
+
+@pytest.mark.timeout(300)
+def test_served_long_request_runs_in_passes():
+    """A submitted request whose one pass exceeds a batch slot's share of
+    the budget (a 160 MiB budget: shares of about 75 MiB; the request needs
+    about 150 MB in one pass) runs alone in passes, between small requests
+    served in batches: every result equals its one-pass search bit for bit."""
+    snap, srch, _ = _case("1M023_serve_2000", O.CPLX_I8, 1023000, 0.0, 1, 2000, [3, 11, 19], [(11, 500.0)],
+                          -500.0, 500.0, 500.0, cn0=38.0)
+    smalls = [_case("1M023_small_%d" % i, O.CPLX_I8, 1023000, 0.0, 1, 4, [7, 9], [(9, 0.0)],
+                    -500.0, 500.0, 500.0, cn0=48.0) for i in range(4)]
+    with G.Context(0) as c:
+        ref = _search(c, snap, srch)
+        ref_small = [_search(c, s, q) for s, q, _ in smalls]
+    with G.Context(0, hbm_budget_bytes=160 << 20) as sc:
+        subs = []
+        for k, (s, q, _) in enumerate(smalls):
+            if k == 2:
+                big = _host_request(snap, srch)
+                subs.append(("long", sc.submit(big[0]), big))
+            h = _host_request(s, q)
+            subs.append((k, sc.submit(h[0]), h))
+        for k, t, h in subs:
+            info = sc.wait(t, 120.0)
+            want = ref if k == "long" else ref_small[k]
+            assert np.array_equal(h[2], want[0]), k
+            assert h[3].tobytes() == want[1].tobytes(), k
+            if k == "long":
+                assert info.batch_size == 1
+    log("served long request in passes equals its one-pass search")
