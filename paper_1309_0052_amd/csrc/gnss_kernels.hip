@@ -435,8 +435,7 @@ constexpr int kBoxBuf = (kBoxChunk + kMaxSpc) + (kBoxChunk + kMaxSpc) / 8 + 8;
 
 // The wipe, fold, boxcar and polyphase split of one (Doppler k, block b) item
 // of request d by NT threads: dst[s * kPolyLen + m] = F[spc m + s] for m <
-// 1023 and 0 at m = 1023 (dst in global memory for the staged path, in LDS
-// for the fused exact-length path; the same integer arithmetic either way).
+// 1023 and 0 at m = 1023 (dst: the item's polyphase vectors in F).
 template <int NT, typename DstPtr>
 __device__ __forceinline__ void box_item(const ReqDesc &d, int k, int b, const uint32_t *s_lut, int2 *s_f,
                                          DstPtr dst)
