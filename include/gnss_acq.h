@@ -244,8 +244,11 @@ int gnss_acquire_device_noalloc(gnss_ctx *ctx, const gnss_request *req, void *st
  * sample rates, PRN lists and Doppler windows searched by one pass of the
  * stage kernels over a device table of the requests (the batch mode of the
  * paper's Listing 3(b), applied to whole requests).  Each request as for gnss_acquire_device.
- * Results are identical to running each request alone.  Errors: as
- * gnss_acquire_device; a bad request reports its index. */
+ * Results are identical to running each request alone.  A batch whose
+ * workspace does not fit (see gnss_acquire_device) runs its requests that
+ * need passes over their blocks alone, in passes, and the others as one
+ * batch, all on `stream`.  Errors: as gnss_acquire_device; a bad request
+ * reports its index. */
 int gnss_acquire_batch_device(gnss_ctx *ctx, const gnss_request *reqs, int32_t n_req, void *stream);
 
 /* A batch captured once into a HIP graph (metadata copy and every stage

@@ -1038,12 +1038,37 @@ int gnss_acquire_batch_device(gnss_ctx *ctx, const gnss_request *reqs, int32_t n
     hipStream_t s = (hipStream_t)stream;
     BatchHost B;
     build_batch(plans.data(), reqs, n_req, corr_shape_for(ctx, plans.data(), n_req), ctx->threshold, ctx->precision, ctx->doppler_fd, ctx->code_doppler, B);
+    auto fits = [&](const BatchHost &Bx) { return fits_hbm(ctx, ctx->ws, Bx, 0); };
     if (n_req == 1) {
-        auto fits = [&](const BatchHost &Bx) { return fits_hbm(ctx, ctx->ws, Bx, 0); };
         if (needs_passes(ctx, plans[0], B, fits)) {
             const int nb = pass_blocks(ctx, plans[0], reqs[0], fits);
             if (nb < plans[0].Nnc) return run_passes(ctx, ctx->ws, plans[0], reqs[0], nb, s, true, false, B);
         }
+    } else if (!fits(B)) {
+        // a batch that does not fit: the requests that need passes run alone
+        // in passes, first, and the others as one batch, all on the stream
+        std::vector<gnss::Plan> rest_p;
+        std::vector<gnss_request> rest_r;
+        for (int i = 0; i < n_req; ++i) {
+            BatchHost Bi;
+            build_batch(&plans[i], &reqs[i], 1, corr_shape_for(ctx, &plans[i], 1), ctx->threshold, ctx->precision,
+                        ctx->doppler_fd, ctx->code_doppler, Bi);
+            int nb = plans[i].Nnc;
+            if (needs_passes(ctx, plans[i], Bi, fits)) nb = pass_blocks(ctx, plans[i], reqs[i], fits);
+            if (nb < plans[i].Nnc) {
+                if ((rc = run_passes(ctx, ctx->ws, plans[i], reqs[i], nb, s, true, false, Bi))) {
+                    std::string m = t_err;
+                    return set_err(rc, "request %d: %s", i, m.c_str());
+                }
+            } else {
+                rest_p.push_back(plans[i]);
+                rest_r.push_back(reqs[i]);
+            }
+        }
+        if (rest_p.empty()) return GNSS_OK;
+        if ((int)rest_p.size() < n_req)
+            build_batch(rest_p.data(), rest_r.data(), (int)rest_p.size(), corr_shape_for(ctx, rest_p.data(), (int)rest_p.size()),
+                        ctx->threshold, ctx->precision, ctx->doppler_fd, ctx->code_doppler, B);
     }
     gnss::Launch L;
     if ((rc = stage_batch(ctx, ctx->ws, B, s, L))) return rc;

@@ -243,3 +243,37 @@ def test_served_long_request_runs_in_passes():
             if k == "long":
                 assert info.batch_size == 1
     log("served long request in passes equals its one-pass search")
+
+
+def _dev_request(snap, srch):
+    nd = O.n_doppler(srch.lo, srch.hi, srch.step)
+    N = snap.fs_hz // 1000
+    x = torch.from_numpy(np.ascontiguousarray(snap.samples)).cuda()
+    grid = torch.full((len(srch.prns) * nd * N,), -1.0, dtype=torch.float32, device="cuda")
+    pk = torch.zeros(len(srch.prns) * 48, dtype=torch.uint8, device="cuda")
+    req = G.make_request(x.data_ptr(), snap.fmt, snap.n, snap.fs_hz, snap.f_if_hz, srch.prns, srch.lo, srch.hi,
+                         srch.step, srch.T_coh, srch.N_noncoh, grid.data_ptr(), pk.data_ptr())
+    return req, x, grid.view(len(srch.prns), nd, N), pk
+
+
+@pytest.mark.timeout(300)
+def test_batch_that_does_not_fit_runs_its_long_request_in_passes():
+    """A batch under a 64 MiB budget holding a 2000-block request (about
+    150 MB in one pass) between three small ones: the long one runs alone in
+    passes, the others as one batch; every result equals its search alone on
+    an unlimited context bit for bit."""
+    long_ = _case("1M023_budget_2000", O.CPLX_I8, 1023000, 0.0, 1, 2000, [3, 11, 19], [(11, -500.0)],
+                  -500.0, 500.0, 500.0, cn0=38.0)
+    smalls = [_case("1M023_bsmall_%d" % i, O.CPLX_I8, 1023000, 0.0, 1, 4, [7, 9], [(9, 0.0)],
+                    -500.0, 500.0, 500.0, cn0=48.0) for i in range(3)]
+    items = [smalls[0], long_, smalls[1], smalls[2]]
+    with G.Context(0) as c:
+        refs = [_search(c, s, q) for s, q, _ in items]
+    with G.Context(0, hbm_budget_bytes=64 << 20) as c:
+        devs = [_dev_request(s, q) for s, q, _ in items]
+        c.acquire_batch_device([d[0] for d in devs], torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        for i, d in enumerate(devs):
+            assert np.array_equal(d[2].cpu().numpy(), refs[i][0]), i
+            assert d[3].cpu().numpy().tobytes() == refs[i][1].tobytes(), i
+    log("batch with a long request under a 64 MiB budget equals the requests alone")
