@@ -3155,18 +3155,31 @@ hipError_t launch_batch(const Launch &L, const Tables &T, int2 *d_F, void *d_G, 
 // ===========================================================================
 constexpr long long kCodeFix = 1023LL << 32;  // one code period, chips * 2^32
 
-// 64-bit sum over the workgroup; the result is valid in thread 0.
-__device__ __forceinline__ long long block_sum64(long long v, long long *s_red)
+// The workgroup's sums of a pass's kTrackCG x 6 per-thread totals, with one
+// pair of barriers for all of them: each wave sums its lanes (shuffles) and
+// lane i keeps value i's wave sum, the waves' sums meet in LDS, and thread
+// i < kTrackCG * 6 adds them.  Returns value i's total in thread i (0 in the
+// others); the sums are exact (int64), so their order does not matter.
+constexpr int kTrackVals = kTrackCG * 6;
+__device__ __forceinline__ long long block_sums64(const long long (&tot)[kTrackCG][6], long long *s_red)
 {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    long long mine = 0;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    const int w = threadIdx.x >> 6;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) s_red[w] = v;
+    for (int cc = 0; cc < kTrackCG; ++cc)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            long long v = tot[cc][k];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if (l == cc * 6 + k) mine = v;
+        }
+    __syncthreads();  // the previous pass's reads of s_red are done
+    if (l < kTrackVals) s_red[w * kTrackVals + l] = mine;
     __syncthreads();
     long long t = 0;
-    if (threadIdx.x == 0)
-        for (int i = 0; i < kTrackThreads / 64; ++i) t += s_red[i];
+    if (threadIdx.x < kTrackVals)
+        for (int i = 0; i < kTrackThreads / 64; ++i) t += s_red[i * kTrackVals + threadIdx.x];
     return t;
 }
 
@@ -3245,7 +3258,7 @@ __global__ __launch_bounds__(kTrackThreads) void k_track(const TrackDesc *__rest
 {
     __shared__ uint32_t s_lut[1024];
     __shared__ int8_t s_sign[kTrackCG][kSignRow];
-    __shared__ long long s_red[kTrackThreads / 64];
+    __shared__ long long s_red[kTrackThreads / 64 * kTrackVals];
     for (int i = threadIdx.x; i < 1024; i += kTrackThreads) s_lut[i] = lut[i];
     for (long long it = blockIdx.x; it < total; it += gridDim.x) {
         const int r = find_req(pre, n_req, it);
@@ -3263,10 +3276,8 @@ __global__ __launch_bounds__(kTrackThreads) void k_track(const TrackDesc *__rest
             __syncthreads();
             uint32_t ph[kTrackCG], dph[kTrackCG];
             unsigned long long q[kTrackCG], dq[kTrackCG], dl[kTrackCG], ndl[kTrackCG];
-            bool on[kTrackCG];
 #pragma unroll
             for (int cc = 0; cc < kTrackCG; ++cc) {
-                on[cc] = c0 + cc < d.n_ch;
                 const TrackCh c = CH[d.ch_off + min(c0 + cc, d.n_ch - 1)];
                 ph[cc] = c.phi0 + (uint32_t)((unsigned long long)n_first * c.D);
                 dph[cc] = (uint32_t)kTrackThreads * c.D;
@@ -3288,14 +3299,10 @@ __global__ __launch_bounds__(kTrackThreads) void k_track(const TrackDesc *__rest
             else
                 track_pass<GNSS_REAL_2BIT_PACKED>(d.samples, n_first, n_mine, s_lut, s_sign, ph, dph, q, dq, dl, ndl,
                                                   tot);
-#pragma unroll
-            for (int cc = 0; cc < kTrackCG; ++cc) {
-#pragma unroll
-                for (int k = 0; k < 6; ++k) {
-                    const long long v = block_sum64(tot[cc][k], s_red);
-                    if (threadIdx.x == 0 && on[cc])
-                        gmem(d.out)[((long long)(c0 + cc) * d.n_epochs + e) * 6 + k] = v;
-                }
+            const long long v = block_sums64(tot, s_red);
+            if (threadIdx.x < kTrackVals) {
+                const int cc = threadIdx.x / 6, k = threadIdx.x - cc * 6;
+                if (c0 + cc < d.n_ch) gmem(d.out)[((long long)(c0 + cc) * d.n_epochs + e) * 6 + k] = v;
             }
         }
     }
