@@ -267,7 +267,7 @@ struct TrackDesc {
 };
 constexpr int kFdCols = 8;  // columns of the long DFT's second pass per workgroup
 constexpr int kTrackThreads = 256;
-constexpr int kTrackCG = 2;  // channels per pass over an epoch
+constexpr int kTrackCG = 4;  // channels per pass over an epoch
 hipError_t launch_track(const TrackDesc *d_reqs, const long long *d_pre, int n_req, long long total,
                         const TrackCh *d_ch, const uint8_t *d_codes, const uint32_t *d_lut, hipStream_t s);
 
