@@ -201,9 +201,10 @@ int gnss_workspace_bytes(const gnss_request *req, size_t *bytes);
  * on one context must not overlap on different streams.  May allocate
  * workspace on first use or growth.
  * Long requests (the non-coherent sum of Sec. 3 over many blocks): when the
- * one-pass workspace does not fit (the HBM budget, or without one three
- * quarters of the device's memory, beside what the context holds
- * elsewhere), or under option "block_window", the request runs in passes of
+ * one-pass workspace does not fit (within the HBM budget beside what the
+ * context holds elsewhere, or without one within nine tenths of the
+ * device's free memory plus the context's workspace), or under option
+ * "block_window", the request runs in passes of
  * a multiple of 256 blocks, enqueued one after another on the stream; each
  * pass wipes, folds and transforms only its own blocks at their places in
  * the record, adds its sums to the grid (out_grid, or an internal one) and

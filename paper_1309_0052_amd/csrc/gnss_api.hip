@@ -816,23 +816,32 @@ void lay_out_pass(gnss_ctx *c, const gnss::Plan &p, const gnss_request &r, int b
     build_batch(&q, &r, 1, corr_shape_for(c, &q, 1), c->threshold, c->precision, c->doppler_fd, c->code_doppler, B);
 }
 
-// Whether a layout fits the context's HBM budget (without one, three
-// quarters of the device's memory) beside the device memory the context
-// holds outside workspace w; extra: what the call needs besides the batch.
+// Whether a layout fits beside what the context holds outside workspace w:
+// within the context's HBM budget, or without one within nine tenths of
+// what the device has free plus what w holds (w's buffers are replaced when
+// they grow); extra: what the call needs besides the batch.
 static bool fits_hbm(gnss_ctx *c, const Workspace &w, const BatchHost &B, size_t extra)
 {
     const DevBuf *bufs[] = {&w.F, &w.G, &w.Q, &w.K, &w.part, &w.grid, &w.meta, &w.samples, &w.peaks};
     size_t held = 0;
     for (const DevBuf *b : bufs)
         if (b->owned) held += b->cap;
-    size_t dev;
-    {
-        std::lock_guard<std::mutex> lk(c->mem_mu);
-        dev = c->dev_bytes;
+    const size_t need = batch_device_bytes(B) + extra;
+    if (c->budget) {
+        size_t dev;
+        {
+            std::lock_guard<std::mutex> lk(c->mem_mu);
+            dev = c->dev_bytes;
+        }
+        const size_t other = dev > held ? dev - held : 0;
+        return other + need <= c->budget;
     }
-    const size_t other = dev > held ? dev - held : 0;
-    const size_t limit = c->budget ? c->budget : c->dev_total / 4 * 3;
-    return other + batch_device_bytes(B) + extra <= limit;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        (void)hipGetLastError();
+        free_b = c->dev_total / 2;
+    }
+    return need <= (free_b + held) / 10 * 9;
 }
 
 int run_passes(gnss_ctx *c, Workspace &w, const gnss::Plan &p, const gnss_request &r, int nb,

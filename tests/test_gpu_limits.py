@@ -1,5 +1,6 @@
 """GPU parity at the request limits of the boundary: the largest Doppler
-window (65536 bins) and the largest non-coherent sum (100000 blocks).
+window (65536 bins), the largest non-coherent sum (100000 blocks), and a
+request whose one-pass workspace is larger than the device.
 
 At 65536 bins the whole FP32 grid is compared with the oracle's FP64 FFT
 route, with detections and refinements (the usual bar, tests/parity.py).
@@ -105,3 +106,47 @@ def test_largest_noncoherent_sum(ctx, where):
     # one block of the satellite (about 6.5e9 at this amplitude) against the
     # 100000 noise blocks summed at every cell (about 4.1e8): some 16 times the mean
     assert got[0] > 10 * means[0]
+
+
+@pytest.mark.timeout(600)
+def test_request_larger_than_the_device_runs_in_passes(ctx):
+    """7000 blocks of 1 ms at 16.368 MHz over the weak-signal Doppler grid
+    (121 bins, 8 PRNs): about 333 GB of one-pass workspace, more than the
+    device holds (288 GiB), so the search runs in passes without any option or
+    budget; the grid equals forced 256-block passes bit for bit, the
+    satellite planted in the first block only is detected at its cell, and
+    sampled cells match the direct oracle within 1e-5 (mixed)."""
+    fs, N_noncoh = 16368000, 7000
+    N = fs // 1000
+    n = N * N_noncoh
+    rng = np.random.default_rng(23)
+    samples = rng.integers(-2, 3, size=2 * n, dtype=np.int8)
+    pl = [synth.Planted(prn=19, code_phase=5000, doppler_hz=0.0, cn0_dbhz=71.0)]
+    sig = synth.make_snapshot(3, O.CPLX_I8, fs, 0.0, 1.0, pl, O.ca_code, noise=False)
+    seg = samples[:2 * N].astype(np.int16) + sig.samples[:2 * N].astype(np.int16)
+    samples[:2 * N] = np.clip(seg, -127, 127).astype(np.int8)
+    prns, lo, hi, step = [19, 1, 2, 3, 4, 5, 6, 7], -7500.0, 7500.0, 125.0
+    nd = O.n_doppler(lo, hi, step)
+    req = G.make_request(1, O.CPLX_I8, n, fs, 0.0, prns, lo, hi, step, 1, N_noncoh, None, 1)
+    need = G.gnss_workspace_bytes(req)
+    free = torch.cuda.mem_get_info()[0]
+    log("request needing %.0f GB in one pass, %.0f GB free on the device" % (need / 1e9, free / 1e9))
+    assert need > free
+    grid, pk = _search(ctx, samples, O.CPLX_I8, n, fs, prns, lo, hi, step, 1, N_noncoh)
+    try:
+        ctx.set("block_window", 256)
+        grid2, pk2 = _search(ctx, samples, O.CPLX_I8, n, fs, prns, lo, hi, step, 1, N_noncoh)
+    finally:
+        ctx.set("block_window", 0)
+    assert np.array_equal(grid, grid2) and pk.tobytes() == pk2.tobytes()
+    k0 = nd // 2  # the 0 Hz bin
+    assert pk[0]["detected"] and pk[0]["code_phase"] == 5000 and pk[0]["doppler_bin"] == k0, pk[0]
+    cells = [(0, k0, 5000)]
+    cells += list(zip(rng.integers(0, len(prns), 5), rng.integers(0, nd, 5), rng.integers(0, N, 5)))
+    cells = np.array(cells, np.int64)
+    vals = O.cells_direct(samples, O.CPLX_I8, fs, 0.0, prns, lo, step, nd, 1, N_noncoh, cells)
+    got = grid[cells[:, 0], cells[:, 1], cells[:, 2]].astype(np.float64)
+    means = grid.astype(np.float64).mean(axis=(1, 2))[cells[:, 0]]
+    err = np.abs(got - vals) / (vals + means)
+    log("  peak %.4e (oracle %.4e), max mixed error %.3e" % (got[0], vals[0], err.max()))
+    assert np.all(err <= 1e-5), err
