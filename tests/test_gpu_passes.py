@@ -277,3 +277,44 @@ def test_batch_that_does_not_fit_runs_its_long_request_in_passes():
             assert np.array_equal(d[2].cpu().numpy(), refs[i][0]), i
             assert d[3].cpu().numpy().tobytes() == refs[i][1].tobytes(), i
     log("batch with a long request under a 64 MiB budget equals the requests alone")
+
+
+def test_a_failed_pass_fails_the_call_and_leaves_the_context_usable(ctx):
+    """The second of three passes fails on the host (failure injection): the
+    call reports GNSS_EDEVICE, and the next search on the context, again in
+    passes, equals the one-pass search bit for bit."""
+    snap, srch, _ = _case(*CASES[0])
+    ref = _search(ctx, snap, srch)
+    try:
+        ctx.set("block_window", GROUP)
+        ctx.set("fault_launch", 2)
+        with pytest.raises(G.GnssError) as ei:
+            _search(ctx, snap, srch)
+        assert ei.value.code == G.GNSS_EDEVICE
+        torch.cuda.synchronize()
+        got = _search(ctx, snap, srch)
+    finally:
+        ctx.set("fault_launch", 0)
+        ctx.set("block_window", 0)
+    assert np.array_equal(got[0], ref[0]) and got[1].tobytes() == ref[1].tobytes()
+
+
+@pytest.mark.timeout(300)
+def test_a_failed_pass_fails_only_its_served_ticket():
+    """Served: the long request's second pass fails (failure injection); its
+    ticket reports the error, and the next ticket, the same request, equals
+    its one-pass search."""
+    snap, srch, _ = _case("1M023_serve_2000", O.CPLX_I8, 1023000, 0.0, 1, 2000, [3, 11, 19], [(11, 500.0)],
+                          -500.0, 500.0, 500.0, cn0=38.0)
+    with G.Context(0) as c:
+        ref = _search(c, snap, srch)
+    with G.Context(0, hbm_budget_bytes=160 << 20) as sc:
+        sc.set("fault_launch", 2)
+        bad = _host_request(snap, srch)
+        with pytest.raises(G.GnssError) as ei:
+            sc.wait(sc.submit(bad[0]), 120.0)
+        assert ei.value.code == G.GNSS_EDEVICE and "injected" in str(ei.value)
+        good = _host_request(snap, srch)
+        info = sc.wait(sc.submit(good[0]), 120.0)
+        assert info.status == 0
+        assert np.array_equal(good[2], ref[0]) and good[3].tobytes() == ref[1].tobytes()
