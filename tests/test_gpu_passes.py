@@ -108,10 +108,13 @@ def test_passes_equal_one_pass(ctx, case):
     log("  passes equal one pass; max mixed error %.3e" % worst)
 
 
-def test_passes_with_code_doppler(ctx):
+@pytest.mark.parametrize("rate", ["chip", "general"])
+def test_passes_with_code_doppler(ctx, rate):
     """Code-Doppler compensation over passes: each pass's shift table is
-    built for its blocks' places in the record."""
-    snap, srch, _ = _case("1M023_cd_600", O.CPLX_I8, 1023000, 0.0, 1, 600, [5, 13], [(13, 4000.0)],
+    built for its blocks' places in the record (chip rate: the polyphase
+    path; 2 MHz: the zero-padded general-rate path)."""
+    fs = 1023000 if rate == "chip" else 2000000
+    snap, srch, _ = _case("cd_600_%s" % rate, O.CPLX_I8, fs, 0.0, 1, 600, [5, 13], [(13, 4000.0)],
                           3000.0, 5000.0, 1000.0)
     try:
         ctx.set("code_doppler", 1)

@@ -182,3 +182,23 @@ def test_noalloc_runs_a_long_request_in_passes():
         _same_peaks(pk, ref_small[1])
         torch.cuda.synchronize()
         assert torch.cuda.mem_get_info()[0] == free0
+
+
+def test_noalloc_runs_a_long_general_rate_request_in_passes():
+    """A 2 MHz request (4096-point zero-padded transforms, whose block and
+    code spectra share the scratch) of 2000 blocks, which the scratch holds
+    only in passes: equal to gnss_acquire_device bit for bit."""
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    pl = [synth.Planted(prn=17, code_phase=1234, doppler_hz=500.0, cn0_dbhz=38.0)]
+    snap = synth.make_snapshot(62, synth.CPLX_I8, 2000000, 0.0, 2000.25, pl, O.ca_code)
+    srch = synth.Search([4, 17], 0.0, 1000.0, 500.0, 1, 2000)
+    with G.Context(0) as ctx:
+        d = Dev(snap, srch)
+        ctx.acquire_device(d.req)
+        ref = d.result()
+        d.clear()
+        ctx.acquire_device_noalloc(d.req)
+        g, pk = d.result()
+        assert np.array_equal(g, ref[0])
+        _same_peaks(pk, ref[1])
+        assert pk[1]["detected"] and pk[1]["code_phase"] == 1234
