@@ -216,3 +216,22 @@ def test_chip_exclusion_is_one_chip():
     G[0, 105] = 2.0
     r = O.peak_one(G, 1, O.chip_exclusion(5000000), 2.5, 0.0, 1.0)
     assert r.second == 2.0 and r.ratio == 5.0
+
+
+def test_long_integration_generator():
+    """The long-integration input (bench.py --workload long) at a reduced size:
+    record length 4 ms x blocks + 0.5 ms, the weak-signal search grid over the
+    given blocks, eight planted PRNs from 1-32 at 22-30 dB-Hz within the
+    Doppler window, and the same record for the same seed."""
+    fs, blocks = 1023000, 16
+    snap, srch = synth.long_complex_int8(O.ca_code, seed=3, fs=fs, blocks=blocks)
+    assert snap.fmt == O.CPLX_I8 and snap.fs_hz == fs
+    assert snap.n == int(round(fs * (4.0 * blocks + 0.5) / 1000.0))
+    assert srch.prns == list(range(1, 33)) and (srch.lo, srch.hi, srch.step) == (-7500.0, 7500.0, 125.0)
+    assert (srch.T_coh, srch.N_noncoh) == (4, blocks)
+    assert len(snap.planted) == 8 and len({p.prn for p in snap.planted}) == 8
+    for p in snap.planted:
+        assert 1 <= p.prn <= 32 and 22.0 <= p.cn0_dbhz <= 30.0 and abs(p.doppler_hz) <= 7500.0
+        assert 0 <= p.code_phase < fs // 1000
+    again, _ = synth.long_complex_int8(O.ca_code, seed=3, fs=fs, blocks=blocks)
+    assert np.array_equal(again.samples, snap.samples)
