@@ -3155,27 +3155,50 @@ hipError_t launch_batch(const Launch &L, const Tables &T, int2 *d_F, void *d_G, 
 // ===========================================================================
 constexpr long long kCodeFix = 1023LL << 32;  // one code period, chips * 2^32
 
+// One round of the wave reduce-scatter below: value i pairs with value
+// i + H; the lane whose bit O is set keeps the upper one, its partner the
+// lower, and each adds the one the other sends.
+template <int O, int H>
+__device__ __forceinline__ void rs_round(long long (&v)[24], int l)
+{
+    const bool up = (l & O) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const long long send = up ? v[i] : v[i + H];
+        const long long keep = up ? v[i + H] : v[i];
+        v[i] = keep + __shfl_xor(send, O);
+    }
+}
+
 // The workgroup's sums of a pass's kTrackCG x 6 per-thread totals, with one
-// pair of barriers for all of them: each wave sums its lanes (shuffles) and
-// lane i keeps value i's wave sum, the waves' sums meet in LDS, and thread
-// i < kTrackCG * 6 adds them.  Returns value i's total in thread i (0 in the
-// others); the sums are exact (int64), so their order does not matter.
+// pair of barriers for all of them.  Within a wave a reduce-scatter halves
+// the values per lane each round (24, 12, 6, 3, padded to 4, 2, 1) while
+// the lanes paired across bits 5 .. 1 add them, and the last round over bit
+// 0 completes the wave's sum; the lane's bits then name its value.  The
+// waves' sums meet in LDS and thread i < 24 adds them.  Returns value i's
+// total in thread i (0 in the others); the sums are exact (int64), so their
+// order does not matter.
 constexpr int kTrackVals = kTrackCG * 6;
+static_assert(kTrackVals == 24, "the reduce-scatter rounds are laid out for 24 values");
 __device__ __forceinline__ long long block_sums64(const long long (&tot)[kTrackCG][6], long long *s_red)
 {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    long long mine = 0;
+    long long v[24];
 #pragma unroll
     for (int cc = 0; cc < kTrackCG; ++cc)
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            long long v = tot[cc][k];
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-            if (l == cc * 6 + k) mine = v;
-        }
+        for (int k = 0; k < 6; ++k) v[cc * 6 + k] = tot[cc][k];
+    rs_round<32, 12>(v, l);
+    rs_round<16, 6>(v, l);
+    rs_round<8, 3>(v, l);
+    v[3] = 0;
+    rs_round<4, 2>(v, l);
+    rs_round<2, 1>(v, l);
+    const long long sum = v[0] + __shfl_xor(v[0], 1);
+    const int j = ((l & 4) ? 2 : 0) + ((l & 2) ? 1 : 0);  // 3: the padding
+    const int idx = ((l & 32) ? 12 : 0) + ((l & 16) ? 6 : 0) + ((l & 8) ? 3 : 0) + j;
     __syncthreads();  // the previous pass's reads of s_red are done
-    if (l < kTrackVals) s_red[w * kTrackVals + l] = mine;
+    if ((l & 1) == 0 && j < 3) s_red[w * kTrackVals + idx] = sum;
     __syncthreads();
     long long t = 0;
     if (threadIdx.x < kTrackVals)
