@@ -66,6 +66,14 @@ CASES = [
     ("1M024_packed", O.REAL_2BIT_PACKED, 1024000, 256000.0, 2, 2, [5, 30], [(30, -500.0)], -500.0, 0.0, 500.0),
     # a tiny N
     ("100k_cplx", O.CPLX_I8, 100000, 0.0, 4, 3, [1, 2], [(2, 0.0)], -250.0, 250.0, 250.0),
+    # odd lengths: N = 63 (M = 128); N = 64 (a power of two: M = N); a prime N = 3001;
+    # N = 13370 packed (every other block starts inside a byte); N = 16383, the largest
+    # length below the limit that is not a power of two (the 32768-point split)
+    ("63k_cplx", O.CPLX_I8, 63000, 0.0, 2, 3, [1, 2], [(2, 0.0)], -250.0, 250.0, 250.0),
+    ("64k_real", O.REAL_I8, 64000, 16000.0, 2, 3, [5, 6], [(6, 0.0)], -250.0, 250.0, 250.0),
+    ("3M001_cplx", O.CPLX_I8, 3001000, 0.0, 1, 2, [4, 9], [(9, 250.0)], -250.0, 250.0, 250.0),
+    ("13M37_packed", O.REAL_2BIT_PACKED, 13370000, 3342500.0, 1, 2, [12], [(12, 0.0)], -500.0, 500.0, 500.0),
+    ("16M383_cplx", O.CPLX_I8, 16383000, 0.0, 1, 2, [30], [(30, -500.0)], -500.0, 0.0, 500.0),
 ]
 
 
