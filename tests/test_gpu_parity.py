@@ -278,6 +278,11 @@ SEARCH_CASES = [
      1000.0, 500.0, 46.0),
     ("spc8_cplx_dup", O.CPLX_I8, 8184000, 0.0, 1, 2, [37, 7, 7], [7], -500.0, 500.0, 500.0, 48.0),
     ("spc16_cplx", O.CPLX_I8, 16368000, 0.0, 2, 1, [11, 31], [31], -250.0, 0.0, 250.0, 47.0),
+    # one Doppler bin (lo = hi: no interior bin for the Doppler parabola)
+    ("spc2_one_bin", O.CPLX_I8, 2046000, 0.0, 1, 3, [6, 19], [19], 250.0, 250.0, 500.0, 50.0),
+    # the longest PRN list, 64 entries: PRNs 1-37 then 1-27 again
+    ("spc4_64_prns", O.REAL_I8, 4092000, 1023000.0, 1, 1, list(range(1, 38)) + list(range(1, 28)), [5],
+     -500.0, 500.0, 500.0, 50.0),
 ]
 
 
